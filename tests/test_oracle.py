@@ -1,0 +1,247 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks the oracle against a definition, a closed form, an
+invariant or the paper's own constants, so that a dropped term, a wrong
+sign or index or a transposed operand in oracle/ fails at least one of them.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gen import (haar_orthogonal, make_config, make_general, make_problem,
+                 random_amplitudes)
+from oracle import brute, ccsd, solvers
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _args(p):
+    return p.f_oo, p.f_ov, p.f_vv, p.L
+
+
+def _eri(L):
+    return np.einsum("Ppq,Prs->pqrs", L, L)
+
+
+# ---------------------------------------------------------------- T1 -----
+@pytest.mark.parametrize("o,v,naux,seed", [(1, 1, 3, 1), (1, 3, 4, 2), (2, 2, 5, 3),
+                                           (2, 3, 6, 4), (3, 2, 4, 5)])
+def test_residual_equals_determinant_space_definition(o, v, naux, seed):
+    """Equation CC_ampl / CC_energy evaluated literally in the determinant
+    space equals the T1-dressed working equations (f_ov != 0, random t)."""
+    p = make_general(o, v, naux, seed)
+    t1, t2 = random_amplitudes(o, v, seed + 100, scale=0.1)
+    h = ccsd.core_hamiltonian(p.fock(), p.L, o)
+    r1b, r2b, eb = brute.brute_force(h, _eri(p.L), o, t1, t2)
+    r1, r2 = ccsd.residual(*_args(p), t1, t2)
+    e = ccsd.energy(*_args(p), t1, t2)
+    assert np.abs(r2b).max() > 1e-2 and np.abs(r1b).max() > 1e-2
+    assert np.allclose(r1, r1b, atol=1e-12, rtol=0)
+    assert np.allclose(r2, r2b, atol=1e-12, rtol=0)
+    assert abs(e - eb) < 1e-12
+
+
+def test_residual_pair_symmetry():
+    p = make_general(2, 3, 5, 8)
+    t1, t2 = random_amplitudes(2, 3, 9)
+    _, r2 = ccsd.residual(*_args(p), t1, t2)
+    assert np.allclose(r2, np.transpose(r2, (1, 0, 3, 2)), atol=1e-14)
+
+
+# ---------------------------------------------------------------- T3 -----
+def _mp2_closed_form(p):
+    """MP2 amplitudes t = (ia|jb) / (e_i + e_j - e_a - e_b) and energy
+    sum (ia|jb)(2 t_ij^ab - t_ij^ba), by loops, for a diagonal Fock."""
+    o, v = p.nocc, p.nvir
+    eo, ev = np.diag(p.f_oo), np.diag(p.f_vv)
+    t = np.zeros((o, o, v, v))
+    for i in range(o):
+        for j in range(o):
+            for a in range(v):
+                for b in range(v):
+                    g = float(np.dot(p.L[:, i, o + a], p.L[:, j, o + b]))
+                    t[i, j, a, b] = g / (eo[i] + eo[j] - ev[a] - ev[b])
+    e = 0.0
+    for i in range(o):
+        for j in range(o):
+            for a in range(v):
+                for b in range(v):
+                    g = float(np.dot(p.L[:, i, o + a], p.L[:, j, o + b]))
+                    e += g * (2 * t[i, j, a, b] - t[i, j, b, a])
+    return t, e
+
+
+def test_mp2_first_step_closed_form():
+    p = make_problem(3, 7, 12, 21, gauge="canonical")
+    x = solvers.mp2_guess(*_args(p))
+    t1, t2 = solvers.unpack(x, 3, 7)
+    tm, em = _mp2_closed_form(p)
+    assert np.abs(t1).max() < 1e-14
+    assert np.allclose(t2, tm, atol=1e-13, rtol=0)
+    assert abs(ccsd.energy(*_args(p), t1, t2) - em) < 1e-13
+    # the same generalized-MP2 energy in a Haar-rotated gauge
+    q = make_problem(3, 7, 12, 21, gauge="haar")
+    y = solvers.mp2_guess(*_args(q))
+    assert abs(ccsd.energy(*_args(q), *solvers.unpack(y, 3, 7)) - em) < 1e-12
+
+
+# ---------------------------------------------------------------- T4 -----
+def _rotate_problem(p, Uo, Uv):
+    o = p.nocc
+    U = np.zeros((p.L.shape[1],) * 2)
+    U[:o, :o] = Uo
+    U[o:, o:] = Uv
+    L = np.einsum("pr,Prs,qs->Ppq", U, p.L, U)
+    return Uo @ p.f_oo @ Uo.T, Uo @ p.f_ov @ Uv.T, Uv @ p.f_vv @ Uv.T, L
+
+
+def test_gauge_covariance_of_residual_and_energy():
+    p = make_general(3, 4, 6, 31)
+    t1, t2 = random_amplitudes(3, 4, 32)
+    rng = np.random.default_rng(33)
+    Uo, Uv = haar_orthogonal(rng, 3), haar_orthogonal(rng, 4)
+    q = _rotate_problem(p, Uo, Uv)
+    s1 = Uo @ t1 @ Uv.T
+    s2 = np.einsum("ik,jl,ac,bd,klcd->ijab", Uo, Uo, Uv, Uv, t2)
+    r1, r2 = ccsd.residual(*_args(p), t1, t2)
+    q1, q2 = ccsd.residual(*q, s1, s2)
+    assert np.allclose(q1, Uo @ r1 @ Uv.T, atol=1e-13)
+    assert np.allclose(q2, np.einsum("ik,jl,ac,bd,klcd->ijab", Uo, Uo, Uv, Uv, r2), atol=1e-13)
+    assert abs(ccsd.energy(*q, s1, s2) - ccsd.energy(*_args(p), t1, t2)) < 1e-13
+
+
+def test_pnk_history_is_gauge_invariant():
+    """The paper's claim that PNK convergence is gauge invariant, made
+    exact: 2-norm residual histories and step counts agree across gauges."""
+    pc = make_problem(3, 8, 16, 41, gauge="canonical")
+    ph = make_problem(3, 8, 16, 41, gauge="haar")
+    _, _, ic = solvers.solve_pnk(*_args(pc), tol=1e-10)
+    _, _, ih = solvers.solve_pnk(*_args(ph), tol=1e-10)
+    assert ic.converged and ih.converged
+    assert ic.n_jvp == ih.n_jvp and ic.newton_iters == ih.newton_iters
+    hc = np.array([h[1] for h in ic.history])
+    hh = np.array([h[1] for h in ih.history])
+    assert np.allclose(hc, hh, rtol=1e-6, atol=1e-12)
+    assert abs(ic.e_corr - ih.e_corr) < 1e-11
+
+
+# ---------------------------------------------------------------- T5 -----
+def test_jvp_complex_step_matches_central_difference():
+    p = make_general(3, 5, 8, 51)
+    t1, t2 = random_amplitudes(3, 5, 52, scale=0.1)
+    v1, v2 = random_amplitudes(3, 5, 53, scale=1.0)
+    j1, j2 = ccsd.jvp_complex_step(*_args(p), t1, t2, v1, v2)
+    c1, c2 = ccsd.jvp_central(*_args(p), t1, t2, v1, v2)
+    num = np.sqrt(np.sum((j1 - c1) ** 2) + np.sum((j2 - c2) ** 2))
+    den = np.sqrt(np.sum(j1 ** 2) + np.sum(j2 ** 2))
+    assert num / den < 1e-7
+    # linearity in v (complex step is exact for a polynomial residual)
+    k1, k2 = ccsd.jvp_complex_step(*_args(p), t1, t2, 2 * v1, 2 * v2)
+    assert np.allclose(k2, 2 * j2, rtol=1e-13, atol=1e-15)
+
+
+# ---------------------------------------------------------------- T6 -----
+def test_fock_operator_is_jacobian_at_zero_without_two_electron_part():
+    p = make_general(3, 4, 5, 61)
+    x1, x2 = random_amplitudes(3, 4, 62, scale=1.0)
+    z1, z2 = np.zeros((3, 4)), np.zeros((3, 3, 4, 4))
+    j1, j2 = ccsd.jvp_complex_step(p.f_oo, p.f_ov, p.f_vv, np.zeros_like(p.L), z1, z2, x1, x2)
+    a1, a2 = solvers.fock_apply(p.f_oo, p.f_ov, p.f_vv, x1, x2)
+    assert np.allclose(a1, j1, atol=1e-14) and np.allclose(a2, j2, atol=1e-14)
+
+
+def test_fock_operator_inverse_gmres_equals_eigendecomposition():
+    p = make_general(3, 6, 5, 63)
+    b1, b2 = random_amplitudes(3, 6, 64, scale=1.0)
+    e1, e2 = solvers.fock_solve_exact(p.f_oo, p.f_ov, p.f_vv, b1, b2)
+    g1, g2, res = solvers.fock_solve_gmres(p.f_oo, p.f_ov, p.f_vv, b1, b2, rtol=1e-13)
+    assert res.converged
+    assert np.allclose(g1, e1, atol=1e-11) and np.allclose(g2, e2, atol=1e-11)
+    y1, y2 = solvers.fock_apply(p.f_oo, p.f_ov, p.f_vv, e1, e2)
+    assert np.allclose(y1, b1, atol=1e-12) and np.allclose(y2, b2, atol=1e-12)
+
+
+def test_fock_doubles_block_is_symmetric():
+    p = make_general(2, 3, 4, 65)
+    o, v = 2, 3
+    N2 = o * o * v * v
+    A = np.zeros((N2, N2))
+    for k in range(N2):
+        e = np.zeros(N2)
+        e[k] = 1.0
+        _, y2 = solvers.fock_apply(p.f_oo, p.f_ov, p.f_vv, np.zeros((o, v)), e.reshape(o, o, v, v))
+        A[:, k] = y2.ravel()
+    assert np.allclose(A, A.T, atol=1e-15)
+
+
+# ---------------------------------------------------------------- T7 -----
+@pytest.mark.parametrize("seed", [71, 72])
+def test_ccsd_equals_fci_for_one_occupied_orbital(seed):
+    p = make_general(1, 5, 7, seed, sigma=0.15, fov_scale=0.1)
+    _, _, info = solvers.solve_pnk(*_args(p), tol=1e-12)
+    h = ccsd.core_hamiltonian(p.fock(), p.L, 1)
+    efci, _ = brute.fci_ground_energy(h, _eri(p.L), 1)
+    assert info.converged
+    assert abs(info.e_corr - efci) < 1e-11
+
+
+# ---------------------------------------------------------------- T8 -----
+def test_thouless_solution_without_two_electron_part():
+    """With L = 0 the exact state is the determinant of the lowest nocc
+    eigenvectors C of f: t1 = C_v C_o^{-1}, t2 = 0, E = 2 (sum lambda - tr f_oo)."""
+    p = make_general(3, 5, 4, 81, fov_scale=0.2)
+    t1, t2, info = solvers.solve_pnk(p.f_oo, p.f_ov, p.f_vv, np.zeros_like(p.L), tol=1e-12)
+    lam, C = np.linalg.eigh(p.fock())
+    Co, Cv = C[:3, :3], C[3:, :3]
+    assert info.converged
+    assert np.allclose(t1, (Cv @ np.linalg.inv(Co)).T, atol=1e-11)
+    assert np.abs(t2).max() < 1e-11
+    assert abs(info.e_corr - 2 * (lam[:3].sum() - np.trace(p.f_oo))) < 1e-11
+
+
+# ---------------------------------------------------------------- T9 -----
+def test_pnk_and_fp_diis_reach_the_same_root_c1():
+    p = make_config("c1_canonical")
+    a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-11)
+    b1, b2, ib = solvers.solve_fp_diis(*_args(p), tol=1e-11)
+    assert ia.converged and ib.converged
+    assert abs(ia.e_corr - ib.e_corr) < 1e-10
+    assert np.abs(a2 - b2).max() < 1e-10 and np.abs(a1 - b1).max() < 1e-10
+    # PNK needs fewer residual evaluations than FP+DIIS (paper, Fig. 4)
+    assert ia.n_residual + ia.n_jvp < ib.n_residual
+
+
+def test_forward_difference_pnk_converges_like_exact_jvp():
+    p = make_problem(3, 8, 16, 91, gauge="haar")
+    _, _, ie = solvers.solve_pnk(*_args(p), tol=1e-9)
+    _, _, idf = solvers.solve_pnk(*_args(p), tol=1e-9, jvp="fd")
+    assert ie.converged and idf.converged
+    assert abs(ie.e_corr - idf.e_corr) < 1e-9
+
+
+def test_fp_diverges_or_slows_in_rotated_gauge_while_pnk_does_not():
+    """Jacobi denominators taken from the diagonal of a rotated Fock matrix
+    (FP AO) lose accuracy; PNK's count stays the same."""
+    pc = make_problem(3, 8, 16, 93, gauge="canonical")
+    ph = make_problem(3, 8, 16, 93, gauge="haar")
+    _, _, fc = solvers.solve_fp_diis(*_args(pc), tol=1e-9, diis_size=0, max_iter=300)
+    _, _, fh = solvers.solve_fp_diis(*_args(ph), tol=1e-9, diis_size=0, max_iter=300)
+    assert fc.converged
+    assert (not fh.converged) or fh.n_residual > fc.n_residual
+
+
+# ---------------------------------------------------------- constants ----
+def test_paper_constants():
+    with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
+        g = json.load(fh)
+    # safeguard inactive (gamma * eta_prev^alpha < 0.1): eta = gamma (ratio)^alpha
+    eta = solvers.forcing_term(1, 0.1, 1.0, 0.01, 1e-12)
+    assert eta == pytest.approx(g["ew_gamma"] * 0.1 ** g["ew_alpha"], rel=1e-14)
+    assert g["convergence_threshold"] == 1e-8
+    M = np.array(g["conclusion_matrix"])
+    lam = np.linalg.eigvalsh(M)
+    assert abs(M[0, 0] - M[1, 1]) == pytest.approx(g["conclusion_diag_gap"], abs=1e-12)
+    assert abs(lam[1] - lam[0]) == pytest.approx(g["conclusion_spectral_gap_approx"], rel=1e-3)
