@@ -1,0 +1,268 @@
+/*
+ * pnkcc: preconditioned Newton-Krylov solver for closed-shell CCSD
+ * amplitude equations on AMD Instinct MI355X (gfx950).
+ *
+ * Method: arXiv 2608.06669, "A robust and efficient solver for coupled
+ * cluster equations". Section "Theory" defines the amplitude equations
+ * r(t) = <Phi_mu| e^{-T} H e^{T} |Phi_0> = 0 (equation CC_ampl), the energy
+ * (equation CC_energy), the Newton system J delta = -r (equation
+ * LinSyst_4_Newton) and the gauge-invariant Fock preconditioner
+ * [A_F]_{mu,nu} = <Phi_mu|[F, X_nu]|Phi_0> (equation Preconditioner, working
+ * equations in Appendix C). Appendix F gives the PNK algorithm and its
+ * Eisenstat-Walker forcing term. The paper works at the CCD level; this
+ * library solves CCSD (singles through the T1-similarity-transformed
+ * Hamiltonian) with density-fitted integrals.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - All array arguments are DEVICE pointers to float64, row-major, owned by
+ *   the caller (for example torch tensors' data_ptr()). The library keeps no
+ *   pointer after a call returns. Host pointers are marked "host".
+ * - Indices: i,j,k,l occupied (0..nocc-1), a,b,c,d virtual (0..nvir-1),
+ *   n = nocc + nvir, P auxiliary (0..naux-1).
+ * - Amplitudes and residuals: t1[i][a] (nocc*nvir) and t2[i][j][a][b]
+ *   (nocc^2*nvir^2) with t2[i][j][a][b] == t2[j][i][b][a]. Residual
+ *   components are the projections onto a+_{a,alpha} a_{i,alpha}|Phi_0> and
+ *   a+_{a,alpha} a_{i,alpha} a+_{b,beta} a_{j,beta}|Phi_0> of
+ *   e^{-T} H e^{T}|Phi_0>, with T = sum t1 E_ai + 1/2 sum t2 E_ai E_bj.
+ * - `stream` is a hipStream_t (NULL: the default stream). All device work of
+ *   a call is ordered on it. Calls that return host scalars (energies,
+ *   iteration counts, solver info) synchronise the stream before returning;
+ *   cc_jvp and cc_fock_apply do not synchronise.
+ * - Errors: a status code; no exception crosses the boundary.
+ *   cc_last_error() describes the last failure on the handle. On an error no
+ *   output is guaranteed to be written.
+ * - A handle holds device workspace sized for the last problem shape and
+ *   caches the integral tensors derived from the last problem, keyed on its
+ *   pointers, sizes and a 64-bit hash of its contents (recomputed on every
+ *   call, so changing the data in place is safe). A handle must not be used
+ *   by two threads at once; use one handle per thread or stream.
+ */
+#ifndef PNKCC_H
+#define PNKCC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CC_OK = 0,
+  CC_NOT_CONVERGED = 1,  /* solver stopped at its iteration cap; outputs hold the last iterate */
+  CC_ERR_ARG = -1,       /* invalid argument (sizes, null pointers, options) */
+  CC_ERR_OOM = -2,       /* device allocation failed or workspace limit exceeded */
+  CC_ERR_HIP = -3,       /* HIP runtime error */
+  CC_ERR_NAN = -4,       /* non-finite residual norm */
+  CC_ERR_REJECTED = -5,  /* serving: request can never fit the memory budget */
+  CC_ERR_INTERNAL = -6
+} cc_status;
+
+/* Internal compute precision of Jacobian-vector products; inputs and
+ * outputs stay float64. FP32 and BF16 products use float accumulation. */
+typedef enum { CC_FP64 = 0, CC_FP32 = 1, CC_BF16 = 2 } cc_precision;
+
+typedef struct cc_handle cc_handle;
+
+/* Create a handle on HIP device `device`. workspace_limit_bytes caps the
+ * device memory the handle may hold (0: no cap). */
+cc_status cc_create(cc_handle** h, int device, size_t workspace_limit_bytes);
+void cc_destroy(cc_handle* h);
+/* Text of the last error on this handle (valid until the next call). */
+const char* cc_last_error(const cc_handle* h);
+
+/* A closed-shell problem (Section "Theory"; gauge transformation f -> U f U^T
+ * of Appendix A): Fock blocks and density-fitting factors with
+ * (pq|rs) = sum_P L[P][p][q] L[P][r][s]. f must be symmetric
+ * (f_vo = f_ov^T); L[P] must be symmetric. Any orthogonal gauge within the
+ * occupied and within the virtual block is allowed (f_oo, f_vv need not be
+ * diagonal; f_ov may be nonzero). */
+typedef struct {
+  int32_t nocc, nvir, naux;
+  const double* f_oo; /* device [nocc][nocc] */
+  const double* f_ov; /* device [nocc][nvir] */
+  const double* f_vv; /* device [nvir][nvir] */
+  const double* L;    /* device [naux][n][n] */
+} cc_problem;
+
+/* Bytes of device workspace a handle needs for this shape: the integral
+ * tensors (including the (ac|bd) block, nvir^4 doubles), the intermediates
+ * of the residual and its linearisation, and Krylov bases of m_max + 1 and
+ * inner_restart + 1 vectors plus diis_size history pairs.
+ * lowp_flags: bit 0 keeps FP32 copies, bit 1 BF16 copies of the constant
+ * integral tensors for mixed-precision products. */
+size_t cc_workspace_bytes(int32_t nocc, int32_t nvir, int32_t naux, int lowp_flags, int m_max, int inner_restart,
+                          int diis_size);
+
+/* CCSD residual r(t) (equation CC_ampl) into r1, r2. If e_corr_host is not
+ * NULL the correlation energy E(t) - E_ref (equation CC_energy) is written
+ * there (host) and the stream is synchronised. */
+cc_status cc_residual(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, double* r1, double* r2,
+                      double* e_corr_host, void* stream);
+
+/* Correlation energy at (t1, t2), host output; synchronises. */
+cc_status cc_energy(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, double* e_corr_host,
+                    void* stream);
+
+/* Jacobian-vector product J(t) v (the directional derivative of r at t
+ * along v = (v1, v2); the analytic product of Appendix B carried through
+ * every term) into jv1, jv2. `prec` is the compute precision of the
+ * contractions of the product. Also evaluates r(t) to linearise. */
+cc_status cc_jvp(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, const double* v1,
+                 const double* v2, double* jv1, double* jv2, cc_precision prec, void* stream);
+
+/* y = A_F x, the Fock operator of equation Preconditioner (Appendix C
+ * working equations, extended to singles: (A_F x)_i^a = sum_c f_ac x_i^c -
+ * sum_k f_ki x_k^a + sum_kc f_kc (2 x_ik^ac - x_ik^ca)). The paper's
+ * normalisation factor 4 is absent (it cancels in preconditioning). */
+cc_status cc_fock_apply(cc_handle* h, const cc_problem* p, const double* x1, const double* x2, double* y1,
+                        double* y2, void* stream);
+
+/* Solve A_F x = b by restarted GMRES (restart 30) to
+ * ||b - A_F x||_2 <= rtol ||b||_2 or maxit A_F products; the iteration count
+ * goes to iters_out (host, may be NULL). Returns CC_NOT_CONVERGED when maxit
+ * is reached first. Synchronises. */
+cc_status cc_precond_solve(cc_handle* h, const cc_problem* p, const double* b1, const double* b2, double* x1,
+                           double* x2, double rtol, int maxit, int* iters_out, void* stream);
+
+/* PNK options (Appendix F; Section "Adaptive Forcing").
+ * tol_inf:   stop when ||r||_inf < tol_inf
+ * max_newton: Newton steps cap
+ * m_max:     GMRES iteration cap per Newton step (Krylov basis size)
+ * gamma, alpha: Eisenstat-Walker eta_k = gamma (||r_k||/||r_{k-1}||)^alpha
+ * eta0, eta_max: first forcing term and cap
+ * inner_rtol, inner_maxit, inner_restart: GMRES for A_F^{-1}
+ * jvp_prec:  compute precision of J v (outer quantities stay FP64)
+ * use_fd_jvp: 1 = forward-difference product of equation
+ *            jacobian_vector_product_via_finite_difference instead of the
+ *            analytic one (FP64 only)
+ * init_mp2:  1 = start from theta = -A_F^{-1} r(0); 0 = start from t1/t2 */
+typedef struct {
+  double tol_inf;
+  int max_newton;
+  int m_max;
+  double gamma, alpha, eta0, eta_max;
+  double inner_rtol;
+  int inner_maxit;
+  int inner_restart;
+  cc_precision jvp_prec;
+  int use_fd_jvp;
+  int init_mp2;
+} cc_pnk_opts;
+
+/* FP (+ level shift, + DIIS) options: t <- t - r/(D + level_shift) with D
+ * from the diagonal of f in the given gauge (equation Commutator_MO;
+ * Appendix D), DIIS over the last diis_size (amplitude, step) pairs from
+ * iteration diis_start on (diis_size 0: plain FP). */
+typedef struct {
+  double tol_inf;
+  int max_iter;
+  int diis_size;
+  int diis_start;
+  double level_shift;
+  int init_mp2;
+} cc_fp_opts;
+
+/* Solve statistics (host). n_residual and n_jvp count residual evaluations
+ * and Jacobian products (the paper's cost measure); n_afmv counts A_F
+ * products of the inner solves. */
+typedef struct {
+  double e_corr, res_inf, res_2;
+  int converged, newton_iters, n_residual, n_jvp, n_afmv, n_inner_iters;
+  double seconds;
+} cc_info;
+
+/* Defaults: tol 1e-8, 100 Newton steps, m_max 20, gamma 0.9, alpha 1.5,
+ * eta0 0.5, eta_max 0.9, inner rtol 1e-12, inner maxit 200, restart 30,
+ * FP64 products, analytic J v, MP2 start. */
+void cc_pnk_opts_default(cc_pnk_opts* o);
+/* Defaults: tol 1e-8, 500 iterations, DIIS 8 from iteration 2, no shift,
+ * MP2 start. */
+void cc_fp_opts_default(cc_fp_opts* o);
+
+/* PNK solve. t1/t2: in = initial guess when !init_mp2, out = solution (or
+ * last iterate). info (host) may be NULL. Returns CC_OK, CC_NOT_CONVERGED or
+ * CC_ERR_NAN (non-finite residual; outputs hold the last iterate).
+ * Synchronises. */
+cc_status cc_solve_pnk(cc_handle* h, const cc_problem* p, const cc_pnk_opts* opts, double* t1, double* t2,
+                       cc_info* info, void* stream);
+
+/* FP/SFP(+DIIS) solve; same contract as cc_solve_pnk. A residual norm above
+ * 1e6 ends the iteration as CC_NOT_CONVERGED (divergence). */
+cc_status cc_solve_fp_diis(cc_handle* h, const cc_problem* p, const cc_fp_opts* opts, double* t1, double* t2,
+                           cc_info* info, void* stream);
+
+/* Residual history of the last solve on the handle: pairs (||r||_2,
+ * ||r||_inf) per outer residual evaluation, up to max_pairs written to
+ * `pairs` (host, 2 * max_pairs doubles); returns the number available. */
+int cc_last_history(const cc_handle* h, double* pairs, int max_pairs);
+
+/* ---------------------------------------------------------------------
+ * Serving: continuous batching of PNK solves on one GPU.
+ *
+ * Requests carry HOST problem arrays that are copied at submission. A
+ * scheduler admits queued requests in arrival order while a slot is free and
+ * the request's device footprint (cc_workspace_bytes of its shape and
+ * options plus its problem arrays) fits in the unused part of mem_budget;
+ * admitted requests run concurrently, each on its own stream, so their
+ * kernels overlap on the device. A finished request frees its memory and
+ * slot, and the next queued request is admitted at once. A request whose
+ * footprint exceeds the whole budget is rejected at submission
+ * (CC_ERR_REJECTED). Each result depends only on its own request: the same
+ * kernels and launch shapes run whatever else is in flight.
+ * --------------------------------------------------------------------- */
+typedef struct cc_server cc_server;
+
+/* max_slots: solves in flight at once; mem_budget: device bytes for all of
+ * them (0: 90% of the free device memory). */
+cc_status cc_server_create(cc_server** s, int device, size_t mem_budget, int max_slots);
+/* Copy the host problem (f_oo, f_ov, f_vv, L are HOST pointers here) and
+ * queue a PNK solve; *req_id receives its id. opts may be NULL (defaults). */
+cc_status cc_server_submit(cc_server* s, const cc_problem* p_host, const cc_pnk_opts* opts, uint64_t* req_id);
+/* Non-blocking: *done = 1 when finished, then info (may be NULL) and the
+ * solution (t1_host [o][v], t2_host [o][o][v][v], may be NULL) are copied
+ * out and the request is released. Returns the solve's own status once
+ * done. */
+cc_status cc_server_poll(cc_server* s, uint64_t req_id, int* done, cc_info* info, double* t1_host, double* t2_host);
+/* Wait until every submitted request has finished. */
+cc_status cc_server_drain(cc_server* s);
+/* Admission/latency figures (host): queued, running, finished counts, peak
+ * bytes admitted at once, and the per-request submit/admit/finish times in
+ * seconds since server creation (arrays of length max_reqs, may be NULL). */
+typedef struct {
+  uint64_t queued, running, finished, rejected;
+  size_t bytes_in_use, peak_bytes, budget;
+  int max_slots, peak_running;
+} cc_server_stats;
+cc_status cc_server_get_stats(cc_server* s, cc_server_stats* st);
+cc_status cc_server_request_times(cc_server* s, uint64_t req_id, double* t_submit, double* t_admit,
+                                  double* t_finish);
+void cc_server_destroy(cc_server* s);
+
+/* ---------------------------------------------------------------------
+ * Diagnostics (for kernel tests; not part of the solver path)
+ * --------------------------------------------------------------------- */
+/* C = alpha * A * B + beta * C with element strides (A[m*a_m + k*a_k],
+ * B[k*b_k + n*b_n], C[m*c_m + n*c_n]), all float64 device arrays, computed
+ * on the matrix cores in precision `prec` (FP32/BF16: float accumulation).
+ * This is the contraction kernel every residual term runs on. */
+/* Device timing of tagged work on the handle, with HIP events recorded on
+ * the stream each launch runs on. Slots: 0 the particle-particle ladder
+ * contraction (one launch per residual or J v), 1 whole residual
+ * evaluations, 2 whole J v products, 3 A_F products, 4 inner A_F solves.
+ * cc_diag_timing(h, 1) enables and resets; cc_diag_timing_read synchronises
+ * the recorded events and returns the launch count and total milliseconds
+ * of one slot. */
+cc_status cc_diag_timing(cc_handle* h, int enable);
+cc_status cc_diag_timing_read(cc_handle* h, int slot, int* count, double* total_ms);
+
+cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_t a_k, const double* B,
+                       int64_t b_k, int64_t b_n, double* C, int64_t c_m, int64_t c_n, double alpha, double beta,
+                       cc_precision prec, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNKCC_H */

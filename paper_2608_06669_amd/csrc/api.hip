@@ -1,0 +1,439 @@
+// C boundary of the library (include/pnkcc.h): argument checks, workspace
+// management, problem caching and status codes.
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+
+#include "../../include/pnkcc.h"
+#include "api_internal.hpp"
+#include "gemm.hpp"
+#include "tensor_ops.hpp"
+
+using namespace pnk;
+
+namespace pnk {
+
+size_t workspace_bytes(int o, int v, int naux, int lowp, int m_max, int restart, int diis) {
+  EngineOptions eo;
+  eo.lowp_f32 = lowp & 1;
+  eo.lowp_bf16 = (lowp >> 1) & 1;
+  const int64_t nvec = (int64_t)o * v + (int64_t)o * o * v * v;
+  return engine_bytes(o, v, naux, eo) + Solver::bytes(nvec, m_max, restart, diis) + 2 * nvec * sizeof(double);
+}
+
+void check_problem(const cc_problem* p) {
+  PNK_REQUIRE(p != nullptr, "problem is NULL");
+  PNK_REQUIRE(p->nocc > 0 && p->nvir > 0 && p->naux > 0, "nocc, nvir and naux must be positive");
+  PNK_REQUIRE(p->f_oo && p->f_ov && p->f_vv && p->L, "problem arrays must not be NULL");
+  PNK_REQUIRE(p->nocc <= 255, "nocc above 255 is not supported");
+  const int64_t ov = (int64_t)p->nocc * p->nvir;
+  PNK_REQUIRE(ov <= 46000, "nocc * nvir above 46000 is not supported");
+  PNK_REQUIRE((int64_t)p->nvir * p->nvir <= 1000000, "nvir above 1000 is not supported");
+}
+
+void* Handle::dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = stream_ordered ? hipMallocAsync(&p, bytes, alloc_stream) : hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw OomError("device allocation of " + std::to_string(bytes) + " bytes failed");
+  }
+  return p;
+}
+
+void Handle::dev_free(void* p) {
+  if (!p) return;
+  (void)(stream_ordered ? hipFreeAsync(p, alloc_stream) : hipFree(p));
+}
+
+Handle::~Handle() {
+  sol.reset();
+  eng.reset();
+  dev_free(xa);
+  dev_free(xb);
+  dev_free(hash_buf);
+}
+
+void Handle::ensure(const cc_problem* p, int lowp, int m_max, int restart, int diis, hipStream_t s) {
+  check_problem(p);
+  PNK_HIP(hipSetDevice(device));
+  const int o = p->nocc, v = p->nvir, naux = p->naux;
+  const bool want32 = (lowp & 1) || (eng && eng->options().lowp_f32 && eng->o() == o && eng->v() == v &&
+                                     eng->naux() == naux);
+  const bool want16 = ((lowp >> 1) & 1) || (eng && eng->options().lowp_bf16 && eng->o() == o && eng->v() == v &&
+                                            eng->naux() == naux);
+  const bool same_shape = eng && eng->o() == o && eng->v() == v && eng->naux() == naux;
+  const bool have_lowp = same_shape && (!want32 || eng->options().lowp_f32) && (!want16 || eng->options().lowp_bf16);
+  const bool have_solver = sol && same_shape && sol_m >= m_max && sol_r >= restart && sol_d >= diis;
+  if (!same_shape || !have_lowp || !have_solver) {
+    const int M = std::max(m_max, same_shape && sol ? sol_m : 0);
+    const int R = std::max(restart, same_shape && sol ? sol_r : 0);
+    const int Dd = std::max(diis, same_shape && sol ? sol_d : 0);
+    const int lp = (want32 ? 1 : 0) | (want16 ? 2 : 0);
+    const size_t need = workspace_bytes(o, v, naux, lp, M, R, Dd);
+    if (limit && need > limit)
+      throw OomError("problem needs " + std::to_string(need) + " workspace bytes; the handle limit is " +
+                     std::to_string(limit));
+    if (!same_shape || !have_lowp) {
+      sol.reset();
+      eng.reset();
+      dev_free(xa);
+      dev_free(xb);
+      xa = xb = nullptr;
+      EngineOptions eo;
+      eo.lowp_f32 = want32;
+      eo.lowp_bf16 = want16;
+      eo.alloc_stream = alloc_stream;
+      eo.stream_ordered = stream_ordered;
+      eng = std::make_unique<Engine>(o, v, naux, eo);
+      eng->set_timers(timers.get());
+      prepared = false;
+      const int64_t n = eng->nvec();
+      xa = (double*)dev_alloc(n * sizeof(double));
+      xb = (double*)dev_alloc(n * sizeof(double));
+    }
+    sol.reset();
+    sol = std::make_unique<Solver>(*eng, M, R, Dd, alloc_stream, stream_ordered);
+    sol_m = M;
+    sol_r = R;
+    sol_d = Dd;
+  }
+  if (!hash_buf) hash_buf = (uint64_t*)dev_alloc((kReduceBlocks + 8) * sizeof(uint64_t));
+  // content key of the problem
+  const int64_t n = o + v;
+  uint64_t* parts = hash_buf + 8;
+  hash64((int64_t)o * o, p->f_oo, hash_buf + 0, parts, s);
+  hash64((int64_t)o * v, p->f_ov, hash_buf + 1, parts, s);
+  hash64((int64_t)v * v, p->f_vv, hash_buf + 2, parts, s);
+  hash64((int64_t)naux * n * n, p->L, hash_buf + 3, parts, s);
+  uint64_t hv[4];
+  PNK_HIP(hipMemcpyAsync(hv, hash_buf, sizeof(hv), hipMemcpyDeviceToHost, s));
+  PNK_HIP(hipStreamSynchronize(s));
+  ProblemKey key{o, v, naux, p->f_oo, p->f_ov, p->f_vv, p->L, {hv[0], hv[1], hv[2], hv[3]}};
+  if (!prepared || !(key == cached_key)) {
+    ProblemView pv;
+    pv.o = o; pv.v = v; pv.naux = naux;
+    pv.f_oo = p->f_oo; pv.f_ov = p->f_ov; pv.f_vv = p->f_vv; pv.L = p->L;
+    eng->prepare(pv, s);
+    cached_key = key;
+    prepared = true;
+  }
+}
+
+void pack(int64_t ov, int64_t n2, const double* a1, const double* a2, double* x, hipStream_t s) {
+  PNK_HIP(hipMemcpyAsync(x, a1, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PNK_HIP(hipMemcpyAsync(x + ov, a2, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+void unpack(int64_t ov, int64_t n2, const double* x, double* a1, double* a2, hipStream_t s) {
+  PNK_HIP(hipMemcpyAsync(a1, x, ov * sizeof(double), hipMemcpyDeviceToDevice, s));
+  PNK_HIP(hipMemcpyAsync(a2, x + ov, n2 * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+PnkOptions to_internal(const cc_pnk_opts& o) {
+  PnkOptions r;
+  r.tol_inf = o.tol_inf;
+  r.max_newton = o.max_newton;
+  r.m_max = o.m_max;
+  r.gamma = o.gamma;
+  r.alpha = o.alpha;
+  r.eta0 = o.eta0;
+  r.eta_max = o.eta_max;
+  r.inner_rtol = o.inner_rtol;
+  r.inner_maxit = o.inner_maxit;
+  r.inner_restart = o.inner_restart;
+  r.jvp_prec = (Prec)o.jvp_prec;
+  r.use_fd_jvp = o.use_fd_jvp != 0;
+  r.init_mp2 = o.init_mp2 != 0;
+  return r;
+}
+
+void check_pnk_opts(const cc_pnk_opts& o) {
+  PNK_REQUIRE(o.tol_inf > 0 && std::isfinite(o.tol_inf), "tol_inf must be positive");
+  PNK_REQUIRE(o.max_newton >= 0, "max_newton must be >= 0");
+  PNK_REQUIRE(o.m_max >= 1 && o.m_max <= 200, "m_max must be in 1..200");
+  PNK_REQUIRE(o.inner_restart >= 1 && o.inner_restart <= 200, "inner_restart must be in 1..200");
+  PNK_REQUIRE(o.inner_maxit >= 1, "inner_maxit must be >= 1");
+  PNK_REQUIRE(o.inner_rtol > 0 && o.inner_rtol < 1, "inner_rtol must be in (0, 1)");
+  PNK_REQUIRE(o.jvp_prec == CC_FP64 || o.jvp_prec == CC_FP32 || o.jvp_prec == CC_BF16, "unknown jvp_prec");
+  PNK_REQUIRE(!(o.use_fd_jvp && o.jvp_prec != CC_FP64), "the finite-difference product is FP64 only");
+  PNK_REQUIRE(o.eta_max > 0 && o.eta_max < 1 && o.eta0 > 0 && o.eta0 < 1, "forcing terms must be in (0, 1)");
+}
+
+int lowp_for(cc_precision p) { return p == CC_FP32 ? 1 : (p == CC_BF16 ? 2 : 0); }
+
+}  // namespace pnk
+
+#define PNK_API_BEGIN(hp)                                   \
+  if (!(hp)) return CC_ERR_ARG;                             \
+  Handle* H = reinterpret_cast<Handle*>(hp);                \
+  H->err.clear();                                           \
+  try {
+#define PNK_API_END                                         \
+  }                                                         \
+  catch (const ArgError& e) { H->err = e.what(); return CC_ERR_ARG; } \
+  catch (const OomError& e) { H->err = e.what(); return CC_ERR_OOM; } \
+  catch (const HipError& e) { H->err = e.what(); return CC_ERR_HIP; } \
+  catch (const std::exception& e) { H->err = e.what(); return CC_ERR_INTERNAL; }
+
+extern "C" {
+
+cc_status cc_create(cc_handle** h, int device, size_t workspace_limit_bytes) {
+  if (!h) return CC_ERR_ARG;
+  *h = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) {
+    (void)hipGetLastError();
+    return CC_ERR_HIP;
+  }
+  Handle* H = new (std::nothrow) Handle();
+  if (!H) return CC_ERR_OOM;
+  H->device = device;
+  H->limit = workspace_limit_bytes;
+  *h = reinterpret_cast<cc_handle*>(H);
+  return CC_OK;
+}
+
+void cc_destroy(cc_handle* h) {
+  if (!h) return;
+  Handle* H = reinterpret_cast<Handle*>(h);
+  (void)hipSetDevice(H->device);
+  delete H;
+}
+
+const char* cc_last_error(const cc_handle* h) {
+  if (!h) return "null handle";
+  return reinterpret_cast<const Handle*>(h)->err.c_str();
+}
+
+size_t cc_workspace_bytes(int32_t nocc, int32_t nvir, int32_t naux, int lowp_flags, int m_max, int inner_restart,
+                          int diis_size) {
+  if (nocc <= 0 || nvir <= 0 || naux <= 0 || m_max < 1 || inner_restart < 1 || diis_size < 0) return 0;
+  return workspace_bytes(nocc, nvir, naux, lowp_flags, m_max, inner_restart, diis_size);
+}
+
+void cc_pnk_opts_default(cc_pnk_opts* o) {
+  if (!o) return;
+  o->tol_inf = 1e-8;
+  o->max_newton = 100;
+  o->m_max = 20;
+  o->gamma = 0.9;
+  o->alpha = 1.5;
+  o->eta0 = 0.5;
+  o->eta_max = 0.9;
+  o->inner_rtol = 1e-12;
+  o->inner_maxit = 200;
+  o->inner_restart = 30;
+  o->jvp_prec = CC_FP64;
+  o->use_fd_jvp = 0;
+  o->init_mp2 = 1;
+}
+
+void cc_fp_opts_default(cc_fp_opts* o) {
+  if (!o) return;
+  o->tol_inf = 1e-8;
+  o->max_iter = 500;
+  o->diis_size = 8;
+  o->diis_start = 2;
+  o->level_shift = 0.0;
+  o->init_mp2 = 1;
+}
+
+cc_status cc_residual(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, double* r1, double* r2,
+                      double* e_corr_host, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(t1 && t2 && r1 && r2, "t1, t2, r1, r2 must not be NULL");
+  H->ensure(p, 0, 1, 1, 0, s);
+  H->eng->residual(t1, t2, r1, r2, s);
+  if (e_corr_host) {
+    H->eng->energy(t1, t2, H->eng->scratch_partials() + 1024, s);
+    PNK_HIP(hipMemcpyAsync(e_corr_host, H->eng->scratch_partials() + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+    PNK_HIP(hipStreamSynchronize(s));
+  }
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_energy(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, double* e_corr_host,
+                    void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(t1 && t2 && e_corr_host, "t1, t2, e_corr_host must not be NULL");
+  H->ensure(p, 0, 1, 1, 0, s);
+  H->eng->energy(t1, t2, H->eng->scratch_partials() + 1024, s);
+  PNK_HIP(hipMemcpyAsync(e_corr_host, H->eng->scratch_partials() + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+  PNK_HIP(hipStreamSynchronize(s));
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_jvp(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, const double* v1,
+                 const double* v2, double* jv1, double* jv2, cc_precision prec, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(t1 && t2 && v1 && v2 && jv1 && jv2, "array arguments must not be NULL");
+  PNK_REQUIRE(prec == CC_FP64 || prec == CC_FP32 || prec == CC_BF16, "unknown precision");
+  H->ensure(p, lowp_for(prec), 1, 1, 0, s);
+  // linearise at t: the residual goes to the handle's scratch vector
+  const int64_t ov = H->eng->o() * (int64_t)H->eng->v();
+  H->eng->residual(t1, t2, H->xa, H->xa + ov, s);
+  H->eng->jvp(v1, v2, jv1, jv2, (Prec)prec, s);
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_fock_apply(cc_handle* h, const cc_problem* p, const double* x1, const double* x2, double* y1,
+                        double* y2, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(x1 && x2 && y1 && y2, "array arguments must not be NULL");
+  H->ensure(p, 0, 1, 1, 0, s);
+  H->eng->fock_apply(x1, x2, y1, y2, s);
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_precond_solve(cc_handle* h, const cc_problem* p, const double* b1, const double* b2, double* x1,
+                           double* x2, double rtol, int maxit, int* iters_out, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(b1 && b2 && x1 && x2, "array arguments must not be NULL");
+  PNK_REQUIRE(rtol > 0 && rtol < 1 && maxit >= 1, "rtol must be in (0, 1) and maxit >= 1");
+  H->ensure(p, 0, 1, 30, 0, s);
+  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
+  pack(ov, n2, b1, b2, H->xb, s);
+  bool conv = true;
+  const int it = H->sol->precond_solve(H->xb, H->xa, rtol, maxit, 30, s, &conv);
+  unpack(ov, n2, H->xa, x1, x2, s);
+  PNK_HIP(hipStreamSynchronize(s));
+  if (iters_out) *iters_out = it;
+  return conv ? CC_OK : CC_NOT_CONVERGED;
+  PNK_API_END
+}
+
+static void fill_info(const SolveStats& st, cc_info* info) {
+  if (!info) return;
+  info->e_corr = st.e_corr;
+  info->res_inf = st.res_inf;
+  info->res_2 = st.res_2;
+  info->converged = st.converged;
+  info->newton_iters = st.newton_iters;
+  info->n_residual = st.n_residual;
+  info->n_jvp = st.n_jvp;
+  info->n_afmv = st.n_afmv;
+  info->n_inner_iters = st.n_inner_iters;
+  info->seconds = st.seconds;
+}
+
+cc_status cc_solve_pnk(cc_handle* h, const cc_problem* p, const cc_pnk_opts* opts, double* t1, double* t2,
+                       cc_info* info, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(t1 && t2, "t1, t2 must not be NULL");
+  cc_pnk_opts o;
+  cc_pnk_opts_default(&o);
+  if (opts) o = *opts;
+  check_pnk_opts(o);
+  H->ensure(p, lowp_for(o.jvp_prec), o.m_max, o.inner_restart, 0, s);
+  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
+  if (!o.init_mp2) pack(ov, n2, t1, t2, H->xa, s);
+  SolveStats st;
+  H->sol->solve_pnk(H->xa, to_internal(o), &st, s);
+  unpack(ov, n2, H->xa, t1, t2, s);
+  PNK_HIP(hipStreamSynchronize(s));
+  H->history = H->sol->history();
+  fill_info(st, info);
+  if (st.diverged) { H->err = "non-finite residual norm"; return CC_ERR_NAN; }
+  return st.converged ? CC_OK : CC_NOT_CONVERGED;
+  PNK_API_END
+}
+
+cc_status cc_solve_fp_diis(cc_handle* h, const cc_problem* p, const cc_fp_opts* opts, double* t1, double* t2,
+                           cc_info* info, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(t1 && t2, "t1, t2 must not be NULL");
+  cc_fp_opts o;
+  cc_fp_opts_default(&o);
+  if (opts) o = *opts;
+  PNK_REQUIRE(o.tol_inf > 0 && o.max_iter >= 0 && o.diis_size >= 0 && o.diis_size <= 32 && o.diis_start >= 0,
+              "invalid FP options");
+  H->ensure(p, 0, 1, 30, std::max(o.diis_size, 1), s);
+  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
+  if (!o.init_mp2) pack(ov, n2, t1, t2, H->xa, s);
+  FpOptions fo;
+  fo.tol_inf = o.tol_inf;
+  fo.max_iter = o.max_iter;
+  fo.diis_size = o.diis_size;
+  fo.diis_start = o.diis_start;
+  fo.level_shift = o.level_shift;
+  fo.init_mp2 = o.init_mp2 != 0;
+  SolveStats st;
+  H->sol->solve_fp_diis(H->xa, fo, &st, s);
+  unpack(ov, n2, H->xa, t1, t2, s);
+  PNK_HIP(hipStreamSynchronize(s));
+  H->history = H->sol->history();
+  fill_info(st, info);
+  if (st.diverged) { H->err = "non-finite residual norm"; return CC_ERR_NAN; }
+  return st.converged ? CC_OK : CC_NOT_CONVERGED;
+  PNK_API_END
+}
+
+int cc_last_history(const cc_handle* h, double* pairs, int max_pairs) {
+  if (!h) return 0;
+  const Handle* H = reinterpret_cast<const Handle*>(h);
+  const int avail = (int)(H->history.size() / 2);
+  if (pairs)
+    for (int i = 0; i < std::min(avail, max_pairs); ++i) {
+      pairs[2 * i] = H->history[2 * i];
+      pairs[2 * i + 1] = H->history[2 * i + 1];
+    }
+  return avail;
+}
+
+cc_status cc_diag_timing(cc_handle* h, int enable) {
+  PNK_API_BEGIN(h)
+  if (enable) {
+    if (!H->timers) H->timers = std::make_unique<Timers>();
+    H->timers->reset();
+  } else if (H->timers) {
+    H->timers->reset();
+    if (H->eng) H->eng->set_timers(nullptr);
+    H->timers.reset();
+  }
+  if (H->eng) H->eng->set_timers(H->timers.get());
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_diag_timing_read(cc_handle* h, int slot, int* count, double* total_ms) {
+  PNK_API_BEGIN(h)
+  PNK_REQUIRE(count && total_ms && slot >= 0 && slot < kTimerSlots, "invalid timing query");
+  if (!H->timers) { *count = 0; *total_ms = 0.0; return CC_OK; }
+  H->timers->read(slot, count, total_ms);
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_t a_k, const double* B,
+                       int64_t b_k, int64_t b_n, double* C, int64_t c_m, int64_t c_n, double alpha, double beta,
+                       cc_precision prec, void* stream) {
+  if (M < 1 || N < 1 || K < 1 || !A || !B || !C) return CC_ERR_ARG;
+  if (prec != CC_FP64 && prec != CC_FP32 && prec != CC_BF16) return CC_ERR_ARG;
+  try {
+    GemmDesc d;
+    d.M = M; d.N = N; d.K = K;
+    d.a_m = a_m; d.a_k = a_k; d.b_k = b_k; d.b_n = b_n; d.c_m = c_m; d.c_n = c_n;
+    d.alpha = alpha; d.beta = beta;
+    gemm(d, A, Prec::F64, B, Prec::F64, C, Prec::F64, (Prec)prec, (hipStream_t)stream);
+  } catch (const ArgError&) {
+    return CC_ERR_ARG;
+  } catch (const std::exception&) {
+    return CC_ERR_HIP;
+  }
+  return CC_OK;
+}
+
+}  // extern "C"

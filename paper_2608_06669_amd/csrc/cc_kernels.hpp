@@ -1,0 +1,33 @@
+// Small problem-specific kernels of the CCSD path (bandwidth or latency
+// bound): integral block extraction, Fock assembly, traces, the energy
+// reduction and the Jacobi update.
+#pragma once
+
+#include "common.hpp"
+
+namespace pnk {
+
+// f[n][n] from f_oo [o][o], f_ov [o][v], f_vv [v][v] (f_vo = f_ov^T)
+void assemble_fock(int o, int v, const double* f_oo, const double* f_ov, const double* f_vv, double* f,
+                   hipStream_t s);
+// Lo[P][k][q] = L[P][k][q] for k < o (rows of the occupied orbitals)
+void extract_occ_rows(int naux, int o, int n, const double* L, double* Lo, hipStream_t s);
+// Blocks of the np = naux + 1 slices [L[0..naux-1]; h]: oo [np][o][o],
+// ov [np][o][v], vo [np][v][o], vv [np][v][v]
+void extract_blocks(int naux, int o, int v, const double* L, const double* h, double* Loo, double* Lov,
+                    double* Lvo, double* Lvv, hipStream_t s);
+// D[P] = sum_k X[P][k][k] for P < nslices, X of shape [.][o][o]
+void trace_slices(int nslices, int o, const double* X, double* D, hipStream_t s);
+// d[P] = sum_{k<o} L[P][k][k], L of shape [naux][n][n]
+void trace_occ(int naux, int o, int n, const double* L, double* d, hipStream_t s);
+// E = 2 sum f_ov t1 + sum_ijab Itil (t2 + t1_ia t1_jb) -> out (device), deterministic
+void energy(int o, int v, const double* f_ov, const double* Itil, const double* t1, const double* t2, double* out,
+            double* partials, hipStream_t s);
+// t <- t - r / (D + shift) with Jacobi denominators from diag(f_oo), diag(f_vv);
+// e = -r / (D + shift) is written to `step` when it is not null
+void jacobi_update(int o, int v, const double* f_oo, const double* f_vv, double shift, const double* r, double* t,
+                   double* step, hipStream_t s);
+// y = x / *s_dev (the divisor stays on the device)
+void scale_by_inverse(int64_t n, const double* x, const double* s_dev, double* y, hipStream_t s);
+
+}  // namespace pnk

@@ -1,0 +1,449 @@
+// PNK (Appendix F algorithm with Eisenstat-Walker forcing) and FP+DIIS.
+//
+// All vectors live on the device in the packed layout [t1 (o*v) | t2
+// (o*o*v*v)]. The outer Newton residual, the energy, the Arnoldi
+// orthogonalisation, the Hessenberg least-squares problem and the
+// amplitude update are FP64 whatever precision the Jacobian products use.
+//
+// Orthogonalisation: classical Gram-Schmidt applied twice (CGS2) with fused
+// multi-vector dot and update kernels. It builds the same Arnoldi relation
+// as the modified Gram-Schmidt of the paper's algorithm (identical in exact
+// arithmetic, at least as orthogonal in floating point) and needs one
+// device-to-host transfer per Krylov step instead of one per basis vector.
+// The small Hessenberg problem (Givens rotations, back substitution) is
+// solved on the host.
+
+#include "solvers.hpp"
+
+#include <chrono>
+#include <cmath>
+
+#include "cc_kernels.hpp"
+#include "tensor_ops.hpp"
+
+namespace pnk {
+
+namespace {
+constexpr int kMaxBasis = 256;  // multi_axpy limit
+constexpr int kScal = 4 * kMaxBasis + 8;
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Givens rotation zeroing b in (a, b): returns (c, s) with c a + s b = rho
+void givens(double a, double b, double* c, double* s) {
+  const double rho = std::hypot(a, b);
+  if (rho == 0.0) { *c = 1.0; *s = 0.0; return; }
+  *c = a / rho;
+  *s = b / rho;
+}
+
+// Solve the upper-triangular k x k system R y = g (R column-major in H with
+// leading dimension ldh).
+std::vector<double> back_substitute(const std::vector<double>& H, int ldh, const std::vector<double>& g, int k) {
+  std::vector<double> y(k, 0.0);
+  for (int i = k - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int j = i + 1; j < k; ++j) acc -= H[i + (size_t)j * ldh] * y[j];
+    const double d = H[i + (size_t)i * ldh];
+    y[i] = d != 0.0 ? acc / d : 0.0;
+  }
+  return y;
+}
+
+}  // namespace
+
+size_t Solver::bytes(int64_t n, int m_max, int restart, int diis) {
+  const size_t vecs = (size_t)(m_max + 1) + (restart + 1) + 4 + 2 * (size_t)diis;
+  return vecs * n * sizeof(double) + (kScal + reduce_partials_size(kMaxBasis)) * sizeof(double) + 16 * 256;
+}
+
+Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_stream, bool stream_ordered)
+    : eng_(eng), n_(eng.nvec()), m_max_(m_max), restart_(restart), diis_(diis), alloc_stream_(alloc_stream),
+      async_(stream_ordered) {
+  PNK_REQUIRE(m_max >= 1 && m_max < kMaxBasis && restart >= 1 && restart < kMaxBasis && diis >= 0 && diis < 64,
+              "solver: Krylov or DIIS size out of range");
+  auto alloc = [&](size_t count) {
+    double* p = nullptr;
+    if (count == 0) return p;
+    hipError_t e = async_ ? hipMallocAsync((void**)&p, count * sizeof(double), alloc_stream_)
+                          : hipMalloc(&p, count * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw OomError("solver allocation failed");
+    }
+    return p;
+  };
+  Qo_ = alloc((size_t)(m_max + 1) * n_);
+  Qi_ = alloc((size_t)(restart + 1) * n_);
+  r_ = alloc(n_);
+  ri_ = alloc(n_);
+  w_ = alloc(n_);
+  w2_ = alloc(n_);
+  hx_ = alloc((size_t)diis * n_);
+  he_ = alloc((size_t)diis * n_);
+  dsc_ = alloc(kScal);
+  partials_ = alloc(reduce_partials_size(kMaxBasis));
+  PNK_HIP(hipHostMalloc(&host_, kScal * sizeof(double), hipHostMallocDefault));
+}
+
+Solver::~Solver() {
+  for (double* p : {Qo_, Qi_, r_, ri_, w_, w2_, hx_, he_, dsc_, partials_})
+    if (p) (void)(async_ ? hipFreeAsync(p, alloc_stream_) : hipFree(p));
+  if (host_) (void)hipHostFree(host_);
+}
+
+// Host-to-device copy through pinned staging (host_ + 3 * kMaxBasis). Every
+// upload is followed by a stream synchronisation before the staging area is
+// written again.
+void Solver::upload(double* dev, const double* src, int n, hipStream_t s) {
+  PNK_REQUIRE(n <= kMaxBasis, "upload: too many scalars");
+  double* stage = host_ + 3 * kMaxBasis;
+  for (int i = 0; i < n; ++i) stage[i] = src[i];
+  PNK_HIP(hipMemcpyAsync(dev, stage, n * sizeof(double), hipMemcpyHostToDevice, s));
+}
+
+void Solver::read_scalars(double* host, const double* dev, int n, hipStream_t s) {
+  PNK_HIP(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  PNK_HIP(hipStreamSynchronize(s));
+}
+
+void Solver::norms(const double* r, double* ninf, double* n2, hipStream_t s) {
+  nrm_inf(n_, r, dsc_ + 0, partials_, s);
+  nrm2(n_, r, dsc_ + 1, partials_ + kReduceBlocks, s);
+  read_scalars(host_, dsc_, 2, s);
+  *ninf = host_[0];
+  *n2 = host_[1];
+}
+
+double Solver::orthogonalise(double* Q, int64_t ldq, int m, double* w, std::vector<double>& h, hipStream_t s) {
+  double* h1 = dsc_;
+  double* h2 = dsc_ + kMaxBasis;
+  double* hn = dsc_ + 2 * kMaxBasis;
+  multi_dot(n_, m, Q, ldq, w, h1, partials_, s);
+  multi_axpy(n_, m, Q, ldq, h1, w, s);
+  multi_dot(n_, m, Q, ldq, w, h2, partials_, s);
+  multi_axpy(n_, m, Q, ldq, h2, w, s);
+  nrm2(n_, w, hn, partials_, s);
+  read_scalars(host_, dsc_, 2 * kMaxBasis + 1, s);
+  h.assign(m, 0.0);
+  for (int i = 0; i < m; ++i) h[i] = host_[i] + host_[kMaxBasis + i];
+  return host_[2 * kMaxBasis];
+}
+
+int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s,
+                          bool* converged) {
+  PNK_REQUIRE(restart >= 1 && restart <= restart_, "precond_solve: restart exceeds the allocated basis");
+  const int64_t n = n_;
+  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  Timers* tm = eng_.timers();
+  if (tm) tm->begin(kTimerPrecond, s);
+  struct EndTimer {
+    Timers* t; hipStream_t s;
+    ~EndTimer() { if (t) t->end(kTimerPrecond, s); }
+  } end_timer{tm, s};
+  double bn, dummy;
+  norms(b, &dummy, &bn, s);
+  fill(n, 0.0, x, s);
+  if (converged) *converged = true;
+  if (bn == 0.0) return 0;
+  int total = 0;
+  copy(n, b, ri_, s);  // r = b - A x with x = 0
+  double beta = bn;
+  std::vector<double> H((size_t)(restart + 1) * restart), cs(restart), sn(restart), g(restart + 1), h;
+  while (true) {
+    if (beta <= rtol * bn || total >= maxit || !std::isfinite(beta)) {
+      if (converged) *converged = beta <= rtol * bn;
+      return total;
+    }
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    // Q_0 = r / beta
+    scale_by_inverse(n, ri_, dsc_ + 1, Qi_, s);  // ||r|| from the last norms()
+    int k_done = 0;
+    bool done = false;
+    for (int k = 0; k < restart; ++k) {
+      double* q = Qi_ + (size_t)k * n;
+      double* wv = Qi_ + (size_t)(k + 1) * n;
+      eng_.fock_apply(q, q + ov, wv, wv + ov, s);
+      ++total;
+      const double hn = orthogonalise(Qi_, n, k + 1, wv, h, s);
+      for (int i = 0; i <= k; ++i) H[i + (size_t)k * (restart + 1)] = h[i];
+      H[k + 1 + (size_t)k * (restart + 1)] = hn;
+      for (int i = 0; i < k; ++i) {
+        double& a = H[i + (size_t)k * (restart + 1)];
+        double& c = H[i + 1 + (size_t)k * (restart + 1)];
+        const double t = cs[i] * a + sn[i] * c;
+        c = -sn[i] * a + cs[i] * c;
+        a = t;
+      }
+      givens(H[k + (size_t)k * (restart + 1)], hn, &cs[k], &sn[k]);
+      H[k + (size_t)k * (restart + 1)] = cs[k] * H[k + (size_t)k * (restart + 1)] + sn[k] * hn;
+      H[k + 1 + (size_t)k * (restart + 1)] = 0.0;
+      g[k + 1] = -sn[k] * g[k];
+      g[k] = cs[k] * g[k];
+      k_done = k + 1;
+      if (std::fabs(g[k + 1]) <= rtol * bn || total >= maxit || hn == 0.0 || !std::isfinite(hn)) {
+        done = std::fabs(g[k + 1]) <= rtol * bn || hn == 0.0;
+        break;
+      }
+      scale_by_inverse(n, wv, dsc_ + 2 * kMaxBasis, wv, s);  // hn, still on the device
+    }
+    std::vector<double> y = back_substitute(H, restart + 1, g, k_done);
+    upload(dsc_ + 3 * kMaxBasis, y.data(), k_done, s);
+    combine(n, k_done, Qi_, n, dsc_ + 3 * kMaxBasis, 1.0, x, s);
+    if (done) {
+      // the Givens estimate already meets the tolerance
+      PNK_HIP(hipStreamSynchronize(s));
+      if (converged) *converged = true;
+      return total;
+    }
+    // true residual for the restart
+    eng_.fock_apply(x, x + ov, ri_, ri_ + ov, s);
+    axpby(n, 1.0, b, -1.0, ri_, s);
+    double rinf;
+    norms(ri_, &rinf, &beta, s);
+  }
+}
+
+namespace {
+double forcing(int k, double rn, double rn_prev, double eta_prev, double tol, const PnkOptions& o) {
+  double eta;
+  if (k == 0) {
+    eta = o.eta0;
+  } else {
+    eta = o.gamma * std::pow(rn / rn_prev, o.alpha);
+    const double sg = o.gamma * std::pow(eta_prev, o.alpha);
+    if (sg > 0.1) eta = std::max(eta, sg);
+  }
+  eta = std::min(eta, o.eta_max);
+  eta = std::max(eta, 0.5 * tol / rn);
+  return std::min(eta, o.eta_max);
+}
+}  // namespace
+
+void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s) {
+  const double t0 = now_s();
+  *st = SolveStats();
+  hist_.clear();
+  PNK_REQUIRE(opt.m_max >= 1 && opt.m_max <= m_max_, "pnk: m_max exceeds the allocated basis");
+  const int64_t n = n_;
+  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  auto Ainv = [&](const double* b, double* out) {
+    bool conv = true;
+    const int it = precond_solve(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv);
+    st->n_afmv += it;
+    st->n_inner_iters += it;
+  };
+  if (opt.init_mp2) {
+    eng_.residual(eng_.zeros(), eng_.zeros() + ov, r_, r_ + ov, s);
+    st->n_residual++;
+    Ainv(r_, x);
+    axpby(n, 0.0, x, -1.0, x, s);
+  }
+  double rn_prev = 0.0, eta = opt.eta0;
+  int k = 0;
+  std::vector<double> H, cs, sn, g, h;
+  while (true) {
+    eng_.residual(x, x + ov, r_, r_ + ov, s);
+    st->n_residual++;
+    double rinf, rn;
+    norms(r_, &rinf, &rn, s);
+    hist_.push_back(rn);
+    hist_.push_back(rinf);
+    st->res_inf = rinf;
+    st->res_2 = rn;
+    if (!std::isfinite(rn)) { st->diverged = 1; break; }
+    if (rinf < opt.tol_inf) { st->converged = 1; break; }
+    if (k >= opt.max_newton) break;
+    eta = forcing(k, rn, rn_prev, eta, opt.tol_inf, opt);
+    // z = A_F^{-1} r, q_1 = z / beta
+    Ainv(r_, w_);
+    double zinf, beta;
+    norms(w_, &zinf, &beta, s);
+    if (!(beta > 0.0) || !std::isfinite(beta)) { st->diverged = !std::isfinite(beta); break; }
+    scale_by_inverse(n, w_, dsc_ + 1, Qo_, s);  // beta from norms()
+    const int M = opt.m_max;
+    H.assign((size_t)(M + 1) * M, 0.0);
+    cs.assign(M, 0.0);
+    sn.assign(M, 0.0);
+    g.assign(M + 1, 0.0);
+    g[0] = beta;
+    double delta = 0.0;
+    if (opt.use_fd_jvp) {
+      double xinf, xn;
+      norms(x, &xinf, &xn, s);
+      delta = std::sqrt(2.220446049250313e-16) * (1.0 + xn);
+    }
+    int m_done = 0;
+    for (int m = 0; m < M; ++m) {
+      double* q = Qo_ + (size_t)m * n;
+      double* wv = Qo_ + (size_t)(m + 1) * n;
+      if (opt.use_fd_jvp) {
+        // (r(theta + delta q) - r(theta)) / delta, the paper's product
+        copy(n, x, w2_, s);
+        axpby(n, delta, q, 1.0, w2_, s);
+        eng_.residual(w2_, w2_ + ov, w_, w_ + ov, s);
+        axpby(n, -1.0 / delta, r_, 1.0 / delta, w_, s);
+      } else {
+        eng_.jvp(q, q + ov, w_, w_ + ov, opt.jvp_prec, s);
+      }
+      st->n_jvp++;
+      Ainv(w_, wv);
+      const double hn = orthogonalise(Qo_, n, m + 1, wv, h, s);
+      for (int i = 0; i <= m; ++i) H[i + (size_t)m * (M + 1)] = h[i];
+      for (int i = 0; i < m; ++i) {
+        double& a = H[i + (size_t)m * (M + 1)];
+        double& c = H[i + 1 + (size_t)m * (M + 1)];
+        const double t = cs[i] * a + sn[i] * c;
+        c = -sn[i] * a + cs[i] * c;
+        a = t;
+      }
+      givens(H[m + (size_t)m * (M + 1)], hn, &cs[m], &sn[m]);
+      H[m + (size_t)m * (M + 1)] = cs[m] * H[m + (size_t)m * (M + 1)] + sn[m] * hn;
+      g[m + 1] = -sn[m] * g[m];
+      g[m] = cs[m] * g[m];
+      m_done = m + 1;
+      if (std::fabs(g[m + 1]) <= eta * beta || hn <= 1e-14 * beta || !std::isfinite(hn)) break;
+      if (m + 1 < M) {
+        scale_by_inverse(n, wv, dsc_ + 2 * kMaxBasis, wv, s);
+      }
+    }
+    std::vector<double> y = back_substitute(H, M + 1, g, m_done);
+    upload(dsc_ + 3 * kMaxBasis, y.data(), m_done, s);
+    combine(n, m_done, Qo_, n, dsc_ + 3 * kMaxBasis, -1.0, x, s);
+    rn_prev = rn;
+    ++k;
+  }
+  st->newton_iters = k;
+  eng_.energy(x, x + ov, dsc_, s);
+  read_scalars(host_, dsc_, 1, s);
+  st->e_corr = host_[0];
+  st->seconds = now_s() - t0;
+}
+
+namespace {
+// Bordered Pulay system [B -1; -1 0][c; l] = [0; -1] by Gaussian elimination
+// with partial pivoting; returns false when it is numerically singular.
+bool pulay_solve(const std::vector<double>& B, int m, std::vector<double>& c) {
+  const int n = m + 1;
+  std::vector<double> A((size_t)n * n, 0.0), rhs(n, 0.0);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) A[(size_t)i * n + j] = B[(size_t)i * m + j];
+  for (int i = 0; i < m; ++i) { A[(size_t)i * n + m] = -1.0; A[(size_t)m * n + i] = -1.0; }
+  rhs[m] = -1.0;
+  double scale = 0.0;
+  for (double a : A) scale = std::max(scale, std::fabs(a));
+  for (int col = 0; col < n; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < n; ++r)
+      if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
+    if (std::fabs(A[(size_t)piv * n + col]) <= 1e-14 * scale) return false;
+    if (piv != col) {
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)piv * n + j], A[(size_t)col * n + j]);
+      std::swap(rhs[piv], rhs[col]);
+    }
+    for (int r = col + 1; r < n; ++r) {
+      const double f = A[(size_t)r * n + col] / A[(size_t)col * n + col];
+      for (int j = col; j < n; ++j) A[(size_t)r * n + j] -= f * A[(size_t)col * n + j];
+      rhs[r] -= f * rhs[col];
+    }
+  }
+  std::vector<double> sol(n);
+  for (int i = n - 1; i >= 0; --i) {
+    double acc = rhs[i];
+    for (int j = i + 1; j < n; ++j) acc -= A[(size_t)i * n + j] * sol[j];
+    sol[i] = acc / A[(size_t)i * n + i];
+  }
+  c.assign(sol.begin(), sol.begin() + m);
+  return true;
+}
+}  // namespace
+
+void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipStream_t s) {
+  const double t0 = now_s();
+  *st = SolveStats();
+  hist_.clear();
+  PNK_REQUIRE(opt.diis_size <= diis_, "fp: DIIS size exceeds the allocated history");
+  const int64_t n = n_;
+  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  if (opt.init_mp2) {
+    eng_.residual(eng_.zeros(), eng_.zeros() + ov, r_, r_ + ov, s);
+    st->n_residual++;
+    bool conv = true;
+    const int it = precond_solve(r_, x, opt.inner_rtol, 200, restart_, s, &conv);
+    st->n_afmv += it;
+    st->n_inner_iters += it;
+    axpby(n, 0.0, x, -1.0, x, s);
+  }
+  const int nd = opt.diis_size;
+  std::vector<int> slots;  // slot ids in age order (oldest first)
+  std::vector<double> Bfull((size_t)std::max(nd, 1) * std::max(nd, 1), 0.0);
+  int it = 0;
+  while (true) {
+    eng_.residual(x, x + ov, r_, r_ + ov, s);
+    st->n_residual++;
+    double rinf, rn;
+    norms(r_, &rinf, &rn, s);
+    hist_.push_back(rn);
+    hist_.push_back(rinf);
+    st->res_inf = rinf;
+    st->res_2 = rn;
+    if (!std::isfinite(rn)) { st->diverged = 1; break; }
+    if (rinf < opt.tol_inf) { st->converged = 1; break; }
+    if (it >= opt.max_iter || rn > 1e6) break;
+    if (nd == 0) {
+      jacobi_update(eng_.o(), eng_.v(), eng_.f_oo(), eng_.f_vv(), opt.level_shift, r_, x, nullptr, s);
+      ++it;
+      continue;
+    }
+    // choose the slot: next free one, else the oldest
+    int slot;
+    if ((int)slots.size() < nd) {
+      slot = (int)slots.size();
+    } else {
+      slot = slots.front();
+      slots.erase(slots.begin());
+    }
+    slots.push_back(slot);
+    double* xs = hx_ + (size_t)slot * n;
+    double* es = he_ + (size_t)slot * n;
+    copy(n, x, xs, s);
+    jacobi_update(eng_.o(), eng_.v(), eng_.f_oo(), eng_.f_vv(), opt.level_shift, r_, xs, es, s);
+    // B row of the new error vector against every stored one (slot order)
+    const int m = (int)slots.size();
+    const int mm = std::max(nd, 1);
+    multi_dot(n, nd, he_, n, es, dsc_, partials_, s);  // unused slots are ignored below
+    read_scalars(host_, dsc_, nd, s);
+    for (int q : slots) {
+      Bfull[(size_t)slot * mm + q] = host_[q];
+      Bfull[(size_t)q * mm + slot] = host_[q];
+    }
+    if (it + 1 >= opt.diis_start && m >= 2) {
+      std::vector<double> B((size_t)m * m), c;
+      for (int a = 0; a < m; ++a)
+        for (int b = 0; b < m; ++b) B[(size_t)a * m + b] = Bfull[(size_t)slots[a] * mm + slots[b]];
+      if (pulay_solve(B, m, c)) {
+        std::vector<double> cs(nd, 0.0);
+        for (int a = 0; a < m; ++a) cs[slots[a]] = c[a];
+        upload(dsc_ + 3 * kMaxBasis, cs.data(), nd, s);
+        fill(n, 0.0, x, s);
+        combine(n, nd, hx_, n, dsc_ + 3 * kMaxBasis, 1.0, x, s);
+      } else {
+        copy(n, xs, x, s);
+      }
+    } else {
+      copy(n, xs, x, s);
+    }
+    ++it;
+  }
+  st->newton_iters = it;
+  eng_.energy(x, x + ov, dsc_, s);
+  read_scalars(host_, dsc_, 1, s);
+  st->e_corr = host_[0];
+  st->seconds = now_s() - t0;
+}
+
+}  // namespace pnk

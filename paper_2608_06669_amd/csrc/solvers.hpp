@@ -1,0 +1,90 @@
+// PNK (preconditioned Newton-Krylov) and FP+DIIS solvers over an Engine.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "ccsd.hpp"
+
+namespace pnk {
+
+struct PnkOptions {
+  double tol_inf = 1e-8;
+  int max_newton = 100;
+  int m_max = 20;
+  double gamma = 0.9, alpha = 1.5, eta0 = 0.5, eta_max = 0.9;
+  double inner_rtol = 1e-12;
+  int inner_maxit = 200;
+  int inner_restart = 30;
+  Prec jvp_prec = Prec::F64;
+  bool use_fd_jvp = false;
+  bool init_mp2 = true;
+};
+
+struct FpOptions {
+  double tol_inf = 1e-8;
+  int max_iter = 500;
+  int diis_size = 8;
+  int diis_start = 2;
+  double level_shift = 0.0;
+  bool init_mp2 = true;
+  double inner_rtol = 1e-12;
+};
+
+struct SolveStats {
+  double e_corr = 0.0, res_inf = 0.0, res_2 = 0.0;
+  int converged = 0, newton_iters = 0, n_residual = 0, n_jvp = 0, n_afmv = 0, n_inner_iters = 0;
+  double seconds = 0.0;
+  int diverged = 0;  // nonfinite residual norm
+};
+
+// Krylov and history buffers for one problem size (device), plus pinned
+// host scalars. Sized once; reused across solves of the same dimensions.
+class Solver {
+ public:
+  Solver(Engine& eng, int m_max, int inner_restart, int diis_size, hipStream_t alloc_stream = nullptr,
+         bool stream_ordered = false);
+  ~Solver();
+  Solver(const Solver&) = delete;
+  Solver& operator=(const Solver&) = delete;
+
+  static size_t bytes(int64_t nvec, int m_max, int inner_restart, int diis_size);
+
+  // A_F x = b by restarted GMRES to ||b - A_F x|| <= rtol ||b||; packed
+  // vectors of length nvec. Returns the number of A_F products.
+  int precond_solve(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s,
+                    bool* converged = nullptr);
+  void solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s);
+  void solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipStream_t s);
+
+  // Residual history (norm-2, norm-inf) per outer residual evaluation.
+  const std::vector<double>& history() const { return hist_; }
+
+ private:
+  void read_scalars(double* host, const double* dev, int n, hipStream_t s);
+  void upload(double* dev, const double* src, int n, hipStream_t s);
+  // CGS2 against Q[0..m-1] (stride ldq), returns h (m entries) and ||w|| on
+  // the host; w is left orthogonalised, not normalised.
+  double orthogonalise(double* Q, int64_t ldq, int m, double* w, std::vector<double>& h, hipStream_t s);
+  void norms(const double* r, double* ninf, double* n2, hipStream_t s);
+
+  Engine& eng_;
+  int64_t n_;
+  int m_max_, restart_, diis_;
+  double* Qo_;     // outer Krylov basis (m_max + 1) x n
+  double* Qi_;     // inner Krylov basis (restart + 1) x n
+  double* r_;      // residual
+  double* ri_;     // inner GMRES residual
+  double* w_;      // work vectors
+  double* w2_;
+  double* hx_;     // DIIS amplitudes, diis x n
+  double* he_;     // DIIS error vectors, diis x n
+  double* dsc_;    // device scalars
+  double* partials_;
+  double* host_;   // pinned host scalars
+  hipStream_t alloc_stream_;
+  bool async_;
+  std::vector<double> hist_;
+};
+
+}  // namespace pnk

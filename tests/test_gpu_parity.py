@@ -1,0 +1,229 @@
+"""GPU parity: the HIP path through the C boundary against the CPU oracle.
+
+Tolerances (FP64): both sides evaluate the same polynomial in float64 with
+different summation orders, so elementwise differences are a few ulps of the
+largest intermediate; we allow 1e-10 relative to the largest residual
+component. Mixed-precision products are checked against bounds derived from
+the unit roundoff of the compute type (FP32: 2^-24, BF16: 2^-8) times the
+depth of the longest contraction.
+"""
+
+import numpy as np
+import pytest
+
+from gen import make_config, make_general, make_problem, random_amplitudes
+from oracle import ccsd, solvers
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2608_06669_amd as pk
+    pk.load()
+    assert torch.cuda.is_available(), "a GPU is required"
+    return pk
+
+
+@pytest.fixture(scope="module")
+def handle(lib):
+    h = lib.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _args(p):
+    return p.f_oo, p.f_ov, p.f_vv, p.L
+
+
+# ------------------------------------------------------------ GEMM -----
+@pytest.mark.parametrize("M,N,K", [(16, 16, 4), (33, 70, 19), (130, 257, 100), (400, 129, 300), (7, 1, 300)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
+def test_gemm_fp64_matches_float64_reference(lib, M, N, K, ta, tb):
+    g = torch.Generator(device="cpu").manual_seed(M * 1000 + N + K)
+    A = torch.randn(K, M, generator=g, dtype=torch.float64) if ta else torch.randn(M, K, generator=g, dtype=torch.float64)
+    B = torch.randn(N, K, generator=g, dtype=torch.float64) if tb else torch.randn(K, N, generator=g, dtype=torch.float64)
+    C0 = torch.randn(M, N, generator=g, dtype=torch.float64)
+    ref = 0.7 * ((A.T if ta else A) @ (B.T if tb else B)) - 0.3 * C0
+    Ad, Bd, Cd = A.cuda(), B.cuda(), C0.cuda()
+    a_str = (1, M) if ta else (K, 1)
+    b_str = (1, K) if tb else (N, 1)
+    lib.diag_gemm(Ad, Bd, Cd, a_str, b_str, (N, 1), M, N, K, alpha=0.7, beta=-0.3)
+    torch.cuda.synchronize()
+    err = (Cd.cpu() - ref).abs().max().item()
+    assert err <= 1e-12 * max(1.0, K ** 0.5) * ref.abs().max().item()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 3e-5), ("bf16", 2e-2)])
+def test_gemm_low_precision_bound(lib, prec, tol):
+    g = torch.Generator(device="cpu").manual_seed(5)
+    M, N, K = 200, 300, 512
+    A = torch.randn(M, K, generator=g, dtype=torch.float64)
+    B = torch.randn(K, N, generator=g, dtype=torch.float64)
+    ref = A @ B
+    Cd = torch.zeros(M, N, dtype=torch.float64, device="cuda")
+    lib.diag_gemm(A.cuda(), B.cuda(), Cd, (K, 1), (N, 1), (N, 1), M, N, K, prec=prec)
+    torch.cuda.synchronize()
+    # error relative to the scale sqrt(K) of a product of unit normals; the
+    # bound is K times the unit roundoff of the compute type (FP32 2^-24:
+    # rounding of the products plus float accumulation; BF16 2^-8: input
+    # rounding dominates)
+    err = (Cd.cpu() - ref).abs().max().item() / K ** 0.5
+    assert err < tol
+
+
+# -------------------------------------------------------- residual -----
+def _check_residual(handle, lib, p, t1, t2, rel=1e-10):
+    P = lib.DeviceProblem.from_problem(p)
+    r1, r2, e = handle.residual(P, dev(t1), dev(t2), energy=True)
+    o1, o2 = ccsd.residual(*_args(p), t1, t2)
+    oe = ccsd.energy(*_args(p), t1, t2)
+    scale = max(np.abs(o1).max(), np.abs(o2).max())
+    assert np.abs(host(r1) - o1).max() <= rel * scale
+    assert np.abs(host(r2) - o2).max() <= rel * scale
+    assert abs(e - oe) <= 1e-12 * max(1.0, abs(oe))
+
+
+@pytest.mark.parametrize("o,v,naux,seed", [(1, 3, 5, 1), (3, 7, 12, 2), (5, 33, 40, 3), (2, 70, 30, 4)])
+def test_residual_parity_general_gauge_with_fov(handle, lib, o, v, naux, seed):
+    """Dense non-diagonal f with f_ov != 0, random t1, t2: every term."""
+    p = make_general(o, v, naux, seed)
+    t1, t2 = random_amplitudes(o, v, seed + 50, scale=0.05)
+    _check_residual(handle, lib, p, t1, t2)
+
+
+def test_residual_parity_c1(handle, lib):
+    p = make_config("c1_canonical")
+    t1, t2 = random_amplitudes(4, 16, 7, scale=0.02)
+    _check_residual(handle, lib, p, t1, t2)
+
+
+def test_residual_parity_c2_haar(handle, lib):
+    p = make_config("c2_haar")
+    t1, t2 = random_amplitudes(10, 90, 8, scale=0.01)
+    _check_residual(handle, lib, p, t1, t2)
+
+
+def test_residual_at_zero_is_mp2_source(handle, lib):
+    p = make_problem(3, 9, 20, 9, gauge="haar")
+    P = lib.DeviceProblem.from_problem(p)
+    z1, z2 = P.zeros_t()
+    r1, r2 = handle.residual(P, z1, z2)
+    o1, o2 = ccsd.residual(*_args(p), np.zeros((3, 9)), np.zeros((3, 3, 9, 9)))
+    assert np.abs(host(r2) - o2).max() <= 1e-13 * np.abs(o2).max()
+    assert np.abs(host(r1)).max() <= 1e-13
+
+
+def test_problem_cache_sees_in_place_changes(handle, lib):
+    p = make_general(3, 6, 8, 10)
+    t1, t2 = random_amplitudes(3, 6, 11)
+    P = lib.DeviceProblem.from_problem(p)
+    a1, a2 = handle.residual(P, dev(t1), dev(t2))
+    P.L.mul_(1.5)  # same pointers, new contents
+    b1, b2 = handle.residual(P, dev(t1), dev(t2))
+    q1, q2 = ccsd.residual(p.f_oo, p.f_ov, p.f_vv, 1.5 * p.L, t1, t2)
+    assert np.abs(host(b2) - q2).max() <= 1e-10 * np.abs(q2).max()
+    assert np.abs(host(a2) - host(b2)).max() > 1e-6
+
+
+# ------------------------------------------------------------- J v -----
+@pytest.mark.parametrize("o,v,naux,seed", [(3, 7, 12, 21), (4, 16, 48, 22), (2, 40, 30, 23)])
+def test_jvp_fp64_parity(handle, lib, o, v, naux, seed):
+    p = make_general(o, v, naux, seed)
+    t1, t2 = random_amplitudes(o, v, seed + 1, scale=0.05)
+    v1, v2 = random_amplitudes(o, v, seed + 2, scale=1.0)
+    P = lib.DeviceProblem.from_problem(p)
+    y1, y2 = handle.jvp(P, dev(t1), dev(t2), dev(v1), dev(v2), prec="fp64")
+    j1, j2 = ccsd.jvp_complex_step(*_args(p), t1, t2, v1, v2)
+    scale = max(np.abs(j1).max(), np.abs(j2).max())
+    assert np.abs(host(y1) - j1).max() <= 1e-10 * scale
+    assert np.abs(host(y2) - j2).max() <= 1e-10 * scale
+
+
+@pytest.mark.parametrize("prec,rel", [("fp32", 5e-5), ("bf16", 3e-2)])
+def test_jvp_mixed_precision_bound(handle, lib, prec, rel):
+    p = make_problem(6, 40, 60, 31, gauge="haar")
+    t1, t2 = random_amplitudes(6, 40, 32, scale=0.02)
+    v1, v2 = random_amplitudes(6, 40, 33, scale=1.0)
+    P = lib.DeviceProblem.from_problem(p)
+    y1, y2 = handle.jvp(P, dev(t1), dev(t2), dev(v1), dev(v2), prec=prec)
+    j1, j2 = ccsd.jvp_complex_step(*_args(p), t1, t2, v1, v2)
+    num = np.sqrt(np.sum((host(y1) - j1) ** 2) + np.sum((host(y2) - j2) ** 2))
+    den = np.sqrt(np.sum(j1 ** 2) + np.sum(j2 ** 2))
+    assert num / den < rel
+
+
+# ------------------------------------------------------------- A_F -----
+def test_fock_apply_and_inverse(handle, lib):
+    p = make_general(3, 8, 6, 41, fov_scale=0.1)
+    x1, x2 = random_amplitudes(3, 8, 42, scale=1.0)
+    P = lib.DeviceProblem.from_problem(p)
+    y1, y2 = handle.fock_apply(P, dev(x1), dev(x2))
+    a1, a2 = solvers.fock_apply(p.f_oo, p.f_ov, p.f_vv, x1, x2)
+    assert np.abs(host(y1) - a1).max() <= 1e-13 * np.abs(a1).max()
+    assert np.abs(host(y2) - a2).max() <= 1e-13 * np.abs(a2).max()
+    s1, s2, iters, ok = handle.precond_solve(P, dev(x1), dev(x2), rtol=1e-13, maxit=300)
+    e1, e2 = solvers.fock_solve_exact(p.f_oo, p.f_ov, p.f_vv, x1, x2)
+    assert ok and iters > 0
+    assert np.abs(host(s1) - e1).max() <= 1e-10 * np.abs(e1).max()
+    assert np.abs(host(s2) - e2).max() <= 1e-10 * np.abs(e2).max()
+
+
+# --------------------------------------------------------- solvers -----
+def test_pnk_c1_matches_oracle(handle, lib):
+    p = make_config("c1_canonical")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-11)
+    a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-11)
+    assert info["status"] == "CC_OK" and ia.converged
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-9
+    assert np.abs(host(t2) - a2).max() < 1e-9
+    # the same Newton/Krylov path as the oracle
+    assert info["n_jvp"] == ia.n_jvp and info["newton_iters"] == ia.newton_iters
+
+
+def test_fp_diis_c1_matches_oracle(handle, lib):
+    p = make_config("c1_canonical")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_fp_diis(P, tol_inf=1e-10)
+    a1, a2, ia = solvers.solve_fp_diis(*_args(p), tol=1e-10)
+    assert info["status"] == "CC_OK" and ia.converged
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-9
+    # Far from DIIS's noise floor the two take the same path (near it the
+    # Pulay system is nearly singular and rounding picks different steps).
+    _, _, info6 = handle.solve_fp_diis(P, tol_inf=1e-6)
+    _, _, ia6 = solvers.solve_fp_diis(*_args(p), tol=1e-6)
+    assert info6["n_residual"] == ia6.n_residual
+
+
+def test_pnk_c2_root_is_an_oracle_root(handle, lib):
+    """FP64 PNK on the Haar-rotated workload; the GPU's amplitudes are a
+    root of the oracle's residual and give the oracle's energy."""
+    p = make_config("c2_haar")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-10)
+    assert info["status"] == "CC_OK", (info, handle.history())
+    h1, h2 = host(t1), host(t2)
+    o1, o2 = ccsd.residual(*_args(p), h1, h2)
+    assert max(np.abs(o1).max(), np.abs(o2).max()) < 1e-9
+    assert abs(ccsd.energy(*_args(p), h1, h2) - info["e_corr"]) < 1e-10
+
+
+def test_pnk_mixed_precision_energy(handle, lib):
+    p = make_problem(6, 30, 60, 51, gauge="haar")
+    P = lib.DeviceProblem.from_problem(p)
+    _, _, ref = handle.solve_pnk(P, tol_inf=1e-10)
+    for prec in ("fp32", "bf16"):
+        t1, t2, info = handle.solve_pnk(P, tol_inf=1e-8, jvp_prec=prec)
+        assert info["status"] == "CC_OK", prec
+        assert abs(info["e_corr"] - ref["e_corr"]) < 1e-6, prec

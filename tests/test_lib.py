@@ -1,0 +1,67 @@
+"""CPU checks of the C boundary: the library loads and exports every entry
+point the public header declares (no compute calls without a GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pnkcc.h")
+LIB = os.path.join(ROOT, "paper_2608_06669_amd", "libpnkcc.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"\b(cc_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_header_declares_the_solver_entry_points():
+    names = declared_functions()
+    for n in ["cc_residual", "cc_jvp", "cc_precond_solve", "cc_solve_pnk", "cc_solve_fp_diis",
+              "cc_server_create", "cc_server_submit", "cc_server_poll"]:
+        assert n in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_binding_signatures_cover_the_header():
+    from paper_2608_06669_amd import _lib
+    assert set(declared_functions()) == set(_lib.SIGNATURES)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_workspace_size_query_and_option_defaults():
+    from paper_2608_06669_amd import _lib
+    lib = _lib.load()
+    small = lib.cc_workspace_bytes(4, 16, 48, 0, 20, 30, 0)
+    assert small > 0
+    # the (ac|bd) tensor alone is nvir^4 doubles
+    assert lib.cc_workspace_bytes(20, 180, 600, 0, 20, 30, 0) > 8 * 180 ** 4
+    assert lib.cc_workspace_bytes(20, 180, 600, 2, 20, 30, 0) > lib.cc_workspace_bytes(20, 180, 600, 0, 20, 30, 0)
+    assert lib.cc_workspace_bytes(0, 16, 48, 0, 20, 30, 0) == 0
+    o = _lib.cc_pnk_opts()
+    lib.cc_pnk_opts_default(ctypes.byref(o))
+    assert (o.tol_inf, o.m_max, o.gamma, o.alpha, o.inner_restart) == (1e-8, 20, 0.9, 1.5, 30)
+    f = _lib.cc_fp_opts()
+    lib.cc_fp_opts_default(ctypes.byref(f))
+    assert (f.diis_size, f.diis_start, f.level_shift) == (8, 2, 0.0)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_null_arguments_are_rejected_without_a_device():
+    from paper_2608_06669_amd import _lib
+    lib = _lib.load()
+    assert lib.cc_residual(None, None, None, None, None, None, None, None) == _lib.CC_ERR_ARG
+    assert lib.cc_create(None, 0, 0) == _lib.CC_ERR_ARG
+    assert lib.cc_server_submit(None, None, None, None) == _lib.CC_ERR_ARG
+    assert lib.cc_diag_gemm(0, 1, 1, None, 0, 0, None, 0, 0, None, 0, 0, 1.0, 0.0, 0, None) == _lib.CC_ERR_ARG
