@@ -142,7 +142,112 @@ __global__ void scale_inv_kernel(int64_t n, const double* __restrict__ x, const 
     y[i] = x[i] * inv;
 }
 
+__device__ inline int64_t upair(int x, int y, int n) {  // x <= y
+  return (int64_t)x * n - (int64_t)x * (x - 1) / 2 + (y - x);
+}
+__device__ inline int64_t spair(int x, int y, int n) {  // x < y
+  return (int64_t)x * (n - 1) - (int64_t)x * (x - 1) / 2 + (y - x - 1);
+}
+
+__global__ void ppl_pack_w_kernel(int v, int a0, int na, const double* __restrict__ Wblk,
+                                  const int* __restrict__ pa, const int* __restrict__ pb,
+                                  const int* __restrict__ ma, const int* __restrict__ mb, double* __restrict__ S,
+                                  double* __restrict__ A) {
+  const int64_t P2 = (int64_t)v * (v + 1) / 2, P2m = (int64_t)v * (v - 1) / 2;
+  const int64_t vv = (int64_t)v * v, v3 = vv * v;
+  const int64_t p_lo = upair(a0, a0, v), p_hi = (a0 + na < v) ? upair(a0 + na, a0 + na, v) : P2;
+  const int64_t m_lo = (a0 < v - 1) ? spair(a0, a0 + 1, v) : P2m;
+  const int64_t m_hi = (a0 + na < v - 1) ? spair(a0 + na, a0 + na + 1, v) : P2m;
+  const int64_t ns = (p_hi - p_lo) * P2, nm = (m_hi - m_lo) * P2m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < ns + nm; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < ns) {
+      const int64_t p = p_lo + e / P2, q = e % P2;
+      const int a = pa[p], b = pb[p], c = pa[q], d = pb[q];
+      const double* w = Wblk + (a - a0) * v3 + (int64_t)b * vv;
+      S[p * P2 + q] = w[(int64_t)c * v + d] + w[(int64_t)d * v + c];
+    } else {
+      const int64_t f = e - ns;
+      const int64_t p = m_lo + f / P2m, q = f % P2m;
+      const int a = ma[p], b = mb[p], c = ma[q], d = mb[q];
+      const double* w = Wblk + (a - a0) * v3 + (int64_t)b * vv;
+      A[p * P2m + q] = w[(int64_t)c * v + d] - w[(int64_t)d * v + c];
+    }
+  }
+}
+
+__global__ void ppl_pack_t_kernel(int o, int v, const double* __restrict__ t2, const int* __restrict__ pa,
+                                  const int* __restrict__ pb, const int* __restrict__ ma,
+                                  const int* __restrict__ mb, double* __restrict__ Tp, double* __restrict__ Tm) {
+  const int64_t P2 = (int64_t)v * (v + 1) / 2, P2m = (int64_t)v * (v - 1) / 2;
+  const int64_t O2 = (int64_t)o * (o + 1) / 2;
+  const int64_t vv = (int64_t)v * v;
+  const int64_t np = O2 * P2, nm = O2 * P2m;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np + nm; e += (int64_t)gridDim.x * blockDim.x) {
+    const bool plus = e < np;
+    const int64_t f = plus ? e : e - np;
+    const int64_t width = plus ? P2 : P2m;
+    const int64_t ij = f / width, q = f % width;
+    // occupied pair (i <= j) from its packed index
+    int i = 0;
+    while (upair(i + 1, i + 1, o) <= ij && i + 1 < o) ++i;
+    const int j = i + (int)(ij - upair(i, i, o));
+    const double* t = t2 + ((int64_t)i * o + j) * vv;
+    if (plus) {
+      const int c = pa[q], d = pb[q];
+      Tp[f] = (c == d) ? 0.5 * t[(int64_t)c * v + c] : 0.5 * (t[(int64_t)c * v + d] + t[(int64_t)d * v + c]);
+    } else {
+      const int c = ma[q], d = mb[q];
+      Tm[f] = 0.5 * (t[(int64_t)c * v + d] - t[(int64_t)d * v + c]);
+    }
+  }
+}
+
+__global__ void ppl_unpack_kernel(int o, int v, const double* __restrict__ Rp, const double* __restrict__ Rm,
+                                  double* __restrict__ R) {
+  const int64_t P2 = (int64_t)v * (v + 1) / 2, P2m = (int64_t)v * (v - 1) / 2;
+  const int64_t vv = (int64_t)v * v;
+  const int64_t total = (int64_t)o * o * vv;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t ijx = e / vv;
+    const int ab = (int)(e % vv);
+    int i = (int)(ijx / o), j = (int)(ijx % o);
+    int a = ab / v, b = ab % v;
+    if (i > j) {  // X_ij^ab = X_ji^ba
+      const int t = i; i = j; j = t;
+      const int u = a; a = b; b = u;
+    }
+    const int64_t ij = upair(i, j, o);
+    double x;
+    if (a <= b) {
+      x = Rp[ij * P2 + upair(a, b, v)];
+      if (a < b) x += Rm[ij * P2m + spair(a, b, v)];
+    } else {
+      x = Rp[ij * P2 + upair(b, a, v)] - Rm[ij * P2m + spair(b, a, v)];
+    }
+    R[e] += x;
+  }
+}
+
 }  // namespace
+
+void ppl_pack_w(int v, int a0, int na, const double* Wblk, const int* pair_a, const int* pair_b, const int* mpair_a,
+                const int* mpair_b, double* S, double* A, hipStream_t s) {
+  const int64_t P2 = (int64_t)v * (v + 1) / 2;
+  ppl_pack_w_kernel<<<grid_for(na * (int64_t)v * P2, 32768), 256, 0, s>>>(v, a0, na, Wblk, pair_a, pair_b, mpair_a,
+                                                                          mpair_b, S, A);
+  PNK_CHECK_LAUNCH();
+}
+void ppl_pack_t(int o, int v, const double* t2, const int* pair_a, const int* pair_b, const int* mpair_a,
+                const int* mpair_b, double* Tp, double* Tm, hipStream_t s) {
+  const int64_t n = (int64_t)o * (o + 1) / 2 * ((int64_t)v * v);
+  ppl_pack_t_kernel<<<grid_for(n, 16384), 256, 0, s>>>(o, v, t2, pair_a, pair_b, mpair_a, mpair_b, Tp, Tm);
+  PNK_CHECK_LAUNCH();
+}
+void ppl_unpack_add(int o, int v, const double* Rp, const double* Rm, double* R, hipStream_t s) {
+  const int64_t n = (int64_t)o * o * v * v;
+  ppl_unpack_kernel<<<grid_for(n, 16384), 256, 0, s>>>(o, v, Rp, Rm, R);
+  PNK_CHECK_LAUNCH();
+}
 
 void assemble_fock(int o, int v, const double* f_oo, const double* f_ov, const double* f_vv, double* f,
                    hipStream_t s) {

@@ -27,6 +27,20 @@ void energy(int o, int v, const double* f_ov, const double* Itil, const double* 
 // e = -r / (D + shift) is written to `step` when it is not null
 void jacobi_update(int o, int v, const double* f_oo, const double* f_vv, double shift, const double* r, double* t,
                    double* step, hipStream_t s);
+// Symmetry-adapted particle-particle ladder. Pairs a <= b are numbered
+// row-major over the upper triangle (p), pairs a < b likewise (p'), and
+// occupied pairs i <= j likewise; pair_a/pair_b map a packed index back.
+// S[p][q] = W_ab,cd + W_ab,dc and A[p'][q'] = W_ab,cd - W_ab,dc for the
+// rows whose a lies in [a0, a0 + na); Wblk[a - a0][b][c][d] = (ac|bd).
+void ppl_pack_w(int v, int a0, int na, const double* Wblk, const int* pair_a, const int* pair_b,
+                const int* mpair_a, const int* mpair_b, double* S, double* A, hipStream_t s);
+// Tp[ij][q] = (t_ij^cd + t_ij^dc)/2 (c < d) or t_ij^cc / 2 (c = d);
+// Tm[ij][q'] = (t_ij^cd - t_ij^dc)/2, for i <= j.
+void ppl_pack_t(int o, int v, const double* t2, const int* pair_a, const int* pair_b, const int* mpair_a,
+                const int* mpair_b, double* Tp, double* Tm, hipStream_t s);
+// R[i][j][a][b] += sum_cd (ac|bd) t_ij^cd rebuilt from Rp = Tp S, Rm = Tm A.
+void ppl_unpack_add(int o, int v, const double* Rp, const double* Rm, double* R, hipStream_t s);
+
 // y = x / *s_dev (the divisor stays on the device)
 void scale_by_inverse(int64_t n, const double* x, const double* s_dev, double* y, hipStream_t s);
 

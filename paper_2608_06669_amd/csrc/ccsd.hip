@@ -127,9 +127,14 @@ void Timers::reset() {
 namespace {
 
 struct Sizes {
-  int64_t o, v, naux, np, n, ov, n2;
+  int64_t o, v, naux, np, n, ov, n2, p2, p2m, o2, wna;
   explicit Sizes(int o_, int v_, int naux_)
-      : o(o_), v(v_), naux(naux_), np(naux_ + 1), n(o_ + v_), ov((int64_t)o_ * v_), n2(ov * ov) {}
+      : o(o_), v(v_), naux(naux_), np(naux_ + 1), n(o_ + v_), ov((int64_t)o_ * v_), n2(ov * ov),
+        p2((int64_t)v_ * (v_ + 1) / 2), p2m((int64_t)v_ * (v_ - 1) / 2), o2((int64_t)o_ * (o_ + 1) / 2) {
+    // (ac|bd) is built for blocks of `wna` values of a at a time
+    const int64_t v3 = v * v * v;
+    wna = std::max<int64_t>(1, std::min<int64_t>(v, (32ll << 20) / v3));
+  }
 };
 
 // Split-K scratch: enough for 64-way splits of the largest small product.
@@ -146,9 +151,11 @@ void for_each_buffer(const Sizes& z, const EngineOptions& opt, F f, G g) {
   // constants
   f(o * o); f(ov); f(v * v); f(n * n); f(n * n); f(naux); f(naux * o * n);
   f(np * o * o); f(np * ov); f(np * ov); f(np * v * v);
-  f(v * v * v * v); f(o * v * v * v); f(n2); f(n2); f(n2); f(n2); f(n2);
-  if (opt.lowp_f32) { g(4 * v * v * v * v); g(4 * o * v * v * v); g(4 * n2); g(4 * n2); g(4 * n2); g(4 * n2); }
-  if (opt.lowp_bf16) { g(2 * v * v * v * v); g(2 * o * v * v * v); g(2 * n2); g(2 * n2); g(2 * n2); g(2 * n2); }
+  const int64_t p2 = z.p2, p2m = z.p2m, o2 = z.o2;
+  f(p2 * p2); f(p2m * p2m); f(z.wna * v * v * v); g(4 * (2 * p2 + 2 * p2m));
+  f(o * v * v * v); f(n2); f(n2); f(n2); f(n2); f(n2);
+  if (opt.lowp_f32) { g(4 * p2 * p2); g(4 * p2m * p2m); g(4 * o * v * v * v); g(4 * n2); g(4 * n2); g(4 * n2); g(4 * n2); }
+  if (opt.lowp_bf16) { g(2 * p2 * p2); g(2 * p2m * p2m); g(2 * o * v * v * v); g(2 * n2); g(2 * n2); g(2 * n2); g(2 * n2); }
   // intermediates, value and tangent
   for (int rep = 0; rep < 2; ++rep) {
     f(np * o * o); f(np * ov); f(np * v * v); f(naux); f(naux * o * o); f(naux * ov);
@@ -158,10 +165,12 @@ void for_each_buffer(const Sizes& z, const EngineOptions& opt, F f, G g) {
     f(v * v); f(o * o); f(o * o * o * o); f(o * o * o * o); f(o * o * o * o); f(o * o * ov);
     f(n2); f(n2);                       // J, Kp
     f(naux * ov); f(naux * ov); f(naux * v * v); f(o * o * ov); f(o * o * ov);
+    f(o2 * p2); f(o2 * p2m); f(o2 * p2); f(o2 * p2m);  // Tp, Tm, Rp, Rm
   }
   f(reduce_partials_size(64));
   f(ov + n2);  // zeros
   f(splitk_elems(z));
+  f(ov + n2); f(ov + n2);  // graph tangent in / out
 }
 
 }  // namespace
@@ -186,25 +195,31 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
   f_oo_ = take(O * O); f_ov_ = take(OV); f_vv_ = take(V * V); fock_ = take(N * N); h_ = take(N * N); dtr_ = take(NA);
   Lo_ = take(NA * O * N);
   Loo0.v = take(NP * O * O); Lov0.v = take(NP * OV); Lvo0.v = take(NP * OV); Lvv0.v = take(NP * V * V);
-  W.v = take(V * V * V * V); Wov.v = take(O * V * V * V);
+  p2_ = z.p2; p2m_ = z.p2m; o2_ = z.o2; wblk_na_ = (int)z.wna;
+  S.v = take(z.p2 * z.p2); Am.v = take(z.p2m * z.p2m); wblk_ = take(z.wna * V * V * V);
+  pair_a_ = arena_.take<int>(z.p2); pair_b_ = arena_.take<int>(z.p2);
+  mpair_a_ = arena_.take<int>(z.p2m); mpair_b_ = arena_.take<int>(z.p2m);
+  Wov.v = take(O * V * V * V);
   Ioovv.v = take(N2); Iovov.v = take(N2); Ix.v = take(N2); Ikldc.v = take(N2); Itil.v = take(N2);
   if (opt.lowp_f32) {
-    W.lp32 = arena_.take<float>(V * V * V * V); Wov.lp32 = arena_.take<float>(O * V * V * V);
+    S.lp32 = arena_.take<float>(z.p2 * z.p2); Am.lp32 = arena_.take<float>(z.p2m * z.p2m); Wov.lp32 = arena_.take<float>(O * V * V * V);
     Ioovv.lp32 = arena_.take<float>(N2); Iovov.lp32 = arena_.take<float>(N2);
     Ix.lp32 = arena_.take<float>(N2); Ikldc.lp32 = arena_.take<float>(N2);
   }
   if (opt.lowp_bf16) {
-    W.lp16 = arena_.take<uint16_t>(V * V * V * V); Wov.lp16 = arena_.take<uint16_t>(O * V * V * V);
+    S.lp16 = arena_.take<uint16_t>(z.p2 * z.p2); Am.lp16 = arena_.take<uint16_t>(z.p2m * z.p2m); Wov.lp16 = arena_.take<uint16_t>(O * V * V * V);
     Ioovv.lp16 = arena_.take<uint16_t>(N2); Iovov.lp16 = arena_.take<uint16_t>(N2);
     Ix.lp16 = arena_.take<uint16_t>(N2); Ikldc.lp16 = arena_.take<uint16_t>(N2);
   }
   Ten* inter[] = {&Loo, &Lvo, &Lvv, &this->D, &LooT, &LvoT, &Foo, &Fov, &Fvo, &Fvv,
                   &U, &Tail, &Tsail, &Uail, &Ukdic, &Uklca, &Uiakc, &Tmp, &X,
-                  &Gv, &Go, &Kilj, &Wkl, &Y, &Z, &J, &Kp, &Q, &QT, &LvvT, &Kilc, &KilcT};
+                  &Gv, &Go, &Kilj, &Wkl, &Y, &Z, &J, &Kp, &Q, &QT, &LvvT, &Kilc, &KilcT,
+                  &Tp, &Tm, &Rp, &Rm};
   const int64_t isz[] = {NP * O * O, NP * OV, NP * V * V, NA, NA * O * O, NA * OV, O * O, OV, OV, V * V,
                          N2, N2, N2, N2, N2, N2, N2, N2, N2,
                          V * V, O * O, O * O * O * O, O * O * O * O, O * O * O * O, O * O * OV, N2, N2,
-                         NA * OV, NA * OV, NA * V * V, O * O * OV, O * O * OV};
+                         NA * OV, NA * OV, NA * V * V, O * O * OV, O * O * OV,
+                         z.o2 * z.p2, z.o2 * z.p2m, z.o2 * z.p2, z.o2 * z.p2m};
   static_assert(sizeof(inter) / sizeof(inter[0]) == sizeof(isz) / sizeof(isz[0]), "buffer table");
   for (int rep = 0; rep < 2; ++rep)
     for (size_t k = 0; k < sizeof(isz) / sizeof(isz[0]); ++k) {
@@ -216,11 +231,68 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
   zeros_ = take(OV + N2);
   ws_elems_ = splitk_elems(z);
   ws_ = take(ws_elems_);
+  tin_ = take(OV + N2);
+  tout_ = take(OV + N2);
   T1.var = T2.var = R1.var = R2.var = true;
   (void)z;
 }
 
-Engine::~Engine() = default;
+Engine::~Engine() {
+  for (GraphSlot* g : {&res_slot_, &jvp_slot_[0], &jvp_slot_[1], &jvp_slot_[2]})
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (cap_) (void)hipStreamDestroy(cap_);
+}
+
+// Record run(m) on a private stream (stream capture does not execute) and
+// instantiate it. Returns false (and leaves the slot empty) if the runtime
+// refuses; the caller then runs eagerly.
+bool Engine::capture(Mode m, GraphSlot* slot) {
+  if (!cap_ && hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    cap_ = nullptr;
+    return false;
+  }
+  hipStream_t saved = s_;
+  Timers* tm = timers_;
+  timers_ = nullptr;
+  s_ = cap_;
+  hipGraph_t g = nullptr;
+  bool ok = false;
+  if (hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    try {
+      run(m);
+    } catch (...) {
+    }
+    if (hipStreamEndCapture(cap_, &g) == hipSuccess && g &&
+        hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0) == hipSuccess)
+      ok = true;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  (void)hipGetLastError();
+  if (!ok) slot->exec = nullptr;
+  s_ = saved;
+  timers_ = tm;
+  mode_ = Mode::Value;
+  return ok;
+}
+
+// True when slot holds a graph for these buffers. A graph is recorded on the
+// second consecutive call with the same key (so one-off evaluations, such as
+// the residual at t = 0, stay eager).
+bool Engine::graph_ready(GraphSlot* slot, const void* k0, const void* k1, const void* k2, const void* k3, Mode m) {
+  if (!use_graphs_) return false;
+  const bool same = slot->key[0] == k0 && slot->key[1] == k1 && slot->key[2] == k2 && slot->key[3] == k3;
+  if (same && slot->exec) return true;
+  if (!same) {
+    if (slot->exec) (void)hipGraphExecDestroy(slot->exec);
+    slot->exec = nullptr;
+    slot->key[0] = k0; slot->key[1] = k1; slot->key[2] = k2; slot->key[3] = k3;
+    slot->hits = 1;
+    return false;
+  }
+  if (++slot->hits < 2) return false;
+  return capture(m, slot);
+}
 
 // ---------------------------------------------------- op primitives -----
 
@@ -319,6 +391,16 @@ void Engine::lin_pairsym(const Ten& Xs, const Ten& R) {
   else pair_symmetrize_add(o_, v_, Xs.d, 1.0, R.d, s_);
 }
 
+void Engine::lin_ppl_pack(const Ten& t2, const Ten& tp, const Ten& tm) {
+  if (mode_ == Mode::Value) ppl_pack_t(o_, v_, t2.v, pair_a_, pair_b_, mpair_a_, mpair_b_, tp.v, tm.v, s_);
+  else ppl_pack_t(o_, v_, t2.d, pair_a_, pair_b_, mpair_a_, mpair_b_, tp.d, tm.d, s_);
+}
+
+void Engine::lin_ppl_unpack(const Ten& rp, const Ten& rm, const Ten& R) {
+  if (mode_ == Mode::Value) ppl_unpack_add(o_, v_, rp.v, rm.v, R.v, s_);
+  else ppl_unpack_add(o_, v_, rp.d, rm.d, R.d, s_);
+}
+
 // ------------------------------------------------------------ prepare ---
 
 void Engine::prepare(const ProblemView& p, hipStream_t s) {
@@ -338,14 +420,34 @@ void Engine::prepare(const ProblemView& p, hipStream_t s) {
   extract_occ_rows(naux, o, n, p.L, Lo_, s);
   gemm64(with_ws(gd(n, n, naux * o, 1, n, n, 1, n, 1, 1.0, 1.0)), Lo_, Lo_, h_, s);
   extract_blocks(naux, o, v, p.L, h_, Loo0.v, Lov0.v, Lvo0.v, Lvv0.v, s);
-  // W[a][b][c][d] = (ac|bd): batch (b0 = b, b1 = a), X_ab[c][d] = sum_P L_ac L_bd
+  // symmetry-adapted (ac|bd): pair tables, then blocks of a at a time:
+  // Wblk[a - a0][b][c][d] = sum_P L_ac L_bd (batch b0 = b, b1 = a - a0),
+  // packed into S (a <= b, c <= d) and A (a < b, c < d)
   {
-    GemmDesc d = gd(v, v, naux, 1, vv, vv, 1, v, 1);
-    d.nb0 = v; d.nb1 = v;
-    d.a_b0 = 0; d.a_b1 = v;
-    d.b_b0 = v; d.b_b1 = 0;
-    d.c_b0 = vv; d.c_b1 = vv * v;
-    gemm64(with_ws(d), Lvv0.v, Lvv0.v, W.v, s);
+    std::vector<int> pa(p2_), pb(p2_), ma(std::max<int64_t>(p2m_, 1)), mb(std::max<int64_t>(p2m_, 1));
+    int64_t k = 0, km = 0;
+    for (int a = 0; a < v; ++a)
+      for (int b = a; b < v; ++b) {
+        pa[k] = a; pb[k] = b; ++k;
+        if (b > a) { ma[km] = a; mb[km] = b; ++km; }
+      }
+    PNK_HIP(hipMemcpyAsync(pair_a_, pa.data(), p2_ * sizeof(int), hipMemcpyHostToDevice, s));
+    PNK_HIP(hipMemcpyAsync(pair_b_, pb.data(), p2_ * sizeof(int), hipMemcpyHostToDevice, s));
+    if (p2m_ > 0) {
+      PNK_HIP(hipMemcpyAsync(mpair_a_, ma.data(), p2m_ * sizeof(int), hipMemcpyHostToDevice, s));
+      PNK_HIP(hipMemcpyAsync(mpair_b_, mb.data(), p2m_ * sizeof(int), hipMemcpyHostToDevice, s));
+    }
+    PNK_HIP(hipStreamSynchronize(s));  // host tables go out of scope
+    for (int a0 = 0; a0 < v; a0 += wblk_na_) {
+      const int na = std::min(wblk_na_, v - a0);
+      GemmDesc d = gd(v, v, naux, 1, vv, vv, 1, v, 1);
+      d.nb0 = v; d.nb1 = na;
+      d.a_b0 = 0; d.a_b1 = v;
+      d.b_b0 = v; d.b_b1 = 0;
+      d.c_b0 = vv; d.c_b1 = vv * v;
+      gemm64(with_ws(d), Lvv0.v + (int64_t)a0 * v, Lvv0.v, wblk_, s);
+      ppl_pack_w(v, a0, na, wblk_, pair_a_, pair_b_, mpair_a_, mpair_b_, S.v, Am.v, s);
+    }
   }
   // Wov[k][b][c][d] = (kc|bd)
   {
@@ -377,9 +479,9 @@ void Engine::prepare(const ProblemView& p, hipStream_t s) {
     permute4(Ioovv.v, Itil.v, dims2, pm2, -1.0, 0.0, s);
     axpby(n2_, 2.0, Ioovv.v, 1.0, Itil.v, s);
   }
-  Ten* lows[] = {&W, &Wov, &Ioovv, &Iovov, &Ix, &Ikldc};
-  const int64_t lsz[] = {vv * vv, (int64_t)o * v * vv, n2_, n2_, n2_, n2_};
-  for (int k = 0; k < 6; ++k) {
+  Ten* lows[] = {&S, &Am, &Wov, &Ioovv, &Iovov, &Ix, &Ikldc};
+  const int64_t lsz[] = {p2_ * p2_, p2m_ * p2m_, (int64_t)o * v * vv, n2_, n2_, n2_, n2_};
+  for (int k = 0; k < 7; ++k) {
     if (lows[k]->lp32) cast_f64_to_f32(lsz[k], lows[k]->v, (float*)lows[k]->lp32, s);
     if (lows[k]->lp16) cast_f64_to_bf16(lsz[k], lows[k]->v, (uint16_t*)lows[k]->lp16, s);
   }
@@ -439,10 +541,20 @@ void Engine::run(Mode m) {
   // ---- r2 = (ai|bj)~ ----
   mm(gd(OV, OV, naux, 1, ov, ov, 1, ov, 1), Lvo, Lvo, Tmp);        // [(a,i)][(b,j)]
   perm(Tmp, R2, v, o, v, o, 1, 3, 0, 2, 1.0, 0.0);
-  // ---- particle-particle ladder with W_vvvv ----
-  if (timers_) timers_->begin(kTimerPPL, s_);
-  mm(gd(OO, VV, VV, vv, 1, vv, 1, vv, 1, 1.0, 1.0), T2, W, R2);
-  if (timers_) timers_->end(kTimerPPL, s_);
+  // ---- particle-particle ladder, symmetry-adapted: for i <= j and the
+  // (anti)symmetric combinations of c,d, R+ = T+ S, R- = T- A ----
+  lin_ppl_pack(T2, Tp, Tm);
+  {
+    // S and A are symmetric matrices: read them along the contiguous index
+    // the compute type stages best (n for FP64/FP32, k for BF16)
+    const bool kc = mode_ == Mode::Tangent && jprec_ == Prec::BF16;
+    const int P2 = (int)p2_, P2m = (int)p2m_, O2 = (int)o2_;
+    if (timers_) timers_->begin(kTimerPPL, s_);
+    mm(gd(O2, P2, P2, p2_, 1, kc ? 1 : p2_, kc ? p2_ : 1, p2_, 1), Tp, S, Rp);
+    if (P2m > 0) mm(gd(O2, P2m, P2m, p2m_, 1, kc ? 1 : p2m_, kc ? p2m_ : 1, p2m_, 1), Tm, Am, Rm);
+    if (timers_) timers_->end(kTimerPPL, s_);
+  }
+  lin_ppl_unpack(Rp, Rm, R2);
   // ---- hole-hole ladder ----
   mm(gd(OO, OO, naux, 1, oo, oo, 1, oo, 1), Loo, Loo, Kilj);       // [(k,i)][(l,j)]
   perm(Kilj, Wkl, o, o, o, o, 0, 2, 1, 3, 1.0, 0.0);               // [(k,l)][(i,j)]
@@ -498,7 +610,8 @@ void Engine::residual(const double* t1, const double* t2, double* r1, double* r2
   R1.v = r1;
   R2.v = r2;
   if (timers_) timers_->begin(kTimerResidual, s);
-  run(Mode::Value);
+  if (graph_ready(&res_slot_, t1, t2, r1, r2, Mode::Value)) PNK_HIP(hipGraphLaunch(res_slot_.exec, s));
+  else run(Mode::Value);
   if (timers_) timers_->end(kTimerResidual, s);
 }
 
@@ -506,12 +619,27 @@ void Engine::jvp(const double* x1, const double* x2, double* y1, double* y2, Pre
   PNK_REQUIRE(T1.v && T2.v, "jvp before any residual evaluation");
   s_ = s;
   jprec_ = prec;
-  T1.d = const_cast<double*>(x1);
-  T2.d = const_cast<double*>(x2);
-  R1.d = y1;
-  R2.d = y2;
   if (timers_) timers_->begin(kTimerJvp, s);
-  run(Mode::Tangent);
+  // graphs run on fixed tangent buffers: copy in, replay, copy out
+  T1.d = tin_;
+  T2.d = tin_ + ov_;
+  R1.d = tout_;
+  R2.d = tout_ + ov_;
+  GraphSlot* slot = &jvp_slot_[(int)prec];
+  if (graph_ready(slot, T1.v, T2.v, nullptr, nullptr, Mode::Tangent)) {
+    jprec_ = prec;
+    PNK_HIP(hipMemcpyAsync(tin_, x1, ov_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PNK_HIP(hipMemcpyAsync(tin_ + ov_, x2, n2_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PNK_HIP(hipGraphLaunch(slot->exec, s));
+    PNK_HIP(hipMemcpyAsync(y1, tout_, ov_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    PNK_HIP(hipMemcpyAsync(y2, tout_ + ov_, n2_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+  } else {
+    T1.d = const_cast<double*>(x1);
+    T2.d = const_cast<double*>(x2);
+    R1.d = y1;
+    R2.d = y2;
+    run(Mode::Tangent);
+  }
   if (timers_) timers_->end(kTimerJvp, s);
   mode_ = Mode::Value;
   jprec_ = Prec::F64;

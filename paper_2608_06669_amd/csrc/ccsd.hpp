@@ -113,6 +113,9 @@ class Engine {
   double* scratch_partials() { return partials_; }
   const double* zeros() const { return zeros_; }
   void set_timers(Timers* t) { timers_ = t; }
+  // Replay recorded HIP graphs for repeated residual / J v evaluations with
+  // the same buffers (default on).
+  void set_graphs(bool on) { use_graphs_ = on; }
   Timers* timers() const { return timers_; }
 
  private:
@@ -133,6 +136,8 @@ class Engine {
   void lin_axpby(int64_t n, double a, const Ten& x, double b, const Ten& y);
   void lin_trace(const Ten& in, int nslices, const Ten& out);
   void lin_pairsym(const Ten& X, const Ten& R);
+  void lin_ppl_pack(const Ten& t2, const Ten& Tp, const Ten& Tm);
+  void lin_ppl_unpack(const Ten& Rp, const Ten& Rm, const Ten& R);
   void operand(const Ten& t, bool tangent, const void** p, Prec* prec) const;
 
   int o_, v_, naux_, np_;
@@ -146,16 +151,34 @@ class Engine {
   // problem constants
   double *f_oo_, *f_ov_, *f_vv_, *fock_, *h_, *dtr_, *Lo_;
   bool fov_zero_ = true;
-  Ten Loo0, Lov0, Lvo0, Lvv0, W, Wov, Ioovv, Iovov, Ix, Ikldc, Itil;
+  Ten Loo0, Lov0, Lvo0, Lvv0, S, Am, Wov, Ioovv, Iovov, Ix, Ikldc, Itil;
+  // symmetry-adapted ladder: pair tables and the (ac|bd) block staging area
+  int *pair_a_, *pair_b_, *mpair_a_, *mpair_b_;
+  double* wblk_;
+  int wblk_na_;
+  int64_t p2_, p2m_, o2_;
   // amplitudes and outputs
   Ten T1, T2, R1, R2;
   // intermediates
   Ten Loo, Lvo, Lvv, D, LooT, LvoT, Foo, Fov, Fvo, Fvv;
   Ten U, Tail, Tsail, Uail, Ukdic, Uklca, Uiakc;
   Ten Tmp, X, Gv, Go, Kilj, Wkl, Y, Z, J, Kp, Q, QT, LvvT, Kilc, KilcT;
+  Ten Tp, Tm, Rp, Rm;
   double* partials_;
   double* zeros_;  // zero t-vector for the residual at t = 0
   Timers* timers_ = nullptr;
+  // recorded graphs of the residual (value) and J v (tangent, per precision)
+  struct GraphSlot {
+    hipGraphExec_t exec = nullptr;
+    const void* key[4] = {nullptr, nullptr, nullptr, nullptr};
+    int hits = 0;
+  };
+  GraphSlot res_slot_, jvp_slot_[3];
+  bool use_graphs_ = true;
+  hipStream_t cap_ = nullptr;
+  double *tin_ = nullptr, *tout_ = nullptr;  // fixed tangent input / output
+  bool capture(Mode m, GraphSlot* slot);
+  bool graph_ready(GraphSlot* slot, const void* k0, const void* k1, const void* k2, const void* k3, Mode m);
   double* ws_ = nullptr;  // split-K partial sums
   int64_t ws_elems_ = 0;
   GemmDesc with_ws(GemmDesc d) const {

@@ -2,23 +2,34 @@
 //
 // One workgroup = 4 wavefronts of 64 lanes computes a BM x BN tile of C.
 // The waves form a WGM x WGN grid; each wave owns (BM/WGM) x (BN/WGN)
-// outputs as a grid of 16 x 16 matrix-core tiles kept in registers for the
-// whole K loop. A and B tiles of depth BK are staged through LDS: the next
-// tile's global loads are issued before the current tile's MFMAs so their
-// latency hides behind the matrix-core work. Operands are converted to the
-// compute type as they are written to LDS, so FP64 tensors can feed the
-// FP32 and BF16 products without a separate cast pass.
+// outputs as a grid of matrix-core instruction tiles held in registers for
+// the whole K loop. A and B panels of depth BK are staged through two LDS
+// buffers: while the matrix cores work on one buffer, the next panel's
+// global loads are in flight and are then written to the other buffer, so
+// each K step costs one barrier. Global loads are 16-byte vectors along the
+// operand's contiguous index whenever strides and alignment allow. Operands
+// are converted to the compute type as they are written to LDS, so FP64
+// tensors feed the FP32 and BF16 products without a separate cast pass.
 //
-// Matrix-core operand layouts (64 lanes, lane l):
-//   f64 / f32 16x16x4:  A[i][k] at i = l%16, k = l/16;  B[k][j] at j = l%16
-//   bf16 16x16x32:      A[i][k..k+7] at i = l%16, k = 8*(l/16); B likewise
-//   D f32 / bf16:       D[i][j] at j = l%16, i = 4*(l/16) + r, r = 0..3
-//   D f64:              D[i][j] at j = l%16, i = l/16 + 4*r,   r = 0..3
+// Matrix-core instructions and operand layouts (64 lanes, lane l):
+//   f64  4x4x4 (4 blocks), used as one 4 x 16 x 4 product:
+//        A[i][k] at i = l%4, k = l/16 (the same for the 4 blocks);
+//        B[k][j] at j = l%16, k = l/16;  D[i][j] at i = l/16, j = l%16.
+//        On gfx950 this instruction runs at the full FP64 matrix rate,
+//        while the 16x16x4 f64 instruction reaches about two thirds of it.
+//   f32  16x16x4:  A[i][k] at i = l%16, k = l/16;  B[k][j] at j = l%16;
+//        D[i][j] at j = l%16, i = 4*(l/16) + r, r = 0..3
+//   bf16 16x16x32: A[i][k..k+7] at i = l%16, k = 8*(l/16); B likewise;
+//        D as f32
 //
 // Workgroup order: tiles of one output column block (same B panel) are
 // consecutive and are placed on the same XCD (hardware dispatches block ids
 // round-robin over the 8 XCDs), so the B panel is fetched from HBM once and
 // re-read by its neighbours from that XCD's L2.
+//
+// Products with too few output tiles to fill the GPU split the contraction
+// (split-K); partial sums are added afterwards in a fixed order, so results
+// never depend on timing.
 
 #include "gemm.hpp"
 
@@ -38,7 +49,6 @@ __device__ inline uint16_t f32_to_bf16(float f) {
   u += 0x7fffu + ((u >> 16) & 1u);
   return (uint16_t)(u >> 16);
 }
-__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
 // Convert one stored element to the LDS (compute) representation.
 template <typename S, typename L> __device__ inline L to_lds(S x);
@@ -54,43 +64,35 @@ template <> __device__ inline double from_acc<double>(double x) { return x; }
 template <> __device__ inline float from_acc<float>(double x) { return (float)x; }
 template <typename C> __device__ inline double load_c(const C* p) { return (double)*p; }
 
+// TM x TN: output tile of one instruction; NACC: accumulator values per lane
 struct MmaF64 {
   using L = double;   // LDS element
-  using Acc = d4;
-  static constexpr int KSTEP = 4;
+  using Acc = double;
+  static constexpr int KSTEP = 4, TM = 4, TN = 16, NACC = 1;
   static constexpr bool KCONTIG_LDS = false;  // LDS laid out [k][m]
 };
 struct MmaF32 {
   using L = float;
   using Acc = f4;
-  static constexpr int KSTEP = 4;
+  static constexpr int KSTEP = 4, TM = 16, TN = 16, NACC = 4;
   static constexpr bool KCONTIG_LDS = false;
 };
 struct MmaBF16 {
   using L = uint16_t;
   using Acc = f4;
-  static constexpr int KSTEP = 32;
+  static constexpr int KSTEP = 32, TM = 16, TN = 16, NACC = 4;
   static constexpr bool KCONTIG_LDS = true;  // LDS laid out [m][k]
 };
+template <class Acc> __device__ inline double acc_get(const Acc& a, int r) { return (double)a[r]; }
+template <> __device__ inline double acc_get<double>(const double& a, int) { return a; }
 
-template <class Mma, int BM, int BN, int BK, int WGM>
-struct Tile {
-  static constexpr int WGN = 4 / WGM;
-  static constexpr int WTM = BM / WGM;  // rows per wave
-  static constexpr int WTN = BN / WGN;
-  static constexpr int TMI = WTM / 16;
-  static constexpr int TNI = WTN / 16;
-  static_assert(WTM % 16 == 0 && WTN % 16 == 0, "wave tile must be 16-aligned");
-  static_assert(BK % Mma::KSTEP == 0, "BK must be a multiple of the MFMA depth");
-  // LDS geometry: [BK][BM+PAD] or [BM][BK+PADK]
-  static constexpr int PAD = 1;
-  static constexpr int PADK = 8;
-  static constexpr int A_LDS = Mma::KCONTIG_LDS ? BM * (BK + PADK) : BK * (BM + PAD);
-  static constexpr int B_LDS = Mma::KCONTIG_LDS ? BN * (BK + PADK) : BK * (BN + PAD);
-  static constexpr int EA = BM * BK / 256;  // A elements loaded per thread
-  static constexpr int EB = BK * BN / 256;
-  static_assert((BM * BK) % 256 == 0 && (BK * BN) % 256 == 0, "tile load split");
-};
+constexpr int kPad = 1;   // [k][rows + kPad]
+constexpr int kPadK = 8;  // [rows][k + kPadK]
+
+template <class Mma, int ROWS, int BK>
+constexpr int lds_elems() {
+  return Mma::KCONTIG_LDS ? ROWS * (BK + kPadK) : BK * (ROWS + kPad);
+}
 
 struct KArgs {
   int M, N, K, nb0;
@@ -98,6 +100,7 @@ struct KArgs {
   double* ws;          // partial sums [split][batch][M][N] when splits > 1
   int nbtot;
   int tiles_m, tiles_n;
+  int a_vec, b_vec;    // 16-byte vector loads allowed
   const void* A;
   int64_t a_m, a_k, a_b0, a_b1;
   const void* B;
@@ -107,21 +110,88 @@ struct KArgs {
   double alpha, beta;
 };
 
+// Loads a ROWS x BK panel (ROWS = BM for A, BN for B) into registers and
+// writes it to one LDS buffer. KC: the operand is contiguous along k.
+template <class Mma, typename T, int ROWS, int BK, bool KC>
+struct Panel {
+  using L = typename Mma::L;
+  static constexpr int V = 16 / (int)sizeof(T);
+  static constexpr int NVEC = ROWS * BK / V;
+  static constexpr int PER = (NVEC + 255) / 256;
+  static_assert(ROWS % V == 0 && BK % V == 0, "panel must split into vectors");
+  T r[PER * V];
+
+  __device__ inline void coords(int q, int* row, int* kk) const {
+    if (KC) { *row = q / (BK / V); *kk = (q % (BK / V)) * V; }
+    else { *kk = q / (ROWS / V); *row = (q % (ROWS / V)) * V; }
+  }
+
+  __device__ inline void load(const T* __restrict__ g, int64_t s_row, int64_t s_k, int row0, int rows, int k0,
+                              int kend, bool vec_ok, int tid) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int q = tid + e * 256;
+      if (q >= NVEC) break;
+      int row, kk;
+      coords(q, &row, &kk);
+      const int gr = row0 + row, gk = k0 + kk;
+      bool full;
+      if (KC) full = vec_ok && gr < rows && gk + V <= kend;
+      else full = vec_ok && gr + V <= rows && gk < kend;
+      if (full) {
+        const T* p = g + (int64_t)gr * s_row + (int64_t)gk * s_k;
+        const uint4 v = *reinterpret_cast<const uint4*>(p);
+        *reinterpret_cast<uint4*>(&r[e * V]) = v;
+      } else {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int rr = KC ? gr : gr + u;
+          const int kx = KC ? gk + u : gk;
+          r[e * V + u] = (rr < rows && kx < kend) ? g[(int64_t)rr * s_row + (int64_t)kx * s_k] : T(0);
+        }
+      }
+    }
+  }
+
+  __device__ inline void store(L* __restrict__ lds, int tid) const {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int q = tid + e * 256;
+      if (q >= NVEC) break;
+      int row, kk;
+      coords(q, &row, &kk);
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int rr = KC ? row : row + u;
+        const int kx = KC ? kk + u : kk;
+        const L x = to_lds<T, L>(r[e * V + u]);
+        if constexpr (Mma::KCONTIG_LDS) lds[rr * (BK + kPadK) + kx] = x;
+        else lds[kx * (ROWS + kPad) + rr] = x;
+      }
+    }
+  }
+};
+
 template <class Mma, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WGM, bool A_KC, bool B_KC>
 __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
-  using T = Tile<Mma, BM, BN, BK, WGM>;
   using L = typename Mma::L;
   using Acc = typename Mma::Acc;
-  __shared__ __attribute__((aligned(16))) L As[T::A_LDS];
-  __shared__ __attribute__((aligned(16))) L Bs[T::B_LDS];
+  constexpr int WGN = 4 / WGM;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int TMI = WTM / Mma::TM, TNI = WTN / Mma::TN;
+  static_assert(WTM % Mma::TM == 0 && WTN % Mma::TN == 0, "wave tile must split into instruction tiles");
+  static_assert(BK % Mma::KSTEP == 0, "BK must be a multiple of the MFMA depth");
+  constexpr int ALDS = lds_elems<Mma, BM, BK>();
+  constexpr int BLDS = lds_elems<Mma, BN, BK>();
+  __shared__ __attribute__((aligned(16))) L As[2][ALDS];
+  __shared__ __attribute__((aligned(16))) L Bs[2][BLDS];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave / T::WGN;
-  const int wn = wave % T::WGN;
+  const int wm = wave / WGN;
+  const int wn = wave % WGN;
 
-  // XCD-aware tile order (see header comment)
   const int ntiles = p.tiles_m * p.tiles_n;
   int bid = blockIdx.x;
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
@@ -140,128 +210,105 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   const TB* __restrict__ Bg = (const TB*)p.B + b0 * p.b_b0 + b1 * p.b_b1;
   TC* __restrict__ Cg = (TC*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
 
-  Acc acc[T::TMI][T::TNI];
+  Acc acc[TMI][TNI];
 #pragma unroll
-  for (int i = 0; i < T::TMI; ++i)
+  for (int i = 0; i < TMI; ++i)
 #pragma unroll
-    for (int j = 0; j < T::TNI; ++j) acc[i][j] = Acc{0, 0, 0, 0};
+    for (int j = 0; j < TNI; ++j) acc[i][j] = Acc{};
 
-  TA ra[T::EA];
-  TB rb[T::EB];
-
-  auto load_tiles = [&](int k0) {
-#pragma unroll
-    for (int e = 0; e < T::EA; ++e) {
-      const int idx = tid + e * 256;
-      const int m = A_KC ? idx / BK : idx % BM;
-      const int k = A_KC ? idx % BK : idx / BM;
-      const int gm = m0 + m, gk = k0 + k;
-      ra[e] = (gm < p.M && gk < kend) ? Ag[gm * p.a_m + gk * p.a_k] : TA(0);
-    }
-#pragma unroll
-    for (int e = 0; e < T::EB; ++e) {
-      const int idx = tid + e * 256;
-      const int n = B_KC ? idx / BK : idx % BN;
-      const int k = B_KC ? idx % BK : idx / BN;
-      const int gn = n0 + n, gk = k0 + k;
-      rb[e] = (gn < p.N && gk < kend) ? Bg[gk * p.b_k + gn * p.b_n] : TB(0);
-    }
-  };
-  auto store_tiles = [&]() {
-#pragma unroll
-    for (int e = 0; e < T::EA; ++e) {
-      const int idx = tid + e * 256;
-      const int m = A_KC ? idx / BK : idx % BM;
-      const int k = A_KC ? idx % BK : idx / BM;
-      const L x = to_lds<TA, L>(ra[e]);
-      if constexpr (Mma::KCONTIG_LDS) As[m * (BK + T::PADK) + k] = x;
-      else As[k * (BM + T::PAD) + m] = x;
-    }
-#pragma unroll
-    for (int e = 0; e < T::EB; ++e) {
-      const int idx = tid + e * 256;
-      const int n = B_KC ? idx / BK : idx % BN;
-      const int k = B_KC ? idx % BK : idx / BN;
-      const L x = to_lds<TB, L>(rb[e]);
-      if constexpr (Mma::KCONTIG_LDS) Bs[n * (BK + T::PADK) + k] = x;
-      else Bs[k * (BN + T::PAD) + n] = x;
-    }
-  };
+  Panel<Mma, TA, BM, BK, A_KC> pa;
+  Panel<Mma, TB, BN, BK, B_KC> pb;
+  const bool avec = p.a_vec != 0, bvec = p.b_vec != 0;
+  const int64_t a_row = p.a_m, a_kk = p.a_k, b_row = p.b_n, b_kk = p.b_k;
 
   const int nk = (kend - kbeg + BK - 1) / BK;
   if (nk > 0) {
-    load_tiles(kbeg);
-    store_tiles();
+    pa.load(Ag, a_row, a_kk, m0, p.M, kbeg, kend, avec, tid);
+    pb.load(Bg, b_row, b_kk, n0, p.N, kbeg, kend, bvec, tid);
+    pa.store(As[0], tid);
+    pb.store(Bs[0], tid);
     __syncthreads();
   }
   for (int kt = 0; kt < nk; ++kt) {
-    if (kt + 1 < nk) load_tiles(kbeg + (kt + 1) * BK);
+    const int cur = kt & 1;
+    if (kt + 1 < nk) {
+      pa.load(Ag, a_row, a_kk, m0, p.M, kbeg + (kt + 1) * BK, kend, avec, tid);
+      pb.load(Bg, b_row, b_kk, n0, p.N, kbeg + (kt + 1) * BK, kend, bvec, tid);
+    }
+    const L* Ac = As[cur];
+    const L* Bc = Bs[cur];
 #pragma unroll
     for (int ks = 0; ks < BK; ks += Mma::KSTEP) {
       if constexpr (Mma::KCONTIG_LDS) {
         const int kk = ks + 8 * (lane >> 4);
-        bf8 af[T::TMI], bfr[T::TNI];
+        bf8 af[TMI], bfr[TNI];
 #pragma unroll
-        for (int i = 0; i < T::TMI; ++i) {
-          const int m = wm * T::WTM + i * 16 + (lane & 15);
-          u16x8 v = *reinterpret_cast<const u16x8*>(&As[m * (BK + T::PADK) + kk]);
-          af[i] = __builtin_bit_cast(bf8, v);
+        for (int i = 0; i < TMI; ++i) {
+          const int m = wm * WTM + i * 16 + (lane & 15);
+          af[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(&Ac[m * (BK + kPadK) + kk]));
         }
 #pragma unroll
-        for (int j = 0; j < T::TNI; ++j) {
-          const int n = wn * T::WTN + j * 16 + (lane & 15);
-          u16x8 v = *reinterpret_cast<const u16x8*>(&Bs[n * (BK + T::PADK) + kk]);
-          bfr[j] = __builtin_bit_cast(bf8, v);
+        for (int j = 0; j < TNI; ++j) {
+          const int n = wn * WTN + j * 16 + (lane & 15);
+          bfr[j] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(&Bc[n * (BK + kPadK) + kk]));
         }
 #pragma unroll
-        for (int i = 0; i < T::TMI; ++i)
+        for (int i = 0; i < TMI; ++i)
 #pragma unroll
-          for (int j = 0; j < T::TNI; ++j)
+          for (int j = 0; j < TNI; ++j)
             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+      } else if constexpr (sizeof(L) == 8) {
+        const int kk = ks + (lane >> 4);
+        double af[TMI], bfr[TNI];
+#pragma unroll
+        for (int i = 0; i < TMI; ++i) af[i] = Ac[kk * (BM + kPad) + wm * WTM + i * 4 + (lane & 3)];
+#pragma unroll
+        for (int j = 0; j < TNI; ++j) bfr[j] = Bc[kk * (BN + kPad) + wn * WTN + j * 16 + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < TMI; ++i)
+#pragma unroll
+          for (int j = 0; j < TNI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[i], bfr[j], acc[i][j], 0, 0, 0);
       } else {
         const int kk = ks + (lane >> 4);
-        L af[T::TMI], bfr[T::TNI];
+        L af[TMI], bfr[TNI];
 #pragma unroll
-        for (int i = 0; i < T::TMI; ++i) af[i] = As[kk * (BM + T::PAD) + wm * T::WTM + i * 16 + (lane & 15)];
+        for (int i = 0; i < TMI; ++i) af[i] = Ac[kk * (BM + kPad) + wm * WTM + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < T::TNI; ++j) bfr[j] = Bs[kk * (BN + T::PAD) + wn * T::WTN + j * 16 + (lane & 15)];
+        for (int j = 0; j < TNI; ++j) bfr[j] = Bc[kk * (BN + kPad) + wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
-        for (int i = 0; i < T::TMI; ++i)
+        for (int i = 0; i < TMI; ++i)
 #pragma unroll
-          for (int j = 0; j < T::TNI; ++j) {
-            if constexpr (sizeof(L) == 8)
-              acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bfr[j], acc[i][j], 0, 0, 0);
-            else
-              acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
-          }
+          for (int j = 0; j < TNI; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bfr[j], acc[i][j], 0, 0, 0);
       }
     }
     if (kt + 1 < nk) {
-      __syncthreads();
-      store_tiles();
-      __syncthreads();
+      // the other buffer was last read before the previous barrier
+      pa.store(As[cur ^ 1], tid);
+      pb.store(Bs[cur ^ 1], tid);
     }
+    __syncthreads();
   }
 
-  // epilogue: C = alpha * acc + beta * C
+  // epilogue: C = alpha * acc + beta * C, or raw partial sums for split-K
   const double alpha = p.alpha, beta = p.beta;
 #pragma unroll
-  for (int i = 0; i < T::TMI; ++i)
+  for (int i = 0; i < TMI; ++i)
 #pragma unroll
-    for (int j = 0; j < T::TNI; ++j)
+    for (int j = 0; j < TNI; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = (sizeof(typename Mma::L) == 8) ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
-        const int gm = m0 + wm * T::WTM + i * 16 + row;
-        const int gn = n0 + wn * T::WTN + j * 16 + (lane & 15);
+      for (int r = 0; r < Mma::NACC; ++r) {
+        const int row = (Mma::NACC == 1) ? (lane >> 4) : 4 * (lane >> 4) + r;
+        const int gm = m0 + wm * WTM + i * Mma::TM + row;
+        const int gn = n0 + wn * WTN + j * Mma::TN + (lane & 15);
+        if (gm >= p.M || gn >= p.N) continue;
         if (p.splits > 1) {
-          if (gm < p.M && gn < p.N) {
-            const int64_t b = (int64_t)b1 * p.nb0 + b0;
-            p.ws[(((int64_t)split * p.nbtot + b) * p.M + gm) * p.N + gn] = (double)acc[i][j][r];
-          }
-        } else if (gm < p.M && gn < p.N) {
+          const int64_t b = (int64_t)b1 * p.nb0 + b0;
+          p.ws[(((int64_t)split * p.nbtot + b) * p.M + gm) * p.N + gn] = acc_get(acc[i][j], r);
+        } else {
           TC* c = Cg + gm * p.c_m + gn * p.c_n;
-          double v = alpha * (double)acc[i][j][r];
+          double v = alpha * acc_get(acc[i][j], r);
           if (beta != 0.0) v += beta * load_c<TC>(c);
           *c = from_acc<TC>(v);
         }
@@ -286,6 +333,16 @@ __global__ __launch_bounds__(256) void splitk_reduce(KArgs p) {
   }
 }
 
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+template <typename T>
+bool vec_ok(const void* base, int64_t s_row, int64_t s_k, int64_t s_b0, int64_t s_b1, bool kc) {
+  const int64_t V = 16 / (int64_t)sizeof(T);
+  if (!aligned16(base) || s_b0 % V != 0 || s_b1 % V != 0) return false;
+  if (kc) return s_k == 1 && s_row % V == 0;
+  return s_row == 1 && s_k % V == 0;
+}
+
 template <class Mma, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WGM>
 void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStream_t s) {
   KArgs p;
@@ -298,6 +355,10 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStr
   p.alpha = d.alpha; p.beta = d.beta;
   const int64_t nb = (int64_t)d.nb0 * d.nb1;
   p.nbtot = (int)nb;
+  const bool akc = d.a_k == 1 && d.a_m != 1;
+  const bool bkc = d.b_k == 1 && d.b_n != 1;
+  p.a_vec = vec_ok<TA>(A, d.a_m, d.a_k, d.a_b0, d.a_b1, akc);
+  p.b_vec = vec_ok<TB>(B, d.b_n, d.b_k, d.b_b0, d.b_b1, bkc);
   // split-K when the output tiles cannot fill the GPU
   int splits = 1;
   const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n * nb;
@@ -308,7 +369,6 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStr
     want = std::min<int64_t>(want, 256);
     if (want >= 2) splits = (int)want;
   }
-  p.splits = splits;
   p.kchunk = splits > 1 ? (int)(ceil_div(ceil_div(d.K, splits), BK) * BK) : d.K;
   if (splits > 1) splits = (int)ceil_div(d.K, p.kchunk);  // no empty chunk
   p.splits = splits;
@@ -316,12 +376,8 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStr
   // gridDim.y * gridDim.z covers the batch; y is a multiple of nb0
   int64_t gy = d.nb0, gz = d.nb1;
   while (gy * 2 <= 65535 && gz % 2 == 0) { gy *= 2; gz /= 2; }
-  PNK_REQUIRE(gy <= 65535 && gz <= 65535, "gemm: batch too large");
-  (void)nb;
-  PNK_REQUIRE(gz * splits <= 65535, "gemm: split-K grid too large");
+  PNK_REQUIRE(gy <= 65535 && gz * splits <= 65535, "gemm: batch too large");
   dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)gy, (unsigned)(gz * splits));
-  const bool akc = d.a_k == 1 && d.a_m != 1;
-  const bool bkc = d.b_k == 1 && d.b_n != 1;
   if (akc && bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, true><<<grid, 256, 0, s>>>(p);
   else if (akc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, false><<<grid, 256, 0, s>>>(p);
   else if (bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, false, true><<<grid, 256, 0, s>>>(p);
@@ -334,16 +390,42 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStr
   }
 }
 
-// Tile choice: large tiles when the product has enough work to fill the
-// 256 CUs several times over, small tiles otherwise.
+double util(int64_t M, int64_t N, int bm, int bn) {
+  return (double)(M * N) / (double)(ceil_div(M, bm) * bm * ceil_div(N, bn) * bn);
+}
+
+// Tile choice. FP64: 64 output columns per workgroup (more resident waves
+// per SIMD hide LDS and global latency better than wider tiles; measured on
+// MI355X) and the row height among 128/112/96/80 that wastes the fewest rows
+// (M = nocc^2 or nocc(nocc+1)/2 is rarely a multiple of 128). FP32/BF16:
+// 128 x 128. Small products: 64 x 64 (split-K fills the GPU).
 template <class Mma, typename TA, typename TB, typename TC, int BK>
 void launch_sized(const GemmDesc& d, const void* A, const void* B, void* C, hipStream_t s) {
   const int64_t nb = (int64_t)d.nb0 * d.nb1;
-  const int64_t big = ceil_div(d.M, 128) * ceil_div(d.N, 128) * nb;
-  if (d.M >= 96 && d.N >= 96 && big >= 512)
-    launch_cfg<Mma, TA, TB, TC, 128, 128, BK, 2>(d, A, B, C, s);
-  else
+  if constexpr (sizeof(typename Mma::L) == 8) {
+    const int64_t tiles = ceil_div(d.M, 128) * ceil_div(d.N, 64) * nb;
+    if (d.M >= 64 && d.N >= 64 && tiles >= 256) {
+      struct Opt { int bm; double score; };
+      const Opt opts[] = {{128, util(d.M, d.N, 128, 64)},
+                          {112, 0.99 * util(d.M, d.N, 112, 64)},
+                          {96, 0.98 * util(d.M, d.N, 96, 64)},
+                          {80, 0.98 * util(d.M, d.N, 80, 64)}};
+      Opt best = opts[0];
+      for (const Opt& o : opts)
+        if (o.score > best.score + 1e-9) best = o;
+      switch (best.bm) {
+        case 112: launch_cfg<Mma, TA, TB, TC, 112, 64, BK, 2>(d, A, B, C, s); return;
+        case 96: launch_cfg<Mma, TA, TB, TC, 96, 64, BK, 2>(d, A, B, C, s); return;
+        case 80: launch_cfg<Mma, TA, TB, TC, 80, 64, BK, 2>(d, A, B, C, s); return;
+        default: launch_cfg<Mma, TA, TB, TC, 128, 64, BK, 2>(d, A, B, C, s); return;
+      }
+    }
     launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, C, s);
+    return;
+  }
+  const int64_t big = ceil_div(d.M, 128) * ceil_div(d.N, 128) * nb;
+  if (d.M >= 64 && d.N >= 96 && big >= 256) launch_cfg<Mma, TA, TB, TC, 128, 128, BK, 2>(d, A, B, C, s);
+  else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, C, s);
 }
 
 }  // namespace
@@ -352,38 +434,29 @@ void gemm(const GemmDesc& d, const void* A, Prec ap, const void* B, Prec bp, voi
           hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.nb0 <= 0 || d.nb1 <= 0) return;
   PNK_REQUIRE(cp == Prec::F64 || cp == Prec::F32, "gemm: C must be f64 or f32");
-  if (d.K <= 0) {
-    // C = beta * C: express as a K=1 product with alpha = 0 would read A/B;
-    // callers never request this shape.
-    PNK_REQUIRE(false, "gemm: K must be positive");
-  }
-#define PNK_GEMM_CASE(MMA, TA, TB, TC, BK) \
-  return launch_sized<MMA, TA, TB, TC, BK>(d, A, B, C, s)
+  PNK_REQUIRE(d.K > 0, "gemm: K must be positive");
+#define PNK_GEMM_CASE(MMA, TA, TB, TC, BK) return launch_sized<MMA, TA, TB, TC, BK>(d, A, B, C, s)
   if (compute == Prec::F64) {
     PNK_REQUIRE(ap == Prec::F64 && bp == Prec::F64, "gemm: f64 compute needs f64 operands");
-    if (cp == Prec::F64) PNK_GEMM_CASE(MmaF64, double, double, double, 16);
-    PNK_GEMM_CASE(MmaF64, double, double, float, 16);
+    PNK_REQUIRE(cp == Prec::F64, "gemm: f64 compute writes f64");
+    PNK_GEMM_CASE(MmaF64, double, double, double, 16);
   }
   if (compute == Prec::F32) {
-    PNK_REQUIRE(ap != Prec::BF16 && bp != Prec::BF16, "gemm: f32 compute needs f32/f64 operands");
-    if (cp == Prec::F64) {
-      if (ap == Prec::F64 && bp == Prec::F64) PNK_GEMM_CASE(MmaF32, double, double, double, 16);
-      if (ap == Prec::F64 && bp == Prec::F32) PNK_GEMM_CASE(MmaF32, double, float, double, 16);
-      if (ap == Prec::F32 && bp == Prec::F64) PNK_GEMM_CASE(MmaF32, float, double, double, 16);
-      PNK_GEMM_CASE(MmaF32, float, float, double, 16);
-    }
-    if (ap == Prec::F64 && bp == Prec::F64) PNK_GEMM_CASE(MmaF32, double, double, float, 16);
-    PNK_GEMM_CASE(MmaF32, float, float, float, 16);
+    PNK_REQUIRE(cp == Prec::F64, "gemm: f32 compute writes f64");
+    if (ap == Prec::F64 && bp == Prec::F64) PNK_GEMM_CASE(MmaF32, double, double, double, 16);
+    if (ap == Prec::F64 && bp == Prec::F32) PNK_GEMM_CASE(MmaF32, double, float, double, 16);
+    if (ap == Prec::F32 && bp == Prec::F64) PNK_GEMM_CASE(MmaF32, float, double, double, 16);
+    if (ap == Prec::F32 && bp == Prec::F32) PNK_GEMM_CASE(MmaF32, float, float, double, 16);
   }
-  // BF16 compute, FP32 accumulation
-  if (cp == Prec::F64) {
+  if (compute == Prec::BF16) {
+    PNK_REQUIRE(cp == Prec::F64, "gemm: bf16 compute writes f64");
     if (ap == Prec::F64 && bp == Prec::F64) PNK_GEMM_CASE(MmaBF16, double, double, double, 32);
     if (ap == Prec::F64 && bp == Prec::BF16) PNK_GEMM_CASE(MmaBF16, double, uint16_t, double, 32);
     if (ap == Prec::BF16 && bp == Prec::F64) PNK_GEMM_CASE(MmaBF16, uint16_t, double, double, 32);
     if (ap == Prec::BF16 && bp == Prec::BF16) PNK_GEMM_CASE(MmaBF16, uint16_t, uint16_t, double, 32);
   }
-  PNK_REQUIRE(false, "gemm: unsupported precision combination");
 #undef PNK_GEMM_CASE
+  PNK_REQUIRE(false, "gemm: unsupported precision combination");
 }
 
 }  // namespace pnk

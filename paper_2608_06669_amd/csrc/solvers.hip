@@ -89,6 +89,7 @@ Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_
 }
 
 Solver::~Solver() {
+  if (lz_exec_) (void)hipGraphExecDestroy(lz_exec_);
   for (double* p : {Qo_, Qi_, r_, ri_, w_, w2_, hx_, he_, dsc_, partials_})
     if (p) (void)(async_ ? hipFreeAsync(p, alloc_stream_) : hipFree(p));
   if (host_) (void)hipHostFree(host_);
@@ -132,6 +133,235 @@ double Solver::orthogonalise(double* Q, int64_t ldq, int m, double* w, std::vect
   return host_[2 * kMaxBasis];
 }
 
+namespace {
+
+// ---- short-recurrence (Lanczos) GMRES for symmetric A_F, all on the device ----
+// state: [0] beta_k  [1] alpha_k  [2] beta_{k+1}  [3] c_{k-2} [4] s_{k-2}
+//        [5] c_{k-1} [6] s_{k-1}  [7] phibar      [8] rho1    [9] delta
+//        [10] eps    [11] phi     [12] |phibar|   [13] 1/beta_{k+1}
+enum { kBeta = 0, kAlpha, kBetaN, kC2, kS2, kC1, kS1, kPhiBar, kRho1, kDelta, kEps, kPhi, kRes, kInvB, kNState };
+
+// p -= beta_k v_prev; partial sums of <v, p>
+__global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ p, const double* __restrict__ vprev,
+                                                const double* __restrict__ v, const double* __restrict__ st,
+                                                double* partials) {
+  __shared__ double sm[256];
+  const double beta = st[kBeta];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double x = p[i] - beta * vprev[i];
+    p[i] = x;
+    acc += v[i] * x;
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+}
+
+// p -= alpha_k v; partial sums of <p, p>
+__global__ __launch_bounds__(256) void lz_step2(int64_t n, double* __restrict__ p, const double* __restrict__ v,
+                                                const double* __restrict__ st, double* partials) {
+  __shared__ double sm[256];
+  const double alpha = st[kAlpha];
+  double acc = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double x = p[i] - alpha * v[i];
+    p[i] = x;
+    acc += x * x;
+  }
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+}
+
+// sums the partials of step1 into alpha (which = 0) or of step2 into
+// beta_{k+1} = sqrt(sum) (which = 1), fixed order
+__global__ __launch_bounds__(256) void lz_reduce(int nparts, const double* partials, double* st, int which) {
+  __shared__ double sm[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) acc += partials[i];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (which == 0) st[kAlpha] = sm[0];
+    else st[kBetaN] = sqrt(sm[0]);
+  }
+}
+
+// Givens update of the tridiagonal QR and the solution coefficients
+__global__ void lz_scalars(double* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double beta = st[kBeta], alpha = st[kAlpha], betan = st[kBetaN];
+  const double c2 = st[kC2], s2 = st[kS2], c1 = st[kC1], s1 = st[kS1];
+  const double eps = s2 * beta;
+  const double dbar = c2 * beta;
+  const double delta = c1 * dbar + s1 * alpha;
+  const double gbar = -s1 * dbar + c1 * alpha;
+  const double rho1 = hypot(gbar, betan);
+  const double c = rho1 != 0.0 ? gbar / rho1 : 1.0;
+  const double s = rho1 != 0.0 ? betan / rho1 : 0.0;
+  const double phibar = st[kPhiBar];
+  st[kPhi] = c * phibar;
+  st[kPhiBar] = -s * phibar;
+  st[kRes] = fabs(s * phibar);
+  st[kRho1] = rho1;
+  st[kDelta] = delta;
+  st[kEps] = eps;
+  st[kC2] = c1; st[kS2] = s1;
+  st[kC1] = c; st[kS1] = s;
+  st[kInvB] = betan != 0.0 ? 1.0 / betan : 0.0;
+  st[kBeta] = betan;
+}
+
+// w_k = (v_k - delta w_{k-1} - eps w_{k-2}) / rho1 (into the w_{k-2} slot),
+// x += phi w_k, v_{k+1} = p / beta_{k+1} (in place)
+__global__ void lz_update(int64_t n, const double* __restrict__ v, const double* __restrict__ w1,
+                          double* __restrict__ w2, double* __restrict__ x, double* __restrict__ p,
+                          const double* __restrict__ st) {
+  const double rho1 = st[kRho1], delta = st[kDelta], eps = st[kEps], phi = st[kPhi], invb = st[kInvB];
+  const double ir = rho1 != 0.0 ? 1.0 / rho1 : 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double w = (v[i] - delta * w1[i] - eps * w2[i]) * ir;
+    w2[i] = w;
+    x[i] += phi * w;
+    p[i] *= invb;
+  }
+}
+
+// state init: beta_1 = ||b|| (from st[kRes] slot holding the norm)
+__global__ void lz_init(double* st, const double* bnorm) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int k = 0; k < kNState; ++k) st[k] = 0.0;
+  st[kC2] = 1.0; st[kC1] = 1.0;
+  st[kPhiBar] = *bnorm;
+  st[kRes] = *bnorm;
+  st[kBeta] = 0.0;  // v_0 = 0
+}
+
+inline int grid_n(int64_t n) {
+  int64_t g = ceil_div(n, 256);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+}
+
+}  // namespace
+
+// A_F symmetric (f_ov = 0): the Arnoldi process of GMRES reduces to the
+// three-term Lanczos recurrence and the Hessenberg least-squares problem to
+// a tridiagonal one, updated with one Givens rotation per step (GMRES and
+// MINRES coincide in exact arithmetic). Everything stays on the device; the
+// host reads the residual estimate every `check` steps.
+// One Lanczos step on fixed buffers (see precond_solve_sym).
+void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
+                          hipStream_t s) {
+  const int64_t n = n_;
+  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  eng_.fock_apply(v, v + ov, p, p + ov, s);
+  lz_step1<<<kReduceBlocks, 256, 0, s>>>(n, p, vprev, v, st, partials_);
+  lz_reduce<<<1, 256, 0, s>>>(kReduceBlocks, partials_, st, 0);
+  lz_step2<<<kReduceBlocks, 256, 0, s>>>(n, p, v, st, partials_);
+  lz_reduce<<<1, 256, 0, s>>>(kReduceBlocks, partials_, st, 1);
+  lz_scalars<<<1, 1, 0, s>>>(st);
+  lz_update<<<grid_n(n), 256, 0, s>>>(n, v, w1, w2, x, p, st);
+  PNK_CHECK_LAUNCH();
+}
+
+// Six steps: the buffer rotation (v: period 3, w: period 2) returns to its
+// start, so the block can be recorded once as a HIP graph and replayed.
+void Solver::lanczos_block(hipStream_t s) {
+  const int64_t n = n_;
+  double* st = dsc_ + 3 * kMaxBasis + kMaxBasis / 2;
+  double *vprev = Qi_, *v = Qi_ + n, *p = Qi_ + 2 * n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *x = Qi_ + 5 * n;
+  for (int k = 0; k < kLanczosBlock; ++k) {
+    lanczos_step(vprev, v, p, w1, w2, x, st, s);
+    std::swap(vprev, v);  // v_{k-1} <- v_k
+    std::swap(v, p);      // v_k <- v_{k+1}; p <- free buffer
+    std::swap(w1, w2);    // w_{k-1} <- w_k
+  }
+}
+
+bool Solver::ensure_lanczos_graph() {
+  if (lz_exec_) return true;
+  if (lz_graph_failed_) return false;
+  Timers* tm = eng_.timers();
+  eng_.set_timers(nullptr);  // no event records inside a graph
+  bool ok = false;
+  hipStream_t cs = nullptr;
+  hipGraph_t g = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
+      hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    try {
+      lanczos_block(cs);
+    } catch (...) {
+    }
+    if (hipStreamEndCapture(cs, &g) == hipSuccess && g &&
+        hipGraphInstantiate(&lz_exec_, g, nullptr, nullptr, 0) == hipSuccess)
+      ok = true;
+  }
+  if (g) (void)hipGraphDestroy(g);
+  if (cs) (void)hipStreamDestroy(cs);
+  (void)hipGetLastError();
+  eng_.set_timers(tm);
+  if (!ok) {
+    lz_exec_ = nullptr;
+    lz_graph_failed_ = true;
+  }
+  return ok;
+}
+
+// A_F symmetric (f_ov = 0): the Arnoldi process of GMRES reduces to the
+// three-term Lanczos recurrence and the Hessenberg least-squares problem to
+// a tridiagonal one, updated with one Givens rotation per step (GMRES and
+// MINRES coincide in exact arithmetic). Everything stays on the device:
+// blocks of six steps are replayed as one HIP graph, and the host reads the
+// residual estimate after each block (so up to five extra steps run past
+// convergence; they only lower the residual further).
+int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged) {
+  const int64_t n = n_;
+  double bn, dummy;
+  norms(b, &dummy, &bn, s);
+  if (converged) *converged = true;
+  if (bn == 0.0) {
+    fill(n, 0.0, x, s);
+    return 0;
+  }
+  double* st = dsc_ + 3 * kMaxBasis + kMaxBasis / 2;  // state block (kNState doubles)
+  double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *xi = Qi_ + 5 * n;
+  lz_init<<<1, 1, 0, s>>>(st, dsc_ + 1);
+  scale_by_inverse(n, b, dsc_ + 1, v, s);  // v_1 = b / ||b||
+  fill(n, 0.0, vprev, s);
+  fill(n, 0.0, w1, s);
+  fill(n, 0.0, w2, s);
+  fill(n, 0.0, xi, s);
+  PNK_CHECK_LAUNCH();
+  const bool graph = use_graphs_ && ensure_lanczos_graph();
+  int it = 0;
+  bool conv = false;
+  while (it < maxit) {
+    if (graph) PNK_HIP(hipGraphLaunch(lz_exec_, s));
+    else lanczos_block(s);
+    it += kLanczosBlock;
+    read_scalars(host_, st, kNState, s);
+    const double res = host_[kRes];
+    if (!std::isfinite(res)) break;
+    if (res <= rtol * bn || host_[kBeta] == 0.0) { conv = true; break; }
+  }
+  copy(n, xi, x, s);
+  if (converged) *converged = conv;
+  return it;
+}
+
 int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s,
                           bool* converged) {
   PNK_REQUIRE(restart >= 1 && restart <= restart_, "precond_solve: restart exceeds the allocated basis");
@@ -143,6 +373,7 @@ int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, in
     Timers* t; hipStream_t s;
     ~EndTimer() { if (t) t->end(kTimerPrecond, s); }
   } end_timer{tm, s};
+  if (eng_.fov_zero() && sym_inner_ && restart_ >= 5) return precond_solve_sym(b, x, rtol, maxit, s, converged);
   double bn, dummy;
   norms(b, &dummy, &bn, s);
   fill(n, 0.0, x, s);

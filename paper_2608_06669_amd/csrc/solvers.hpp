@@ -54,6 +54,13 @@ class Solver {
   // vectors of length nvec. Returns the number of A_F products.
   int precond_solve(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s,
                     bool* converged = nullptr);
+  // Symmetric A_F (f_ov = 0): device-resident Lanczos form of GMRES.
+  int precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged);
+  // Use the short-recurrence form when A_F is symmetric (default on).
+  void set_symmetric_inner(bool on) { sym_inner_ = on; }
+  // Replay recorded HIP graphs for the inner iterations (default on).
+  void set_graphs(bool on) { use_graphs_ = on; }
+  static constexpr int kLanczosBlock = 6;
   void solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s);
   void solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipStream_t s);
 
@@ -84,6 +91,14 @@ class Solver {
   double* host_;   // pinned host scalars
   hipStream_t alloc_stream_;
   bool async_;
+  bool sym_inner_ = true;
+  bool use_graphs_ = true;
+  bool lz_graph_failed_ = false;
+  hipGraphExec_t lz_exec_ = nullptr;
+  void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
+                    hipStream_t s);
+  void lanczos_block(hipStream_t s);
+  bool ensure_lanczos_graph();
   std::vector<double> hist_;
 };
 
