@@ -23,6 +23,7 @@
 // Z_ij,kb = sum_cd (kc|bd) t_ij^cd and Y_ij,kl = sum_cd (kc|ld) t_ij^cd.
 
 #include "ccsd.hpp"
+#include "fock_op.hpp"
 
 #include <algorithm>
 #include <cstring>
@@ -137,10 +138,13 @@ struct Sizes {
   }
 };
 
-// Split-K scratch: enough for 64-way splits of the largest small product.
+// Split-K scratch. Products are split only when they have fewer than 256
+// output tiles of at least 64 x 64, into at most ceil(512 / tiles) chunks,
+// so splits * M * N * batch stays below 512 * 4096 + 64 * 64 * 256 doubles;
+// small problems need far less.
 int64_t splitk_elems(const Sizes& z) {
-  const int64_t big = std::max<int64_t>({z.v * z.v, z.ov, z.o * z.o * 4});
-  return std::min<int64_t>(64 * big, 4 * 1024 * 1024);
+  const int64_t big = std::max<int64_t>({z.o * z.o * z.v * z.v, z.ov * z.ov, (int64_t)z.o * z.o * z.o * z.o});
+  return std::min<int64_t>(std::max<int64_t>(16 * big, 1 << 16), 3 * 1024 * 1024);
 }
 
 // Calls `f(count_doubles)` for every FP64 buffer in allocation order, and
@@ -234,6 +238,11 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
   tin_ = take(OV + N2);
   tout_ = take(OV + N2);
   T1.var = T2.var = R1.var = R2.var = true;
+  fop_.o = o;
+  fop_.v = v;
+  fop_.f_oo = f_oo_;
+  fop_.f_vv = f_vv_;
+  fop_ok_ = fock_op_plan(fop_);
   (void)z;
 }
 
@@ -655,17 +664,22 @@ void Engine::fock_apply(const double* x1, const double* x2, double* y1, double* 
   const int o = o_, v = v_;
   const int64_t O = o, V = v, vv = V * V, oo = O * O, ov = ov_;
   if (timers_) timers_->begin(kTimerFock, s);
-  // a index: batched over ij, y_ij = f_vv x_ij
-  gemm64(with_ws(batch0(gd(v, v, v, v, 1, v, 1, v, 1), (int)oo, 0, vv, vv)), f_vv_, x2, y2, s);
-  // b index: y[(ija)][b] += sum_c x[(ija)][c] f_bc
-  gemm64(with_ws(gd((int)(oo * v), v, v, v, 1, 1, v, v, 1, 1.0, 1.0)), x2, f_vv_, y2, s);
-  // i index: y[i][(jab)] -= sum_k f_ki x[k][(jab)]
-  gemm64(with_ws(gd(o, (int)(O * vv), o, 1, o, O * vv, 1, O * vv, 1, -1.0, 1.0)), f_oo_, x2, y2, s);
-  // j index: batched over i, y_i[j][(ab)] -= sum_k f_kj x_i[k][(ab)]
-  gemm64(with_ws(batch0(gd(o, (int)vv, o, 1, o, vv, 1, vv, 1, -1.0, 1.0), o, 0, O * vv, O * vv)), f_oo_, x2, y2, s);
-  // singles
-  gemm64(with_ws(gd(o, v, v, v, 1, 1, v, v, 1)), x1, f_vv_, y1, s);
-  gemm64(with_ws(gd(o, v, o, 1, o, v, 1, v, 1, -1.0, 1.0)), f_oo_, x1, y1, s);
+  if (fop_ok_ && x1 != y1 && x2 != y2) {
+    // virtual and occupied contractions and singles in one launch
+    fock_op_apply(fop_, x1, x2, y1, y2, s);
+  } else {
+    // a index: batched over ij, y_ij = f_vv x_ij
+    gemm64(with_ws(batch0(gd(v, v, v, v, 1, v, 1, v, 1), (int)oo, 0, vv, vv)), f_vv_, x2, y2, s);
+    // b index: y[(ija)][b] += sum_c x[(ija)][c] f_bc
+    gemm64(with_ws(gd((int)(oo * v), v, v, v, 1, 1, v, v, 1, 1.0, 1.0)), x2, f_vv_, y2, s);
+    // i index: y[i][(jab)] -= sum_k f_ki x[k][(jab)]
+    gemm64(with_ws(gd(o, (int)(O * vv), o, 1, o, O * vv, 1, O * vv, 1, -1.0, 1.0)), f_oo_, x2, y2, s);
+    // j index: batched over i, y_i[j][(ab)] -= sum_k f_kj x_i[k][(ab)]
+    gemm64(with_ws(batch0(gd(o, (int)vv, o, 1, o, vv, 1, vv, 1, -1.0, 1.0), o, 0, O * vv, O * vv)), f_oo_, x2, y2, s);
+    // singles
+    gemm64(with_ws(gd(o, v, v, v, 1, 1, v, v, 1)), x1, f_vv_, y1, s);
+    gemm64(with_ws(gd(o, v, o, 1, o, v, 1, v, 1, -1.0, 1.0)), f_oo_, x1, y1, s);
+  }
   if (!fov_zero_) {
     // u_x[i][a][k][c] = 2 x_ik^ac - x_ik^ca, then y1 += u_x f_ov
     const int dims[4] = {o, o, v, v};

@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "common.hpp"
+#include "fock_op.hpp"
 #include "gemm.hpp"
 
 namespace pnk {
@@ -110,6 +111,8 @@ class Engine {
   const double* f_oo() const { return f_oo_; }
   const double* f_vv() const { return f_vv_; }
   bool fov_zero() const { return fov_zero_; }
+  // Fused A_F kernel plan (null when the general path must be used).
+  const FockOp* fock_op() const { return fop_ok_ ? &fop_ : nullptr; }
   double* scratch_partials() { return partials_; }
   const double* zeros() const { return zeros_; }
   void set_timers(Timers* t) { timers_ = t; }
@@ -151,6 +154,8 @@ class Engine {
   // problem constants
   double *f_oo_, *f_ov_, *f_vv_, *fock_, *h_, *dtr_, *Lo_;
   bool fov_zero_ = true;
+  FockOp fop_;
+  bool fop_ok_ = false;
   Ten Loo0, Lov0, Lvo0, Lvv0, S, Am, Wov, Ioovv, Iovov, Ix, Ikldc, Itil;
   // symmetry-adapted ladder: pair tables and the (ac|bd) block staging area
   int *pair_a_, *pair_b_, *mpair_a_, *mpair_b_;

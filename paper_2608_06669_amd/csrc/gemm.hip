@@ -32,67 +32,14 @@
 // never depend on timing.
 
 #include "gemm.hpp"
+#include "mfma_tiles.hpp"
 
 #include <algorithm>
 
 namespace pnk {
 namespace {
 
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-
-__device__ inline uint16_t f32_to_bf16(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return (uint16_t)(u >> 16);
-}
-
-// Convert one stored element to the LDS (compute) representation.
-template <typename S, typename L> __device__ inline L to_lds(S x);
-template <> __device__ inline double to_lds<double, double>(double x) { return x; }
-template <> __device__ inline float to_lds<double, float>(double x) { return (float)x; }
-template <> __device__ inline float to_lds<float, float>(float x) { return x; }
-template <> __device__ inline uint16_t to_lds<double, uint16_t>(double x) { return f32_to_bf16((float)x); }
-template <> __device__ inline uint16_t to_lds<float, uint16_t>(float x) { return f32_to_bf16(x); }
-template <> __device__ inline uint16_t to_lds<uint16_t, uint16_t>(uint16_t x) { return x; }
-
-template <typename C> __device__ inline C from_acc(double x);
-template <> __device__ inline double from_acc<double>(double x) { return x; }
-template <> __device__ inline float from_acc<float>(double x) { return (float)x; }
-template <typename C> __device__ inline double load_c(const C* p) { return (double)*p; }
-
-// TM x TN: output tile of one instruction; NACC: accumulator values per lane
-struct MmaF64 {
-  using L = double;   // LDS element
-  using Acc = double;
-  static constexpr int KSTEP = 4, TM = 4, TN = 16, NACC = 1;
-  static constexpr bool KCONTIG_LDS = false;  // LDS laid out [k][m]
-};
-struct MmaF32 {
-  using L = float;
-  using Acc = f4;
-  static constexpr int KSTEP = 4, TM = 16, TN = 16, NACC = 4;
-  static constexpr bool KCONTIG_LDS = false;
-};
-struct MmaBF16 {
-  using L = uint16_t;
-  using Acc = f4;
-  static constexpr int KSTEP = 32, TM = 16, TN = 16, NACC = 4;
-  static constexpr bool KCONTIG_LDS = true;  // LDS laid out [m][k]
-};
-template <class Acc> __device__ inline double acc_get(const Acc& a, int r) { return (double)a[r]; }
-template <> __device__ inline double acc_get<double>(const double& a, int) { return a; }
-
-constexpr int kPad = 1;   // [k][rows + kPad]
-constexpr int kPadK = 8;  // [rows][k + kPadK]
-
-template <class Mma, int ROWS, int BK>
-constexpr int lds_elems() {
-  return Mma::KCONTIG_LDS ? ROWS * (BK + kPadK) : BK * (ROWS + kPad);
-}
+using namespace tiles;
 
 struct KArgs {
   int M, N, K, nb0;
@@ -108,68 +55,6 @@ struct KArgs {
   void* C;
   int64_t c_m, c_n, c_b0, c_b1;
   double alpha, beta;
-};
-
-// Loads a ROWS x BK panel (ROWS = BM for A, BN for B) into registers and
-// writes it to one LDS buffer. KC: the operand is contiguous along k.
-template <class Mma, typename T, int ROWS, int BK, bool KC>
-struct Panel {
-  using L = typename Mma::L;
-  static constexpr int V = 16 / (int)sizeof(T);
-  static constexpr int NVEC = ROWS * BK / V;
-  static constexpr int PER = (NVEC + 255) / 256;
-  static_assert(ROWS % V == 0 && BK % V == 0, "panel must split into vectors");
-  T r[PER * V];
-
-  __device__ inline void coords(int q, int* row, int* kk) const {
-    if (KC) { *row = q / (BK / V); *kk = (q % (BK / V)) * V; }
-    else { *kk = q / (ROWS / V); *row = (q % (ROWS / V)) * V; }
-  }
-
-  __device__ inline void load(const T* __restrict__ g, int64_t s_row, int64_t s_k, int row0, int rows, int k0,
-                              int kend, bool vec_ok, int tid) {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int q = tid + e * 256;
-      if (q >= NVEC) break;
-      int row, kk;
-      coords(q, &row, &kk);
-      const int gr = row0 + row, gk = k0 + kk;
-      bool full;
-      if (KC) full = vec_ok && gr < rows && gk + V <= kend;
-      else full = vec_ok && gr + V <= rows && gk < kend;
-      if (full) {
-        const T* p = g + (int64_t)gr * s_row + (int64_t)gk * s_k;
-        const uint4 v = *reinterpret_cast<const uint4*>(p);
-        *reinterpret_cast<uint4*>(&r[e * V]) = v;
-      } else {
-#pragma unroll
-        for (int u = 0; u < V; ++u) {
-          const int rr = KC ? gr : gr + u;
-          const int kx = KC ? gk + u : gk;
-          r[e * V + u] = (rr < rows && kx < kend) ? g[(int64_t)rr * s_row + (int64_t)kx * s_k] : T(0);
-        }
-      }
-    }
-  }
-
-  __device__ inline void store(L* __restrict__ lds, int tid) const {
-#pragma unroll
-    for (int e = 0; e < PER; ++e) {
-      const int q = tid + e * 256;
-      if (q >= NVEC) break;
-      int row, kk;
-      coords(q, &row, &kk);
-#pragma unroll
-      for (int u = 0; u < V; ++u) {
-        const int rr = KC ? row : row + u;
-        const int kx = KC ? kk + u : kk;
-        const L x = to_lds<T, L>(r[e * V + u]);
-        if constexpr (Mma::KCONTIG_LDS) lds[rr * (BK + kPadK) + kx] = x;
-        else lds[kx * (ROWS + kPad) + rr] = x;
-      }
-    }
-  }
 };
 
 template <class Mma, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WGM, bool A_KC, bool B_KC>
@@ -333,6 +218,61 @@ __global__ __launch_bounds__(256) void splitk_reduce(KArgs p) {
   }
 }
 
+// Products with a short contraction (K <= kSmallK) and a short output side
+// (<= kSmallSide): a matrix-core tile would be mostly padding and the cost
+// is one pass over the long operand. Each lane owns one index of the long
+// output side, holds its K operand values in registers and produces every
+// output along the short side; the short operand's elements are the same
+// for all lanes (scalar loads). LONG_N: the long side is N.
+constexpr int kSmallK = 32, kSmallSide = 32;
+
+template <bool LONG_N>
+__global__ __launch_bounds__(256) void gemm_smallk(KArgs p) {
+  const int b0 = blockIdx.y % p.nb0;
+  const int b1 = blockIdx.y / p.nb0 + blockIdx.z * (gridDim.y / p.nb0);
+  const double* __restrict__ A = (const double*)p.A + b0 * p.a_b0 + b1 * p.a_b1;
+  const double* __restrict__ B = (const double*)p.B + b0 * p.b_b0 + b1 * p.b_b1;
+  double* __restrict__ C = (double*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
+  const int l = blockIdx.x * 256 + threadIdx.x;
+  const int L = LONG_N ? p.N : p.M;
+  const int S = LONG_N ? p.M : p.N;
+  if (l >= L) return;
+  double r[kSmallK];
+#pragma unroll
+  for (int k = 0; k < kSmallK; ++k)
+    r[k] = k < p.K ? (LONG_N ? B[k * p.b_k + l * p.b_n] : A[l * p.a_m + k * p.a_k]) : 0.0;
+  for (int s = 0; s < S; ++s) {
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kSmallK; ++k)
+      if (k < p.K) acc += (LONG_N ? A[s * p.a_m + k * p.a_k] : B[k * p.b_k + s * p.b_n]) * r[k];
+    double* c = LONG_N ? C + s * p.c_m + l * p.c_n : C + l * p.c_m + s * p.c_n;
+    double v = p.alpha * acc;
+    if (p.beta != 0.0) v += p.beta * *c;
+    *c = v;
+  }
+}
+
+void launch_smallk(const GemmDesc& d, const void* A, const void* B, void* C, hipStream_t s) {
+  KArgs p{};
+  p.M = d.M; p.N = d.N; p.K = d.K; p.nb0 = d.nb0; p.splits = 1;
+  p.A = A; p.a_m = d.a_m; p.a_k = d.a_k; p.a_b0 = d.a_b0; p.a_b1 = d.a_b1;
+  p.B = B; p.b_k = d.b_k; p.b_n = d.b_n; p.b_b0 = d.b_b0; p.b_b1 = d.b_b1;
+  p.C = C; p.c_m = d.c_m; p.c_n = d.c_n; p.c_b0 = d.c_b0; p.c_b1 = d.c_b1;
+  p.alpha = d.alpha; p.beta = d.beta;
+  // the long side is the one with more elements; ties go to N (usually the
+  // contiguous index of C)
+  const bool long_n = d.N >= d.M;
+  const int L = long_n ? d.N : d.M;
+  int64_t gy = d.nb0, gz = d.nb1;
+  while (gy * 2 <= 65535 && gz % 2 == 0) { gy *= 2; gz /= 2; }
+  PNK_REQUIRE(gy <= 65535 && gz <= 65535, "gemm: batch too large");
+  dim3 grid((unsigned)ceil_div(L, 256), (unsigned)gy, (unsigned)gz);
+  if (long_n) gemm_smallk<true><<<grid, 256, 0, s>>>(p);
+  else gemm_smallk<false><<<grid, 256, 0, s>>>(p);
+  PNK_CHECK_LAUNCH();
+}
+
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
 template <typename T>
@@ -362,7 +302,9 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStr
   // split-K when the output tiles cannot fill the GPU
   int splits = 1;
   const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n * nb;
-  if (d.ws && tiles < 256 && d.K >= 4 * BK) {
+  // (short contractions are not split: the extra pass over the partial sums
+  // would cost more than the product)
+  if (d.ws && tiles < 256 && d.K >= 256) {
     int64_t want = ceil_div(512, tiles);
     want = std::min<int64_t>(want, d.K / (2 * BK));
     want = std::min<int64_t>(want, d.ws_elems / std::max<int64_t>(1, nb * d.M * d.N));
@@ -439,6 +381,7 @@ void gemm(const GemmDesc& d, const void* A, Prec ap, const void* B, Prec bp, voi
   if (compute == Prec::F64) {
     PNK_REQUIRE(ap == Prec::F64 && bp == Prec::F64, "gemm: f64 compute needs f64 operands");
     PNK_REQUIRE(cp == Prec::F64, "gemm: f64 compute writes f64");
+    if (d.K <= kSmallK && std::min(d.M, d.N) <= kSmallSide) return launch_smallk(d, A, B, C, s);
     PNK_GEMM_CASE(MmaF64, double, double, double, 16);
   }
   if (compute == Prec::F32) {

@@ -14,6 +14,7 @@
 // solved on the host.
 
 #include "solvers.hpp"
+#include "fock_op.hpp"
 
 #include <chrono>
 #include <cmath>
@@ -136,15 +137,51 @@ double Solver::orthogonalise(double* Q, int64_t ldq, int m, double* w, std::vect
 namespace {
 
 // ---- short-recurrence (Lanczos) GMRES for symmetric A_F, all on the device ----
+// Three kernels per step. Global sums are never a kernel of their own: the
+// kernel that needs a sum adds the previous kernel's per-workgroup partial
+// sums itself, every workgroup in the same fixed order (so every workgroup
+// gets the same bits), and the scalar recurrences are evaluated redundantly
+// by every workgroup of the last kernel. The state therefore has two slots:
+// step k reads slot k % 2 and workgroup 0 writes slot (k + 1) % 2.
 // state: [0] beta_k  [1] alpha_k  [2] beta_{k+1}  [3] c_{k-2} [4] s_{k-2}
 //        [5] c_{k-1} [6] s_{k-1}  [7] phibar      [8] rho1    [9] delta
 //        [10] eps    [11] phi     [12] |phibar|   [13] 1/beta_{k+1}
 enum { kBeta = 0, kAlpha, kBetaN, kC2, kS2, kC1, kS1, kPhiBar, kRho1, kDelta, kEps, kPhi, kRes, kInvB, kNState };
+constexpr int kStateStride = 16;
+constexpr int kLzBlocks = 512;
 
-// p -= beta_k v_prev; partial sums of <v, p>
+constexpr int kMaxFusedParts = 16384;  // partial sums written by the fused A_F launch
+
+// Fixed-order sum of n partials by one workgroup of 256 threads (every
+// workgroup that calls it gets the same bits).
+__device__ inline double lz_block_sum(const double* partials, int n, double* sm) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) acc += partials[k];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline void lz_block_partial(double acc, double* sm, double* partials) {
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+}
+
+// p -= beta_k v_{k-1}; partial sums of <v_k, p>
 __global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ p, const double* __restrict__ vprev,
                                                 const double* __restrict__ v, const double* __restrict__ st,
-                                                double* partials) {
+                                                double* __restrict__ part1) {
   __shared__ double sm[256];
   const double beta = st[kBeta];
   double acc = 0.0;
@@ -153,57 +190,36 @@ __global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ 
     p[i] = x;
     acc += v[i] * x;
   }
-  sm[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+  lz_block_partial(acc, sm, part1);
 }
 
-// p -= alpha_k v; partial sums of <p, p>
+// alpha_k = <v_k, p>; p -= alpha_k v_k; partial sums of <p, p>
 __global__ __launch_bounds__(256) void lz_step2(int64_t n, double* __restrict__ p, const double* __restrict__ v,
-                                                const double* __restrict__ st, double* partials) {
+                                                const double* __restrict__ part1, int nparts1,
+                                                double* __restrict__ st, double* __restrict__ part2) {
   __shared__ double sm[256];
-  const double alpha = st[kAlpha];
+  const double alpha = lz_block_sum(part1, nparts1, sm);
+  if (blockIdx.x == 0 && threadIdx.x == 0) st[kAlpha] = alpha;  // read by lz_update only
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const double x = p[i] - alpha * v[i];
     p[i] = x;
     acc += x * x;
   }
-  sm[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
+  lz_block_partial(acc, sm, part2);
 }
 
-// sums the partials of step1 into alpha (which = 0) or of step2 into
-// beta_{k+1} = sqrt(sum) (which = 1), fixed order
-__global__ __launch_bounds__(256) void lz_reduce(int nparts, const double* partials, double* st, int which) {
+// beta_{k+1} = ||p||; one Givens rotation of the tridiagonal QR; then
+// w_k = (v_k - delta w_{k-1} - eps w_{k-2}) / rho1 (into the w_{k-2} slot),
+// x += phi w_k, v_{k+1} = p / beta_{k+1} (in place)
+__global__ __launch_bounds__(256) void lz_update(int64_t n, const double* __restrict__ v,
+                                                 const double* __restrict__ w1, double* __restrict__ w2,
+                                                 double* __restrict__ x, double* __restrict__ p,
+                                                 const double* __restrict__ part2, const double* __restrict__ st,
+                                                 double* __restrict__ stn) {
   __shared__ double sm[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) acc += partials[i];
-  sm[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    if (which == 0) st[kAlpha] = sm[0];
-    else st[kBetaN] = sqrt(sm[0]);
-  }
-}
-
-// Givens update of the tridiagonal QR and the solution coefficients
-__global__ void lz_scalars(double* st) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const double beta = st[kBeta], alpha = st[kAlpha], betan = st[kBetaN];
+  const double betan = sqrt(lz_block_sum(part2, kLzBlocks, sm));
+  const double beta = st[kBeta], alpha = st[kAlpha];
   const double c2 = st[kC2], s2 = st[kS2], c1 = st[kC1], s1 = st[kS1];
   const double eps = s2 * beta;
   const double dbar = c2 * beta;
@@ -213,26 +229,24 @@ __global__ void lz_scalars(double* st) {
   const double c = rho1 != 0.0 ? gbar / rho1 : 1.0;
   const double s = rho1 != 0.0 ? betan / rho1 : 0.0;
   const double phibar = st[kPhiBar];
-  st[kPhi] = c * phibar;
-  st[kPhiBar] = -s * phibar;
-  st[kRes] = fabs(s * phibar);
-  st[kRho1] = rho1;
-  st[kDelta] = delta;
-  st[kEps] = eps;
-  st[kC2] = c1; st[kS2] = s1;
-  st[kC1] = c; st[kS1] = s;
-  st[kInvB] = betan != 0.0 ? 1.0 / betan : 0.0;
-  st[kBeta] = betan;
-}
-
-// w_k = (v_k - delta w_{k-1} - eps w_{k-2}) / rho1 (into the w_{k-2} slot),
-// x += phi w_k, v_{k+1} = p / beta_{k+1} (in place)
-__global__ void lz_update(int64_t n, const double* __restrict__ v, const double* __restrict__ w1,
-                          double* __restrict__ w2, double* __restrict__ x, double* __restrict__ p,
-                          const double* __restrict__ st) {
-  const double rho1 = st[kRho1], delta = st[kDelta], eps = st[kEps], phi = st[kPhi], invb = st[kInvB];
+  const double phi = c * phibar;
+  const double invb = betan != 0.0 ? 1.0 / betan : 0.0;
   const double ir = rho1 != 0.0 ? 1.0 / rho1 : 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    stn[kBeta] = betan;
+    stn[kAlpha] = alpha;
+    stn[kBetaN] = betan;
+    stn[kC2] = c1; stn[kS2] = s1;
+    stn[kC1] = c; stn[kS1] = s;
+    stn[kPhiBar] = -s * phibar;
+    stn[kRho1] = rho1;
+    stn[kDelta] = delta;
+    stn[kEps] = eps;
+    stn[kPhi] = phi;
+    stn[kRes] = fabs(s * phibar);
+    stn[kInvB] = invb;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const double w = (v[i] - delta * w1[i] - eps * w2[i]) * ir;
     w2[i] = w;
     x[i] += phi * w;
@@ -240,14 +254,14 @@ __global__ void lz_update(int64_t n, const double* __restrict__ v, const double*
   }
 }
 
-// state init: beta_1 = ||b|| (from st[kRes] slot holding the norm)
+// state init (slot 0): beta_1 = ||b|| (v_0 = 0)
 __global__ void lz_init(double* st, const double* bnorm) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int k = 0; k < kNState; ++k) st[k] = 0.0;
   st[kC2] = 1.0; st[kC1] = 1.0;
   st[kPhiBar] = *bnorm;
   st[kRes] = *bnorm;
-  st[kBeta] = 0.0;  // v_0 = 0
+  st[kBeta] = 0.0;
 }
 
 inline int grid_n(int64_t n) {
@@ -263,28 +277,45 @@ inline int grid_n(int64_t n) {
 // MINRES coincide in exact arithmetic). Everything stays on the device; the
 // host reads the residual estimate every `check` steps.
 // One Lanczos step on fixed buffers (see precond_solve_sym).
+// Device scalars: [0, kMaxBasis) and [kMaxBasis, 2 kMaxBasis) projections,
+// then norms; the Lanczos state's two slots start at 3.5 kMaxBasis.
+double* Solver::lanczos_state() const { return dsc_ + 3 * kMaxBasis + kMaxBasis / 2; }
+
 void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
-                          hipStream_t s) {
+                          double* stn, hipStream_t s) {
   const int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
-  eng_.fock_apply(v, v + ov, p, p + ov, s);
-  lz_step1<<<kReduceBlocks, 256, 0, s>>>(n, p, vprev, v, st, partials_);
-  lz_reduce<<<1, 256, 0, s>>>(kReduceBlocks, partials_, st, 0);
-  lz_step2<<<kReduceBlocks, 256, 0, s>>>(n, p, v, st, partials_);
-  lz_reduce<<<1, 256, 0, s>>>(kReduceBlocks, partials_, st, 1);
-  lz_scalars<<<1, 1, 0, s>>>(st);
-  lz_update<<<grid_n(n), 256, 0, s>>>(n, v, w1, w2, x, p, st);
+  double* part1 = partials_;
+  double* part2 = partials_ + kMaxFusedParts;
+  const FockOp* op = eng_.fock_op();
+  int nparts1 = kLzBlocks;
+  if (op && op->nparts() <= kMaxFusedParts) {
+    // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p> in one launch
+    Timers* tm = eng_.timers();
+    if (tm) tm->begin(kTimerFock, s);
+    fock_op_lanczos(*op, v, vprev, st + kBeta, p, part1, s);
+    if (tm) tm->end(kTimerFock, s);
+    nparts1 = (int)op->nparts();
+  } else {
+    eng_.fock_apply(v, v + ov, p, p + ov, s);
+    lz_step1<<<kLzBlocks, 256, 0, s>>>(n, p, vprev, v, st, part1);
+  }
+  lz_step2<<<kLzBlocks, 256, 0, s>>>(n, p, v, part1, nparts1, st, part2);
+  lz_update<<<kLzBlocks, 256, 0, s>>>(n, v, w1, w2, x, p, part2, st, stn);
   PNK_CHECK_LAUNCH();
 }
 
-// Six steps: the buffer rotation (v: period 3, w: period 2) returns to its
-// start, so the block can be recorded once as a HIP graph and replayed.
+// Six steps: the buffer rotation (v: period 3, w: period 2, state slot:
+// period 2) returns to its start, so the block can be recorded once as a
+// HIP graph and replayed.
 void Solver::lanczos_block(hipStream_t s) {
   const int64_t n = n_;
-  double* st = dsc_ + 3 * kMaxBasis + kMaxBasis / 2;
+  double* st = lanczos_state();
   double *vprev = Qi_, *v = Qi_ + n, *p = Qi_ + 2 * n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *x = Qi_ + 5 * n;
   for (int k = 0; k < kLanczosBlock; ++k) {
-    lanczos_step(vprev, v, p, w1, w2, x, st, s);
+    double* cur = st + (k % 2) * kStateStride;
+    double* nxt = st + ((k + 1) % 2) * kStateStride;
+    lanczos_step(vprev, v, p, w1, w2, x, cur, nxt, s);
     std::swap(vprev, v);  // v_{k-1} <- v_k
     std::swap(v, p);      // v_k <- v_{k+1}; p <- free buffer
     std::swap(w1, w2);    // w_{k-1} <- w_k
@@ -336,7 +367,7 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
     fill(n, 0.0, x, s);
     return 0;
   }
-  double* st = dsc_ + 3 * kMaxBasis + kMaxBasis / 2;  // state block (kNState doubles)
+  double* st = lanczos_state();  // slot 0 holds the state after every block
   double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *xi = Qi_ + 5 * n;
   lz_init<<<1, 1, 0, s>>>(st, dsc_ + 1);
   scale_by_inverse(n, b, dsc_ + 1, v, s);  // v_1 = b / ||b||

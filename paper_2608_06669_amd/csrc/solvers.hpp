@@ -96,7 +96,9 @@ class Solver {
   bool lz_graph_failed_ = false;
   hipGraphExec_t lz_exec_ = nullptr;
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
-                    hipStream_t s);
+                    double* stn, hipStream_t s);
+  // two state slots of the Lanczos recurrence (device scalars)
+  double* lanczos_state() const;
   void lanczos_block(hipStream_t s);
   bool ensure_lanczos_graph();
   std::vector<double> hist_;

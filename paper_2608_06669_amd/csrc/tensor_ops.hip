@@ -245,12 +245,18 @@ __global__ __launch_bounds__(256) void hash_stage1(int64_t n, const double* __re
   }
   if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
 }
-__global__ void hash_stage2(int nparts, const uint64_t* partials, int64_t n, uint64_t* out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    uint64_t acc = mix64((uint64_t)n);
-    for (int i = 0; i < nparts; ++i) acc += partials[i];
-    *out = mix64(acc);
+__global__ __launch_bounds__(256) void hash_stage2(int nparts, const uint64_t* partials, int64_t n, uint64_t* out) {
+  // integer addition is exact, so the summation order does not matter
+  __shared__ uint64_t sm[256];
+  uint64_t acc = 0;
+  for (int i = threadIdx.x; i < nparts; i += 256) acc += partials[i];
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) *out = mix64(sm[0] + mix64((uint64_t)n));
 }
 
 inline int grid_for(int64_t n, int cap = 4096) {
@@ -377,7 +383,7 @@ void combine(int64_t n, int m, const double* Q, int64_t ldq, const double* y, do
 }
 void hash64(int64_t n, const double* x, uint64_t* out, uint64_t* partials, hipStream_t s) {
   hash_stage1<<<kReduceBlocks, 256, 0, s>>>(n, x, partials);
-  hash_stage2<<<1, 64, 0, s>>>(kReduceBlocks, partials, n, out);
+  hash_stage2<<<1, 256, 0, s>>>(kReduceBlocks, partials, n, out);
   PNK_CHECK_LAUNCH();
 }
 
