@@ -341,6 +341,19 @@ void Engine::mm(const GemmDesc& d, const Ten& A, const Ten& B, const Ten& C) {
   const void *pa, *pb;
   Prec qa, qb;
   GemmDesc e = with_ws(d);
+  if (A.var && B.var) {
+    // dA B + A dB as one launch when the operand precisions agree
+    const void *pa2, *pb2;
+    Prec qa2, qb2;
+    operand(A, true, &pa, &qa);
+    operand(B, false, &pb, &qb);
+    operand(A, false, &pa2, &qa2);
+    operand(B, true, &pb2, &qb2);
+    if (qa == qa2 && qb == qb2) {
+      gemm_sum(e, pa, pb, pa2, pb2, qa, qb, C.d, Prec::F64, jprec_, s_);
+      return;
+    }
+  }
   bool first = true;
   if (A.var) {
     operand(A, true, &pa, &qa);

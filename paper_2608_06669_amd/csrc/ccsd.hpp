@@ -72,6 +72,8 @@ class Timers {
   void end(int slot, hipStream_t s);
   // Synchronises the recorded events and returns (count, total ms).
   void read(int slot, int* count, double* total_ms);
+  // Adds durations measured elsewhere (event nodes inside a graph).
+  void add(int slot, int count, double ms) { count_[slot] += count; total_[slot] += ms; }
   void reset();
 
  private:

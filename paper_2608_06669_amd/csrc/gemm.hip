@@ -52,6 +52,8 @@ struct KArgs {
   int64_t a_m, a_k, a_b0, a_b1;
   const void* B;
   int64_t b_k, b_n, b_b0, b_b1;
+  const void* A2;  // optional second product A2 B2 (same strides as A, B)
+  const void* B2;
   void* C;
   int64_t c_m, c_n, c_b0, c_b1;
   double alpha, beta;
@@ -93,6 +95,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   const int kend = min(p.K, kbeg + p.kchunk);
   const TA* __restrict__ Ag = (const TA*)p.A + b0 * p.a_b0 + b1 * p.a_b1;
   const TB* __restrict__ Bg = (const TB*)p.B + b0 * p.b_b0 + b1 * p.b_b1;
+  const bool dual = p.A2 != nullptr;
+  const TA* __restrict__ Ag2 = dual ? (const TA*)p.A2 + b0 * p.a_b0 + b1 * p.a_b1 : Ag;
+  const TB* __restrict__ Bg2 = dual ? (const TB*)p.B2 + b0 * p.b_b0 + b1 * p.b_b1 : Bg;
   TC* __restrict__ Cg = (TC*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
 
   Acc acc[TMI][TNI];
@@ -106,20 +111,25 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   const bool avec = p.a_vec != 0, bvec = p.b_vec != 0;
   const int64_t a_row = p.a_m, a_kk = p.a_k, b_row = p.b_n, b_kk = p.b_k;
 
-  const int nk = (kend - kbeg + BK - 1) / BK;
+  // panels 0 .. nk1-1 read A, B; with a second product, panels nk1 ..
+  // 2 nk1-1 read A2, B2 over the same k range into the same accumulators
+  const int nk1 = (kend - kbeg + BK - 1) / BK;
+  const int nk = dual ? 2 * nk1 : nk1;
+  auto load = [&](int t) {
+    const bool second = t >= nk1;
+    const int k0 = kbeg + (second ? t - nk1 : t) * BK;
+    pa.load(second ? Ag2 : Ag, a_row, a_kk, m0, p.M, k0, kend, avec, tid);
+    pb.load(second ? Bg2 : Bg, b_row, b_kk, n0, p.N, k0, kend, bvec, tid);
+  };
   if (nk > 0) {
-    pa.load(Ag, a_row, a_kk, m0, p.M, kbeg, kend, avec, tid);
-    pb.load(Bg, b_row, b_kk, n0, p.N, kbeg, kend, bvec, tid);
+    load(0);
     pa.store(As[0], tid);
     pb.store(Bs[0], tid);
     __syncthreads();
   }
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
-    if (kt + 1 < nk) {
-      pa.load(Ag, a_row, a_kk, m0, p.M, kbeg + (kt + 1) * BK, kend, avec, tid);
-      pb.load(Bg, b_row, b_kk, n0, p.N, kbeg + (kt + 1) * BK, kend, bvec, tid);
-    }
+    if (kt + 1 < nk) load(kt + 1);
     const L* Ac = As[cur];
     const L* Bc = Bs[cur];
 #pragma unroll
@@ -218,6 +228,37 @@ __global__ __launch_bounds__(256) void splitk_reduce(KArgs p) {
   }
 }
 
+// The same sum for many splits and few outputs: 16 lanes per output, each
+// adding every 16th split in increasing order, then the 16 lane sums in
+// order (deterministic, and no lane walks all splits).
+template <typename TC>
+__global__ __launch_bounds__(256) void splitk_reduce_wide(KArgs p) {
+  __shared__ double sm[16][17];
+  const int64_t MN = (int64_t)p.M * p.N;
+  const int64_t total = MN * p.nbtot;
+  const int eo = threadIdx.x & 15, sg = threadIdx.x >> 4;
+  for (int64_t e0 = blockIdx.x * (int64_t)16; e0 < total; e0 += (int64_t)gridDim.x * 16) {
+    const int64_t e = e0 + eo;
+    double acc = 0.0;
+    if (e < total)
+      for (int s = sg; s < p.splits; s += 16) acc += p.ws[(int64_t)s * total + e];
+    sm[sg][eo] = acc;
+    __syncthreads();
+    if (sg == 0 && e < total) {
+      double sum = 0.0;
+      for (int g = 0; g < 16; ++g) sum += sm[g][eo];
+      const int64_t b = e / MN;
+      const int m = (int)((e % MN) / p.N), n = (int)(e % p.N);
+      const int b0 = (int)(b % p.nb0), b1 = (int)(b / p.nb0);
+      TC* c = (TC*)p.C + b0 * p.c_b0 + b1 * p.c_b1 + m * p.c_m + n * p.c_n;
+      double v = p.alpha * sum;
+      if (p.beta != 0.0) v += p.beta * load_c<TC>(c);
+      *c = from_acc<TC>(v);
+    }
+    __syncthreads();
+  }
+}
+
 // Products with a short contraction (K <= kSmallK) and a short output side
 // (<= kSmallSide): a matrix-core tile would be mostly padding and the cost
 // is one pass over the long operand. Each lane owns one index of the long
@@ -284,8 +325,11 @@ bool vec_ok(const void* base, int64_t s_row, int64_t s_k, int64_t s_b0, int64_t 
 }
 
 template <class Mma, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WGM>
-void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStream_t s) {
+void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, void* C,
+                hipStream_t s) {
   KArgs p;
+  p.A2 = A2;
+  p.B2 = A2 ? B2 : nullptr;
   p.M = d.M; p.N = d.N; p.K = d.K; p.nb0 = d.nb0;
   p.tiles_m = (int)ceil_div(d.M, BM);
   p.tiles_n = (int)ceil_div(d.N, BN);
@@ -297,8 +341,8 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStr
   p.nbtot = (int)nb;
   const bool akc = d.a_k == 1 && d.a_m != 1;
   const bool bkc = d.b_k == 1 && d.b_n != 1;
-  p.a_vec = vec_ok<TA>(A, d.a_m, d.a_k, d.a_b0, d.a_b1, akc);
-  p.b_vec = vec_ok<TB>(B, d.b_n, d.b_k, d.b_b0, d.b_b1, bkc);
+  p.a_vec = vec_ok<TA>(A, d.a_m, d.a_k, d.a_b0, d.a_b1, akc) && (!A2 || vec_ok<TA>(A2, d.a_m, d.a_k, d.a_b0, d.a_b1, akc));
+  p.b_vec = vec_ok<TB>(B, d.b_n, d.b_k, d.b_b0, d.b_b1, bkc) && (!A2 || vec_ok<TB>(B2, d.b_n, d.b_k, d.b_b0, d.b_b1, bkc));
   // split-K when the output tiles cannot fill the GPU
   int splits = 1;
   const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n * nb;
@@ -327,7 +371,10 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, void* C, hipStr
   PNK_CHECK_LAUNCH();
   if (splits > 1) {
     const int64_t total = nb * d.M * d.N;
-    splitk_reduce<TC><<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 4096), 256, 0, s>>>(p);
+    if (splits >= 32)
+      splitk_reduce_wide<TC><<<(unsigned)std::min<int64_t>(ceil_div(total, 16), 8192), 256, 0, s>>>(p);
+    else
+      splitk_reduce<TC><<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 4096), 256, 0, s>>>(p);
     PNK_CHECK_LAUNCH();
   }
 }
@@ -342,7 +389,8 @@ double util(int64_t M, int64_t N, int bm, int bn) {
 // (M = nocc^2 or nocc(nocc+1)/2 is rarely a multiple of 128). FP32/BF16:
 // 128 x 128. Small products: 64 x 64 (split-K fills the GPU).
 template <class Mma, typename TA, typename TB, typename TC, int BK>
-void launch_sized(const GemmDesc& d, const void* A, const void* B, void* C, hipStream_t s) {
+void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, void* C,
+                  hipStream_t s) {
   const int64_t nb = (int64_t)d.nb0 * d.nb1;
   if constexpr (sizeof(typename Mma::L) == 8) {
     const int64_t tiles = ceil_div(d.M, 128) * ceil_div(d.N, 64) * nb;
@@ -356,32 +404,42 @@ void launch_sized(const GemmDesc& d, const void* A, const void* B, void* C, hipS
       for (const Opt& o : opts)
         if (o.score > best.score + 1e-9) best = o;
       switch (best.bm) {
-        case 112: launch_cfg<Mma, TA, TB, TC, 112, 64, BK, 2>(d, A, B, C, s); return;
-        case 96: launch_cfg<Mma, TA, TB, TC, 96, 64, BK, 2>(d, A, B, C, s); return;
-        case 80: launch_cfg<Mma, TA, TB, TC, 80, 64, BK, 2>(d, A, B, C, s); return;
-        default: launch_cfg<Mma, TA, TB, TC, 128, 64, BK, 2>(d, A, B, C, s); return;
+        case 112: launch_cfg<Mma, TA, TB, TC, 112, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
+        case 96: launch_cfg<Mma, TA, TB, TC, 96, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
+        case 80: launch_cfg<Mma, TA, TB, TC, 80, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
+        default: launch_cfg<Mma, TA, TB, TC, 128, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
       }
     }
-    launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, C, s);
+    launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
     return;
   }
   const int64_t big = ceil_div(d.M, 128) * ceil_div(d.N, 128) * nb;
-  if (d.M >= 64 && d.N >= 96 && big >= 256) launch_cfg<Mma, TA, TB, TC, 128, 128, BK, 2>(d, A, B, C, s);
-  else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, C, s);
+  if (d.M >= 64 && d.N >= 96 && big >= 256) launch_cfg<Mma, TA, TB, TC, 128, 128, BK, 2>(d, A, B, A2, B2, C, s);
+  else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
 }
 
 }  // namespace
 
-void gemm(const GemmDesc& d, const void* A, Prec ap, const void* B, Prec bp, void* C, Prec cp, Prec compute,
-          hipStream_t s) {
+namespace {
+
+void gemm_impl(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, Prec ap, Prec bp,
+               void* C, Prec cp, Prec compute, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.nb0 <= 0 || d.nb1 <= 0) return;
   PNK_REQUIRE(cp == Prec::F64 || cp == Prec::F32, "gemm: C must be f64 or f32");
   PNK_REQUIRE(d.K > 0, "gemm: K must be positive");
-#define PNK_GEMM_CASE(MMA, TA, TB, TC, BK) return launch_sized<MMA, TA, TB, TC, BK>(d, A, B, C, s)
+#define PNK_GEMM_CASE(MMA, TA, TB, TC, BK) return launch_sized<MMA, TA, TB, TC, BK>(d, A, B, A2, B2, C, s)
   if (compute == Prec::F64) {
     PNK_REQUIRE(ap == Prec::F64 && bp == Prec::F64, "gemm: f64 compute needs f64 operands");
     PNK_REQUIRE(cp == Prec::F64, "gemm: f64 compute writes f64");
-    if (d.K <= kSmallK && std::min(d.M, d.N) <= kSmallSide) return launch_smallk(d, A, B, C, s);
+    if (d.K <= kSmallK && std::min(d.M, d.N) <= kSmallSide) {
+      launch_smallk(d, A, B, C, s);
+      if (A2) {
+        GemmDesc e = d;
+        e.beta = 1.0;
+        launch_smallk(e, A2, B2, C, s);
+      }
+      return;
+    }
     PNK_GEMM_CASE(MmaF64, double, double, double, 16);
   }
   if (compute == Prec::F32) {
@@ -400,6 +458,19 @@ void gemm(const GemmDesc& d, const void* A, Prec ap, const void* B, Prec bp, voi
   }
 #undef PNK_GEMM_CASE
   PNK_REQUIRE(false, "gemm: unsupported precision combination");
+}
+
+}  // namespace
+
+void gemm(const GemmDesc& d, const void* A, Prec ap, const void* B, Prec bp, void* C, Prec cp, Prec compute,
+          hipStream_t s) {
+  gemm_impl(d, A, B, nullptr, nullptr, ap, bp, C, cp, compute, s);
+}
+
+void gemm_sum(const GemmDesc& d, const void* A1, const void* B1, const void* A2, const void* B2, Prec ap, Prec bp,
+              void* C, Prec cp, Prec compute, hipStream_t s) {
+  PNK_REQUIRE(A2 && B2, "gemm_sum: second product missing");
+  gemm_impl(d, A1, B1, A2, B2, ap, bp, C, cp, compute, s);
 }
 
 }  // namespace pnk

@@ -31,11 +31,17 @@ struct GemmDesc {
 };
 
 // Pointers carry their storage precision; `compute` selects the matrix-core
-// instruction (F64: 16x16x4 f64; F32: 16x16x4 f32; BF16: 16x16x32 bf16),
+// instruction (F64: 4x4x4 f64; F32: 16x16x4 f32; BF16: 16x16x32 bf16),
 // with float accumulation for F32 and BF16. Operands stored in a wider type
 // are rounded to the compute type while being staged into LDS.
 void gemm(const GemmDesc& d, const void* A, Prec a_prec, const void* B, Prec b_prec,
           void* C, Prec c_prec, Prec compute, hipStream_t stream);
+
+// C = alpha (A1 B1 + A2 B2) + beta C in one launch: both products share
+// strides, storage precisions (ap for A1, A2; bp for B1, B2) and the
+// contraction length, and accumulate into the same registers.
+void gemm_sum(const GemmDesc& d, const void* A1, const void* B1, const void* A2, const void* B2, Prec ap, Prec bp,
+              void* C, Prec cp, Prec compute, hipStream_t stream);
 
 // Convenience for all-FP64 products.
 inline void gemm64(const GemmDesc& d, const double* A, const double* B, double* C,

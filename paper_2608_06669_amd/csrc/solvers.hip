@@ -91,6 +91,9 @@ Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_
 
 Solver::~Solver() {
   if (lz_exec_) (void)hipGraphExecDestroy(lz_exec_);
+  if (lz_exec_timed_) (void)hipGraphExecDestroy(lz_exec_timed_);
+  for (hipEvent_t e : lz_ev_)
+    if (e) (void)hipEventDestroy(e);
   for (double* p : {Qo_, Qi_, r_, ri_, w_, w2_, hx_, he_, dsc_, partials_})
     if (p) (void)(async_ ? hipFreeAsync(p, alloc_stream_) : hipFree(p));
   if (host_) (void)hipHostFree(host_);
@@ -282,7 +285,7 @@ inline int grid_n(int64_t n) {
 double* Solver::lanczos_state() const { return dsc_ + 3 * kMaxBasis + kMaxBasis / 2; }
 
 void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
-                          double* stn, hipStream_t s) {
+                          double* stn, hipStream_t s, hipEvent_t* ev) {
   const int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
   double* part1 = partials_;
@@ -291,10 +294,14 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
   int nparts1 = kLzBlocks;
   if (op && op->nparts() <= kMaxFusedParts) {
     // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p> in one launch
+    // (inside a recorded graph, `ev` brackets the launch with external
+    // event nodes so its duration can be read after every replay)
     Timers* tm = eng_.timers();
-    if (tm) tm->begin(kTimerFock, s);
+    if (ev) PNK_HIP(hipEventRecordWithFlags(ev[0], s, hipEventRecordExternal));
+    else if (tm) tm->begin(kTimerFock, s);
     fock_op_lanczos(*op, v, vprev, st + kBeta, p, part1, s);
-    if (tm) tm->end(kTimerFock, s);
+    if (ev) PNK_HIP(hipEventRecordWithFlags(ev[1], s, hipEventRecordExternal));
+    else if (tm) tm->end(kTimerFock, s);
     nparts1 = (int)op->nparts();
   } else {
     eng_.fock_apply(v, v + ov, p, p + ov, s);
@@ -308,36 +315,44 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
 // Six steps: the buffer rotation (v: period 3, w: period 2, state slot:
 // period 2) returns to its start, so the block can be recorded once as a
 // HIP graph and replayed.
-void Solver::lanczos_block(hipStream_t s) {
+void Solver::lanczos_block(hipStream_t s, hipEvent_t* ev) {
   const int64_t n = n_;
   double* st = lanczos_state();
   double *vprev = Qi_, *v = Qi_ + n, *p = Qi_ + 2 * n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *x = Qi_ + 5 * n;
   for (int k = 0; k < kLanczosBlock; ++k) {
     double* cur = st + (k % 2) * kStateStride;
     double* nxt = st + ((k + 1) % 2) * kStateStride;
-    lanczos_step(vprev, v, p, w1, w2, x, cur, nxt, s);
+    lanczos_step(vprev, v, p, w1, w2, x, cur, nxt, s, ev ? ev + 2 * k : nullptr);
     std::swap(vprev, v);  // v_{k-1} <- v_k
     std::swap(v, p);      // v_k <- v_{k+1}; p <- free buffer
     std::swap(w1, w2);    // w_{k-1} <- w_k
   }
 }
 
-bool Solver::ensure_lanczos_graph() {
-  if (lz_exec_) return true;
-  if (lz_graph_failed_) return false;
+// Records the six-step block as a HIP graph. The timed variant also holds
+// external event nodes around each fused A_F launch (used only while the
+// engine's timers are on).
+bool Solver::ensure_lanczos_graph(bool timed) {
+  hipGraphExec_t& exec = timed ? lz_exec_timed_ : lz_exec_;
+  bool& failed = timed ? lz_timed_failed_ : lz_graph_failed_;
+  if (exec) return true;
+  if (failed) return false;
+  if (timed && !lz_ev_[0]) {
+    for (auto& e : lz_ev_)
+      if (hipEventCreate(&e) != hipSuccess) { failed = true; return false; }
+  }
   Timers* tm = eng_.timers();
-  eng_.set_timers(nullptr);  // no event records inside a graph
+  eng_.set_timers(nullptr);  // no host-side timer events inside a graph
   bool ok = false;
   hipStream_t cs = nullptr;
   hipGraph_t g = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
       hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
     try {
-      lanczos_block(cs);
+      lanczos_block(cs, timed ? lz_ev_ : nullptr);
     } catch (...) {
     }
-    if (hipStreamEndCapture(cs, &g) == hipSuccess && g &&
-        hipGraphInstantiate(&lz_exec_, g, nullptr, nullptr, 0) == hipSuccess)
+    if (hipStreamEndCapture(cs, &g) == hipSuccess && g && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
       ok = true;
   }
   if (g) (void)hipGraphDestroy(g);
@@ -345,8 +360,8 @@ bool Solver::ensure_lanczos_graph() {
   (void)hipGetLastError();
   eng_.set_timers(tm);
   if (!ok) {
-    lz_exec_ = nullptr;
-    lz_graph_failed_ = true;
+    exec = nullptr;
+    failed = true;
   }
   return ok;
 }
@@ -376,14 +391,24 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   fill(n, 0.0, w2, s);
   fill(n, 0.0, xi, s);
   PNK_CHECK_LAUNCH();
-  const bool graph = use_graphs_ && ensure_lanczos_graph();
+  Timers* tm = eng_.timers();
+  const FockOp* op = eng_.fock_op();
+  const bool fused = op && op->nparts() <= kMaxFusedParts;
+  const bool timed = use_graphs_ && tm && fused && ensure_lanczos_graph(true);
+  const bool graph = timed || (use_graphs_ && ensure_lanczos_graph(false));
   int it = 0;
   bool conv = false;
   while (it < maxit) {
-    if (graph) PNK_HIP(hipGraphLaunch(lz_exec_, s));
+    if (graph) PNK_HIP(hipGraphLaunch(timed ? lz_exec_timed_ : lz_exec_, s));
     else lanczos_block(s);
     it += kLanczosBlock;
-    read_scalars(host_, st, kNState, s);
+    read_scalars(host_, st, kNState, s);  // synchronises the stream
+    if (timed)
+      for (int k = 0; k < kLanczosBlock; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, lz_ev_[2 * k], lz_ev_[2 * k + 1]) == hipSuccess) tm->add(kTimerFock, 1, ms);
+        else (void)hipGetLastError();
+      }
     const double res = host_[kRes];
     if (!std::isfinite(res)) break;
     if (res <= rtol * bn || host_[kBeta] == 0.0) { conv = true; break; }

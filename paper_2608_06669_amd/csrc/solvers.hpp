@@ -95,12 +95,15 @@ class Solver {
   bool use_graphs_ = true;
   bool lz_graph_failed_ = false;
   hipGraphExec_t lz_exec_ = nullptr;
+  hipGraphExec_t lz_exec_timed_ = nullptr;
+  bool lz_timed_failed_ = false;
+  hipEvent_t lz_ev_[2 * kLanczosBlock] = {};
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
-                    double* stn, hipStream_t s);
+                    double* stn, hipStream_t s, hipEvent_t* ev = nullptr);
   // two state slots of the Lanczos recurrence (device scalars)
   double* lanczos_state() const;
-  void lanczos_block(hipStream_t s);
-  bool ensure_lanczos_graph();
+  void lanczos_block(hipStream_t s, hipEvent_t* ev = nullptr);
+  bool ensure_lanczos_graph(bool timed);
   std::vector<double> hist_;
 };
 
