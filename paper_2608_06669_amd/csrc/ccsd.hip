@@ -26,6 +26,8 @@
 #include "fock_op.hpp"
 
 #include <algorithm>
+#include <cstdlib>
+#include <cstdio>
 #include <cstring>
 
 #include "cc_kernels.hpp"
@@ -268,11 +270,15 @@ bool Engine::capture(Mode m, GraphSlot* slot) {
   hipGraph_t g = nullptr;
   bool ok = false;
   if (hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    // a failure while recording must not leave a partial graph behind
+    bool threw = false;
     try {
       run(m);
-    } catch (...) {
+    } catch (const std::exception& e) {
+      threw = true;
+      if (std::getenv("PNK_DEBUG")) std::fprintf(stderr, "pnk: graph capture failed: %s\n", e.what());
     }
-    if (hipStreamEndCapture(cap_, &g) == hipSuccess && g &&
+    if (hipStreamEndCapture(cap_, &g) == hipSuccess && g && !threw &&
         hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0) == hipSuccess)
       ok = true;
   }

@@ -241,6 +241,12 @@ bool fock_op_plan(FockOp& op) {
   return op.gx <= 65535 && op.gy <= 65535;
 }
 
+bool fock_op_is_lanczos_kernel(const void* func) {
+  return func == reinterpret_cast<const void*>(&fock_op_kernel<32, 2, true>) ||
+         func == reinterpret_cast<const void*>(&fock_op_kernel<48, 4, true>) ||
+         func == reinterpret_cast<const void*>(&fock_op_kernel<64, 2, true>);
+}
+
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s) {
   launch<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, s);
 }

@@ -40,4 +40,8 @@ void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double*
 void fock_op_lanczos(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
                      double* partials, hipStream_t s);
 
+// True for the kernel function that fock_op_lanczos launches (used to find
+// its nodes in a recorded graph).
+bool fock_op_is_lanczos_kernel(const void* func);
+
 }  // namespace pnk

@@ -17,7 +17,10 @@
 #include "fock_op.hpp"
 
 #include <chrono>
+#include <cstdlib>
+#include <cstdio>
 #include <cmath>
+#include <vector>
 
 #include "cc_kernels.hpp"
 #include "tensor_ops.hpp"
@@ -285,7 +288,7 @@ inline int grid_n(int64_t n) {
 double* Solver::lanczos_state() const { return dsc_ + 3 * kMaxBasis + kMaxBasis / 2; }
 
 void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
-                          double* stn, hipStream_t s, hipEvent_t* ev) {
+                          double* stn, hipStream_t s) {
   const int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
   double* part1 = partials_;
@@ -294,14 +297,10 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
   int nparts1 = kLzBlocks;
   if (op && op->nparts() <= kMaxFusedParts) {
     // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p> in one launch
-    // (inside a recorded graph, `ev` brackets the launch with external
-    // event nodes so its duration can be read after every replay)
     Timers* tm = eng_.timers();
-    if (ev) PNK_HIP(hipEventRecordWithFlags(ev[0], s, hipEventRecordExternal));
-    else if (tm) tm->begin(kTimerFock, s);
+    if (tm) tm->begin(kTimerFock, s);
     fock_op_lanczos(*op, v, vprev, st + kBeta, p, part1, s);
-    if (ev) PNK_HIP(hipEventRecordWithFlags(ev[1], s, hipEventRecordExternal));
-    else if (tm) tm->end(kTimerFock, s);
+    if (tm) tm->end(kTimerFock, s);
     nparts1 = (int)op->nparts();
   } else {
     eng_.fock_apply(v, v + ov, p, p + ov, s);
@@ -315,22 +314,65 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
 // Six steps: the buffer rotation (v: period 3, w: period 2, state slot:
 // period 2) returns to its start, so the block can be recorded once as a
 // HIP graph and replayed.
-void Solver::lanczos_block(hipStream_t s, hipEvent_t* ev) {
+void Solver::lanczos_block(hipStream_t s) {
   const int64_t n = n_;
   double* st = lanczos_state();
   double *vprev = Qi_, *v = Qi_ + n, *p = Qi_ + 2 * n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *x = Qi_ + 5 * n;
   for (int k = 0; k < kLanczosBlock; ++k) {
     double* cur = st + (k % 2) * kStateStride;
     double* nxt = st + ((k + 1) % 2) * kStateStride;
-    lanczos_step(vprev, v, p, w1, w2, x, cur, nxt, s, ev ? ev + 2 * k : nullptr);
+    lanczos_step(vprev, v, p, w1, w2, x, cur, nxt, s);
     std::swap(vprev, v);  // v_{k-1} <- v_k
     std::swap(v, p);      // v_k <- v_{k+1}; p <- free buffer
     std::swap(w1, w2);    // w_{k-1} <- w_k
   }
 }
 
+namespace {
+
+// Brackets every fused A_F kernel node of a recorded graph with two event
+// record nodes (ev[2k], ev[2k+1]) so each launch's duration can be read
+// after a replay. Returns the number of nodes bracketed, -1 on error.
+int bracket_fock_nodes(hipGraph_t g, hipEvent_t* ev, int max_pairs) {
+  size_t nn = 0;
+  if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return -1;
+  std::vector<hipGraphNode_t> nodes(nn);
+  if (hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return -1;
+  int k = 0;
+  for (hipGraphNode_t node : nodes) {
+    hipGraphNodeType type;
+    if (hipGraphNodeGetType(node, &type) != hipSuccess) return -1;
+    if (type != hipGraphNodeTypeKernel) continue;
+    hipKernelNodeParams kp{};
+    if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) return -1;
+    if (!fock_op_is_lanczos_kernel(kp.func)) continue;
+    if (k >= max_pairs) return -1;
+    size_t nd = 0, ns = 0;
+    if (hipGraphNodeGetDependencies(node, nullptr, &nd) != hipSuccess) return -1;
+    std::vector<hipGraphNode_t> deps(nd);
+    if (nd && hipGraphNodeGetDependencies(node, deps.data(), &nd) != hipSuccess) return -1;
+    if (hipGraphNodeGetDependentNodes(node, nullptr, &ns) != hipSuccess) return -1;
+    std::vector<hipGraphNode_t> succ(ns);
+    if (ns && hipGraphNodeGetDependentNodes(node, succ.data(), &ns) != hipSuccess) return -1;
+    hipGraphNode_t e1, e2;
+    if (hipGraphAddEventRecordNode(&e1, g, deps.data(), nd, ev[2 * k]) != hipSuccess) return -1;
+    for (hipGraphNode_t d : deps)
+      if (hipGraphRemoveDependencies(g, &d, &node, 1) != hipSuccess) return -1;
+    if (hipGraphAddDependencies(g, &e1, &node, 1) != hipSuccess) return -1;
+    if (hipGraphAddEventRecordNode(&e2, g, &node, 1, ev[2 * k + 1]) != hipSuccess) return -1;
+    for (hipGraphNode_t sn : succ) {
+      if (hipGraphRemoveDependencies(g, &node, &sn, 1) != hipSuccess) return -1;
+      if (hipGraphAddDependencies(g, &e2, &sn, 1) != hipSuccess) return -1;
+    }
+    ++k;
+  }
+  return k;
+}
+
+}  // namespace
+
 // Records the six-step block as a HIP graph. The timed variant also holds
-// external event nodes around each fused A_F launch (used only while the
+// event record nodes around each fused A_F launch (used only while the
 // engine's timers are on).
 bool Solver::ensure_lanczos_graph(bool timed) {
   hipGraphExec_t& exec = timed ? lz_exec_timed_ : lz_exec_;
@@ -348,11 +390,17 @@ bool Solver::ensure_lanczos_graph(bool timed) {
   hipGraph_t g = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess &&
       hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+    // a failure while recording must not leave a partial graph behind
+    bool threw = false;
     try {
-      lanczos_block(cs, timed ? lz_ev_ : nullptr);
-    } catch (...) {
+      lanczos_block(cs);
+    } catch (const std::exception& e) {
+      threw = true;
+      if (std::getenv("PNK_DEBUG")) std::fprintf(stderr, "pnk: graph capture failed: %s\n", e.what());
     }
-    if (hipStreamEndCapture(cs, &g) == hipSuccess && g && hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
+    if (hipStreamEndCapture(cs, &g) == hipSuccess && g && !threw &&
+        (!timed || bracket_fock_nodes(g, lz_ev_, kLanczosBlock) == kLanczosBlock) &&
+        hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
       ok = true;
   }
   if (g) (void)hipGraphDestroy(g);
@@ -360,6 +408,7 @@ bool Solver::ensure_lanczos_graph(bool timed) {
   (void)hipGetLastError();
   eng_.set_timers(tm);
   if (!ok) {
+    if (std::getenv("PNK_DEBUG")) std::fprintf(stderr, "pnk: no %s inner-solve graph\n", timed ? "timed" : "plain");
     exec = nullptr;
     failed = true;
   }

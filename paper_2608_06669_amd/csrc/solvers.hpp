@@ -99,10 +99,10 @@ class Solver {
   bool lz_timed_failed_ = false;
   hipEvent_t lz_ev_[2 * kLanczosBlock] = {};
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
-                    double* stn, hipStream_t s, hipEvent_t* ev = nullptr);
+                    double* stn, hipStream_t s);
   // two state slots of the Lanczos recurrence (device scalars)
   double* lanczos_state() const;
-  void lanczos_block(hipStream_t s, hipEvent_t* ev = nullptr);
+  void lanczos_block(hipStream_t s);
   bool ensure_lanczos_graph(bool timed);
   std::vector<double> hist_;
 };

@@ -248,6 +248,25 @@ def test_fp_diis_c1_matches_oracle(handle, lib):
     assert info6["n_residual"] == ia6.n_residual
 
 
+
+def test_timed_solve_matches_untimed(handle, lib):
+    """Timing instrumentation (events around the fused A_F launches inside
+    the replayed inner-solve graph) changes nothing in the solve."""
+    p = make_problem(4, 18, 40, 53, gauge="haar")
+    P = lib.DeviceProblem.from_problem(p)
+    _, _, ref = handle.solve_pnk(P, tol_inf=1e-10)
+    handle.timing(True)
+    try:
+        _, _, got = handle.solve_pnk(P, tol_inf=1e-10)
+        n_af, _ = handle.timing_read(3)
+    finally:
+        handle.timing(False)
+    assert ref["status"] == got["status"] == "CC_OK"
+    assert got["e_corr"] == ref["e_corr"]
+    for k in ("newton_iters", "n_residual", "n_jvp", "n_afmv"):
+        assert got[k] == ref[k], k
+    assert n_af > 0
+
 def test_pnk_c2_root_is_an_oracle_root(handle, lib):
     """FP64 PNK on the Haar-rotated workload (o=10, v=90, naux=300) to its
     stated stopping test, max |R| < 1e-8. The synthetic Hamiltonian is
