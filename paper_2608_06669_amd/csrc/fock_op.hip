@@ -1,17 +1,20 @@
-// Fused Fock operator (see fock_op.hpp).
+// Fock operator A_F in two launches (see fock_op.hpp).
 //
-// One workgroup computes a BM x BM block (a, b) of y_ij for one occupied
-// pair (i, j). The two virtual contractions form a single matrix-core
-// product over a contraction of length 2v: panels 0 .. nkp-1 multiply
-// f_vv[a][c] by x_ij[c][b], panels nkp .. 2nkp-1 multiply x_ij[a][c] by
-// f_vv[c][b] (f_vv is symmetric), so both accumulate into the same
-// registers with the FP64 4x4x4 matrix-core instruction and LDS double
-// buffering. The two occupied contractions are short (length o) and are
-// added in the epilogue from global memory (the o slices x_kj and x_ik of
-// the block are read once each per workgroup and hit L2), with the f_oo
-// columns i and j staged in LDS. One extra row of workgroups computes the
-// singles. With the Lanczos fusion the epilogue also forms
-// p = y - beta v_{k-1} and a fixed-order per-workgroup partial of <v_k, p>.
+// Virtual kernel: one workgroup computes a bm x bm block (a, b) of
+// y_ij = f_vv x_ij + x_ij f_vv for one occupied pair (i, j). The two
+// contractions form a single matrix-core product over a contraction of
+// length 2v: panels 0 .. nkp-1 multiply f_vv[a][c] by x_ij[c][b], panels
+// nkp .. 2nkp-1 multiply x_ij[a][c] by f_vv[c][b] (f_vv is symmetric), so
+// both accumulate into the same registers (FP64 4x4x4 matrix-core
+// instruction, LDS double buffering).
+//
+// Occupied kernel: the two occupied contractions are short (length o) but
+// touch o slices of x per output; done per output they re-read x 2o times.
+// Instead one workgroup stages x[:, :, chunk] (all o^2 pairs for a chunk of
+// ch consecutive (a, b)) in LDS once and forms both sums for every pair
+// from there, so x is read from memory once. The same launch adds the
+// virtual part, applies the Lanczos update and sums <v_k, p> per workgroup.
+// Trailing workgroups compute the singles, 16 lanes per output.
 
 #include "fock_op.hpp"
 #include "mfma_tiles.hpp"
@@ -23,26 +26,18 @@ namespace {
 
 using namespace tiles;
 
-struct FockKArgs {
-  int o, v, tiles_m, tiles;
+struct VirArgs {
+  int v, tiles_m;
   int vec;  // 16-byte operand loads allowed
-  const double* f_oo;
   const double* f_vv;
-  const double* x1;  // singles and doubles blocks of the input
   const double* x2;
-  double* y1;        // ... and of the output
   double* y2;
-  const double* vprev1;
-  const double* vprev2;
-  const double* beta;
-  double* partials;
 };
 
-template <int BM, int WGM, bool LZ>
-__global__ __launch_bounds__(256) void fock_op_kernel(FockKArgs p) {
+template <int BM, int WGM, int BK>
+__global__ __launch_bounds__(256) void fock_vir_kernel(VirArgs p) {
   using Mma = MmaF64;
   constexpr int BN = BM;
-  constexpr int BK = 16;
   constexpr int WGN = 4 / WGM;
   constexpr int WTM = BM / WGM, WTN = BN / WGN;
   constexpr int TMI = WTM / Mma::TM, TNI = WTN / Mma::TN;
@@ -51,117 +46,165 @@ __global__ __launch_bounds__(256) void fock_op_kernel(FockKArgs p) {
   constexpr int BLDS = lds_elems<Mma, BN, BK>();
   __shared__ __attribute__((aligned(16))) double As[2][ALDS];
   __shared__ __attribute__((aligned(16))) double Bs[2][BLDS];
-  __shared__ double fi[kFockOpMaxOcc];
-  __shared__ double fj[kFockOpMaxOcc];
-  __shared__ double red[256];
 
-  const int o = p.o, v = p.v;
-  const int64_t ov = (int64_t)o * v, vv = (int64_t)v * v;
-  const double* __restrict__ x1 = p.x1;
-  const double* __restrict__ x2 = p.x2;
+  const int v = p.v;
+  const int64_t vv = (int64_t)v * v;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int pair = blockIdx.y;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const int m0 = (blockIdx.x % p.tiles_m) * BM;
+  const int n0 = (blockIdx.x / p.tiles_m) * BN;
+  const double* __restrict__ X = p.x2 + (int64_t)blockIdx.y * vv;
+  const double* __restrict__ F = p.f_vv;
+  const bool vec = p.vec != 0;
+  const int nkp = (v + BK - 1) / BK;
+  const int nk = 2 * nkp;
+
+  double acc[TMI][TNI];
+#pragma unroll
+  for (int a = 0; a < TMI; ++a)
+#pragma unroll
+    for (int b = 0; b < TNI; ++b) acc[a][b] = 0.0;
+
+  Panel<Mma, double, BM, BK, true> pa;   // A[a][c], contiguous along c
+  Panel<Mma, double, BN, BK, false> pb;  // B[c][b], contiguous along b
+  auto load = [&](int t) {
+    const int ph = t >= nkp ? 1 : 0;
+    const int k0 = (t - ph * nkp) * BK;
+    pa.load(ph ? X : F, v, 1, m0, v, k0, v, vec, tid);
+    pb.load(ph ? F : X, 1, v, n0, v, k0, v, vec, tid);
+  };
+  load(0);
+  pa.store(As[0], tid);
+  pb.store(Bs[0], tid);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
+    const double* Ac = As[cur];
+    const double* Bc = Bs[cur];
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += Mma::KSTEP) {
+      const int kk = ks + (lane >> 4);
+      double af[TMI], bf[TNI];
+#pragma unroll
+      for (int a = 0; a < TMI; ++a) af[a] = Ac[kk * (BM + kPad) + wm * WTM + a * 4 + (lane & 3)];
+#pragma unroll
+      for (int b = 0; b < TNI; ++b) bf[b] = Bc[kk * (BN + kPad) + wn * WTN + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TMI; ++a)
+#pragma unroll
+        for (int b = 0; b < TNI; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) {
+      pa.store(As[cur ^ 1], tid);
+      pb.store(Bs[cur ^ 1], tid);
+    }
+    __syncthreads();
+  }
+
+  double* __restrict__ Y = p.y2 + (int64_t)blockIdx.y * vv;
+#pragma unroll
+  for (int a = 0; a < TMI; ++a)
+#pragma unroll
+    for (int b = 0; b < TNI; ++b) {
+      const int ga = m0 + wm * WTM + a * 4 + (lane >> 4);
+      const int gb = n0 + wn * WTN + b * 16 + (lane & 15);
+      if (ga < v && gb < v) Y[(int64_t)ga * v + gb] = acc[a][b];
+    }
+}
+
+struct OccArgs {
+  int o, v, ch, nchunks;
+  const double* f_oo;
+  const double* f_vv;
+  const double* x1;
+  const double* x2;
+  double* y1;
+  double* y2;  // holds the virtual part on entry
+  const double* vprev1;
+  const double* vprev2;
+  const double* beta;
+  double* partials;
+};
+
+// Dynamic LDS: xs[o*o][ch] then fo[o][o].
+template <bool LZ>
+__global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
+  extern __shared__ double lds[];
+  __shared__ double red[256];
+  const int o = p.o, v = p.v, ch = p.ch;
+  const int oo = o * o;
+  const int64_t vv = (int64_t)v * v, ov = (int64_t)o * v;
+  const int tid = threadIdx.x;
   double beta = 0.0;
   if constexpr (LZ) beta = *p.beta;
   double dot = 0.0;
 
-  if (pair < o * o) {
-    if ((int)blockIdx.x < p.tiles) {  // uniform over the workgroup
-      const int i = pair / o, j = pair % o;
-      for (int k = tid; k < o; k += 256) {
-        fi[k] = p.f_oo[(int64_t)k * o + i];
-        fj[k] = p.f_oo[(int64_t)k * o + j];
-      }
-      const int wm = wave / WGN, wn = wave % WGN;
-      const int m0 = (blockIdx.x % p.tiles_m) * BM;
-      const int n0 = (blockIdx.x / p.tiles_m) * BN;
-      const double* __restrict__ X = x2 + (int64_t)pair * vv;
-      const double* __restrict__ F = p.f_vv;
-      const bool vec = p.vec != 0;
-      const int nkp = (v + BK - 1) / BK;
-      const int nk = 2 * nkp;
-
-      double acc[TMI][TNI];
+  if ((int)blockIdx.x < p.nchunks) {
+    double* xs = lds;
+    double* fo = lds + (int64_t)oo * ch;
+    const int64_t ab0 = (int64_t)blockIdx.x * ch;
+    for (int q = tid; q < oo * ch; q += 256) {
+      const int pr = q / ch, e = q % ch;
+      xs[q] = ab0 + e < vv ? p.x2[(int64_t)pr * vv + ab0 + e] : 0.0;
+    }
+    for (int q = tid; q < oo; q += 256) fo[q] = p.f_oo[q];
+    __syncthreads();
+    const int e = tid % ch;
+    const int groups = 256 / ch;
+    if (ab0 + e < vv) {
+      // four pairs per round: their global loads are issued together
+      constexpr int R = 4;
+      for (int pr0 = tid / ch; pr0 < oo; pr0 += R * groups) {
+        double yin[R], vin[R];
 #pragma unroll
-      for (int a = 0; a < TMI; ++a)
-#pragma unroll
-        for (int b = 0; b < TNI; ++b) acc[a][b] = 0.0;
-
-      Panel<Mma, double, BM, BK, true> pa;   // A[a][c], contiguous along c
-      Panel<Mma, double, BN, BK, false> pb;  // B[c][b], contiguous along b
-      auto load = [&](int t) {
-        const int ph = t >= nkp ? 1 : 0;
-        const int k0 = (t - ph * nkp) * BK;
-        pa.load(ph ? X : F, v, 1, m0, v, k0, v, vec, tid);
-        pb.load(ph ? F : X, 1, v, n0, v, k0, v, vec, tid);
-      };
-      load(0);
-      pa.store(As[0], tid);
-      pb.store(Bs[0], tid);
-      __syncthreads();
-      for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) load(kt + 1);
-        const double* Ac = As[cur];
-        const double* Bc = Bs[cur];
-#pragma unroll
-        for (int ks = 0; ks < BK; ks += Mma::KSTEP) {
-          const int kk = ks + (lane >> 4);
-          double af[TMI], bf[TNI];
-#pragma unroll
-          for (int a = 0; a < TMI; ++a) af[a] = Ac[kk * (BM + kPad) + wm * WTM + a * 4 + (lane & 3)];
-#pragma unroll
-          for (int b = 0; b < TNI; ++b) bf[b] = Bc[kk * (BN + kPad) + wn * WTN + b * 16 + (lane & 15)];
-#pragma unroll
-          for (int a = 0; a < TMI; ++a)
-#pragma unroll
-            for (int b = 0; b < TNI; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+        for (int r = 0; r < R; ++r) {
+          const int pr = pr0 + r * groups;
+          const int64_t idx = (int64_t)(pr < oo ? pr : 0) * vv + ab0 + e;
+          yin[r] = p.y2[idx];
+          if constexpr (LZ) vin[r] = p.vprev2[idx];
         }
-        if (kt + 1 < nk) {
-          pa.store(As[cur ^ 1], tid);
-          pb.store(Bs[cur ^ 1], tid);
-        }
-        __syncthreads();
-      }
-
-      const double* __restrict__ xkj = x2 + (int64_t)j * vv;           // + k o v^2
-      const double* __restrict__ xik = x2 + (int64_t)i * o * vv;       // + k v^2
-      const int64_t step_kj = (int64_t)o * vv;
 #pragma unroll
-      for (int a = 0; a < TMI; ++a)
-#pragma unroll
-        for (int b = 0; b < TNI; ++b) {
-          const int ga = m0 + wm * WTM + a * 4 + (lane >> 4);
-          const int gb = n0 + wn * WTN + b * 16 + (lane & 15);
-          if (ga >= v || gb >= v) continue;
-          const int64_t ab = (int64_t)ga * v + gb;
-          double y = acc[a][b];
-          for (int k = 0; k < o; ++k) y -= fi[k] * xkj[k * step_kj + ab] + fj[k] * xik[k * vv + ab];
-          const int64_t idx = (int64_t)pair * vv + ab;
+        for (int r = 0; r < R; ++r) {
+          const int pr = pr0 + r * groups;
+          if (pr >= oo) break;
+          const int i = pr / o, j = pr % o;
+          double occ = 0.0;
+          for (int k = 0; k < o; ++k)
+            occ += fo[k * o + i] * xs[(k * o + j) * ch + e] + fo[k * o + j] * xs[(i * o + k) * ch + e];
+          const int64_t idx = (int64_t)pr * vv + ab0 + e;
+          const double y = yin[r] - occ;
           if constexpr (LZ) {
-            const double q = y - beta * p.vprev2[idx];
+            const double q = y - beta * vin[r];
             p.y2[idx] = q;
-            dot += x2[idx] * q;
+            dot += xs[pr * ch + e] * q;
           } else {
             p.y2[idx] = y;
           }
         }
+      }
     }
   } else {
-    const int64_t e = (int64_t)blockIdx.x * 256 + tid;
-    if (e < ov) {
-      const int i = (int)(e / v), a = (int)(e % v);
-      double y = 0.0;
-      for (int c = 0; c < v; ++c) y += p.f_vv[(int64_t)a * v + c] * x1[(int64_t)i * v + c];
-      for (int k = 0; k < o; ++k) y -= p.f_oo[(int64_t)k * o + i] * x1[(int64_t)k * v + a];
+    // singles: 16 outputs per workgroup, 16 lanes per output
+    const int w = tid >> 4, l = tid & 15;
+    const int64_t out = (int64_t)(blockIdx.x - p.nchunks) * 16 + w;
+    double part = 0.0;
+    if (out < ov) {
+      const int i = (int)(out / v), a = (int)(out % v);
+      for (int c = l; c < v; c += 16) part += p.f_vv[(int64_t)a * v + c] * p.x1[(int64_t)i * v + c];
+      for (int k = l; k < o; k += 16) part -= p.f_oo[(int64_t)k * o + i] * p.x1[(int64_t)k * v + a];
+    }
+    // fixed-order butterfly over the 16 lanes of this output
+    for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
+    if (out < ov && l == 0) {
       if constexpr (LZ) {
-        const double q = y - beta * p.vprev1[e];
-        p.y1[e] = q;
-        dot += x1[e] * q;
+        const double q = part - beta * p.vprev1[out];
+        p.y1[out] = q;
+        dot += p.x1[out] * q;
       } else {
-        p.y1[e] = y;
+        p.y1[out] = part;
       }
     }
   }
@@ -173,23 +216,45 @@ __global__ __launch_bounds__(256) void fock_op_kernel(FockKArgs p) {
       if (tid < s) red[tid] += red[tid + s];
       __syncthreads();
     }
-    if (tid == 0) p.partials[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = red[0];
+    if (tid == 0) p.partials[blockIdx.x] = red[0];
   }
 }
 
 bool aligned16(const void* q) { return ((uintptr_t)q & 15u) == 0; }
 
-template <bool LZ>
-void launch(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, const double* vprev1,
-            const double* vprev2, const double* beta, double* partials, hipStream_t s) {
-  PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
-  PNK_REQUIRE(x1 != y1 && x2 != y2, "fock_op: output must not alias the input");
-  FockKArgs a;
-  a.o = op.o;
+void launch_vir(const FockOp& op, const double* x2, double* y2, hipStream_t s) {
+  VirArgs a;
   a.v = op.v;
   a.tiles_m = (int)ceil_div(op.v, op.bm);
-  a.tiles = op.tiles;
   a.vec = (op.v % 2 == 0 && aligned16(x2) && aligned16(op.f_vv)) ? 1 : 0;
+  a.f_vv = op.f_vv;
+  a.x2 = x2;
+  a.y2 = y2;
+  dim3 grid((unsigned)op.tiles, (unsigned)(op.o * op.o));
+  // contraction panels of 32 for the 32-wide blocks when that pads v no
+  // more than panels of 16 (measured: the wider blocks run better with 16)
+  const bool bk32 = op.bm == 32 && ceil_div(op.v, 32) * 32 <= ceil_div(op.v, 16) * 16;
+  switch (op.bm * 2 + (bk32 ? 1 : 0)) {
+    case 64: fock_vir_kernel<32, 2, 16><<<grid, 256, 0, s>>>(a); break;
+    case 65: fock_vir_kernel<32, 2, 32><<<grid, 256, 0, s>>>(a); break;
+    case 96: fock_vir_kernel<48, 4, 16><<<grid, 256, 0, s>>>(a); break;
+    case 97: fock_vir_kernel<48, 4, 32><<<grid, 256, 0, s>>>(a); break;
+    case 128: fock_vir_kernel<64, 2, 16><<<grid, 256, 0, s>>>(a); break;
+    default: fock_vir_kernel<64, 2, 32><<<grid, 256, 0, s>>>(a); break;
+  }
+  PNK_CHECK_LAUNCH();
+}
+
+size_t occ_lds_bytes(int o, int ch) { return sizeof(double) * ((size_t)o * o * ch + (size_t)o * o); }
+
+template <bool LZ>
+void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, const double* vprev1,
+                const double* vprev2, const double* beta, double* partials, hipStream_t s) {
+  OccArgs a;
+  a.o = op.o;
+  a.v = op.v;
+  a.ch = op.ch;
+  a.nchunks = op.nchunks;
   a.f_oo = op.f_oo;
   a.f_vv = op.f_vv;
   a.x1 = x1;
@@ -200,22 +265,19 @@ void launch(const FockOp& op, const double* x1, const double* x2, double* y1, do
   a.vprev2 = vprev2;
   a.beta = beta;
   a.partials = partials;
-  dim3 grid((unsigned)op.gx, (unsigned)op.gy);
-  switch (op.bm) {
-    case 32: fock_op_kernel<32, 2, LZ><<<grid, 256, 0, s>>>(a); break;
-    case 48: fock_op_kernel<48, 4, LZ><<<grid, 256, 0, s>>>(a); break;
-    default: fock_op_kernel<64, 2, LZ><<<grid, 256, 0, s>>>(a); break;
-  }
+  fock_occ_kernel<LZ><<<(unsigned)op.nparts(), 256, occ_lds_bytes(op.o, op.ch), s>>>(a);
   PNK_CHECK_LAUNCH();
 }
 
 }  // namespace
 
-// Tile: the block edge among 32 / 48 / 64 that wastes the fewest padded
-// outputs (v^2 / (tiles * bm^2)); among near-ties the largest edge that
-// still gives at least 512 workgroups (two per CU), else the smallest.
+// Virtual kernel: the block edge among 32 / 48 / 64 that wastes the fewest
+// padded outputs (v^2 / (tiles * bm^2)); among near-ties the largest edge
+// that still gives at least 512 workgroups (two per CU), else the smallest.
+// Occupied kernel: the widest chunk (64 .. 8 elements) whose LDS stays
+// within 64 KB (two workgroups per CU) and that still gives 512 workgroups.
 bool fock_op_plan(FockOp& op) {
-  if (op.o < 1 || op.v < 1 || op.o >= kFockOpMaxOcc) return false;
+  if (op.o < 1 || op.v < 1 || op.o > kFockOpMaxOcc) return false;
   const int cand[3] = {32, 48, 64};
   double util[3], best = 0.0;
   for (int c = 0; c < 3; ++c) {
@@ -235,26 +297,49 @@ bool fock_op_plan(FockOp& op) {
   op.bm = cand[pick];
   const int64_t tm = ceil_div(op.v, op.bm);
   op.tiles = (int)(tm * tm);
-  const int64_t singles = ceil_div((int64_t)op.o * op.v, 256);
-  op.gx = (int)std::max<int64_t>(op.tiles, singles);
-  op.gy = op.o * op.o + 1;
-  return op.gx <= 65535 && op.gy <= 65535;
+
+  const int64_t vv = (int64_t)op.v * op.v;
+  op.ch = 0;
+  for (int ch : {64, 32, 16, 8}) {
+    if (occ_lds_bytes(op.o, ch) > 64 * 1024) continue;
+    if (op.ch == 0) op.ch = ch;  // widest that fits, whatever the count
+    if (ceil_div(vv, ch) >= 512) { op.ch = ch; break; }
+  }
+  if (op.ch == 0) return false;
+  op.nchunks = (int)ceil_div(vv, op.ch);
+  op.nsingles = (int)ceil_div((int64_t)op.o * op.v, 16);
+  return op.tiles <= 65535 && op.o * op.o <= 65535 && op.nparts() <= 0x7fffffff;
 }
 
-bool fock_op_is_lanczos_kernel(const void* func) {
-  return func == reinterpret_cast<const void*>(&fock_op_kernel<32, 2, true>) ||
-         func == reinterpret_cast<const void*>(&fock_op_kernel<48, 4, true>) ||
-         func == reinterpret_cast<const void*>(&fock_op_kernel<64, 2, true>);
+bool fock_op_is_virtual_kernel(const void* func) {
+  return func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 16>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 32>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 16>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 32>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 16>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 32>);
 }
 
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s) {
-  launch<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, s);
+  PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
+  PNK_REQUIRE(x1 != y1 && x2 != y2, "fock_op: output must not alias the input");
+  launch_vir(op, x2, y2, s);
+  launch_occ<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, s);
 }
 
-void fock_op_lanczos(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                     double* partials, hipStream_t s) {
+void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s) {
+  PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
+  PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
   const int64_t ov = (int64_t)op.o * op.v;
-  launch<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, s);
+  launch_vir(op, v + ov, p + ov, s);
+}
+
+void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
+                         double* partials, hipStream_t s) {
+  PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
+  PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
+  const int64_t ov = (int64_t)op.o * op.v;
+  launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, s);
 }
 
 }  // namespace pnk

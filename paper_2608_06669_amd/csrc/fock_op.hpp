@@ -1,47 +1,53 @@
-// Fused Fock operator y = A_F x (equation Preconditioner, Appendix C working
-// equations extended to singles) for f_ov = 0, in one kernel launch:
+// Fock operator y = A_F x (equation Preconditioner, Appendix C working
+// equations extended to singles), f_ov-free part, in two launches:
 //
-//   y_ij^ab = sum_c f_ac x_ij^cb + sum_c x_ij^ac f_cb
-//             - sum_k f_ki x_kj^ab - sum_k f_kj x_ik^ab
-//   y_i^a   = sum_c f_ac x_i^c - sum_k f_ki x_k^a
+//   y_ij^ab = sum_c f_ac x_ij^cb + sum_c x_ij^ac f_cb      (virtual kernel)
+//             - sum_k f_ki x_kj^ab - sum_k f_kj x_ik^ab     (occupied kernel)
+//   y_i^a   = sum_c f_ac x_i^c - sum_k f_ki x_k^a          (occupied kernel)
 //
 // f_oo and f_vv are symmetric (any orthogonal gauge). Vectors are packed as
 // [x1 (o*v) | x2 (o*o*v*v)], x1[i][a], x2[i][j][a][b].
 //
-// The same launch can also carry the first Lanczos update of the inner
-// solve: p = A_F v_k - beta_k v_{k-1} together with per-workgroup partial
-// sums of <v_k, p>, so the operator's output is never re-read for it.
+// The occupied launch can also carry the first Lanczos update of the inner
+// solve: p = A_F v_k - beta_k v_{k-1} and per-workgroup partial sums of
+// <v_k, p>.
 #pragma once
 
 #include "common.hpp"
 
 namespace pnk {
 
+constexpr int kFockOpMaxOcc = 31;  // the occupied kernel stages o^2 slices in LDS
+
 struct FockOp {
   int o = 0, v = 0;
   const double* f_oo = nullptr;
   const double* f_vv = nullptr;
   // set by fock_op_plan
-  int bm = 0, tiles = 0, gx = 0, gy = 0;
-  int64_t nparts() const { return (int64_t)gx * gy; }
+  int bm = 0, tiles = 0;    // virtual kernel: bm x bm blocks, tiles per pair
+  int ch = 0, nchunks = 0;  // occupied kernel: ch (ab) elements per workgroup
+  int nsingles = 0;         // ... plus workgroups of 16 singles each
+  int64_t nparts() const { return (int64_t)nchunks + nsingles; }
 };
 
-// Picks the tile shape; returns false when the fused kernel does not apply
-// (o > kFockOpMaxOcc) and the caller must use the general path.
-constexpr int kFockOpMaxOcc = 256;
+// Picks the launch shapes; false when these kernels do not apply (o too
+// large) and the caller must use the general path.
 bool fock_op_plan(FockOp& op);
 
-// y = A_F x (the f_ov-free part; y must not alias x)
+// y = A_F x (y must not alias x)
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s);
 
-// Packed vectors: p = A_F v - (*beta) vprev and partials[b] = sum over
-// workgroup b of v . p (op.nparts() entries, each summed in a fixed order).
-// beta is a device scalar.
-void fock_op_lanczos(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                     double* partials, hipStream_t s);
+// The same two launches on packed vectors with the first Lanczos update:
+// fock_op_lanczos_vir writes the virtual part of A_F v into p; then
+// fock_op_lanczos_occ completes p = A_F v - (*beta) vprev and writes
+// partials[b] = the sum over its workgroup b of v . p (op.nparts() entries,
+// each summed in a fixed order). beta is a device scalar.
+void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s);
+void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
+                         double* partials, hipStream_t s);
 
-// True for the kernel function that fock_op_lanczos launches (used to find
-// its nodes in a recorded graph).
-bool fock_op_is_lanczos_kernel(const void* func);
+// True for the virtual-contraction kernel (the launch that does the matrix
+// work), used to find its nodes in a recorded graph.
+bool fock_op_is_virtual_kernel(const void* func);
 
 }  // namespace pnk

@@ -263,20 +263,26 @@ __global__ __launch_bounds__(256) void splitk_reduce_wide(KArgs p) {
 // (<= kSmallSide): a matrix-core tile would be mostly padding and the cost
 // is one pass over the long operand. Each lane owns one index of the long
 // output side, holds its K operand values in registers and produces every
-// output along the short side; the short operand's elements are the same
-// for all lanes (scalar loads). LONG_N: the long side is N.
+// output along the short side; the short operand is staged in LDS and read
+// as broadcasts. LONG_N: the long side is N.
 constexpr int kSmallK = 32, kSmallSide = 32;
 
 template <bool LONG_N>
 __global__ __launch_bounds__(256) void gemm_smallk(KArgs p) {
+  __shared__ double sh[kSmallSide * kSmallK];  // the short operand, [s][k]
   const int b0 = blockIdx.y % p.nb0;
   const int b1 = blockIdx.y / p.nb0 + blockIdx.z * (gridDim.y / p.nb0);
   const double* __restrict__ A = (const double*)p.A + b0 * p.a_b0 + b1 * p.a_b1;
   const double* __restrict__ B = (const double*)p.B + b0 * p.b_b0 + b1 * p.b_b1;
   double* __restrict__ C = (double*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
-  const int l = blockIdx.x * 256 + threadIdx.x;
   const int L = LONG_N ? p.N : p.M;
   const int S = LONG_N ? p.M : p.N;
+  for (int q = threadIdx.x; q < S * p.K; q += 256) {
+    const int s = q / p.K, k = q % p.K;
+    sh[s * kSmallK + k] = LONG_N ? A[s * p.a_m + k * p.a_k] : B[k * p.b_k + s * p.b_n];
+  }
+  __syncthreads();
+  const int l = blockIdx.x * 256 + threadIdx.x;
   if (l >= L) return;
   double r[kSmallK];
 #pragma unroll
@@ -286,7 +292,7 @@ __global__ __launch_bounds__(256) void gemm_smallk(KArgs p) {
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < kSmallK; ++k)
-      if (k < p.K) acc += (LONG_N ? A[s * p.a_m + k * p.a_k] : B[k * p.b_k + s * p.b_n]) * r[k];
+      if (k < p.K) acc += sh[s * kSmallK + k] * r[k];
     double* c = LONG_N ? C + s * p.c_m + l * p.c_n : C + l * p.c_m + s * p.c_n;
     double v = p.alpha * acc;
     if (p.beta != 0.0) v += p.beta * *c;

@@ -296,11 +296,13 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
   const FockOp* op = eng_.fock_op();
   int nparts1 = kLzBlocks;
   if (op && op->nparts() <= kMaxFusedParts) {
-    // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p> in one launch
+    // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p>; the timer
+    // covers the virtual (matrix-core) launch
     Timers* tm = eng_.timers();
     if (tm) tm->begin(kTimerFock, s);
-    fock_op_lanczos(*op, v, vprev, st + kBeta, p, part1, s);
+    fock_op_lanczos_vir(*op, v, p, s);
     if (tm) tm->end(kTimerFock, s);
+    fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, part1, s);
     nparts1 = (int)op->nparts();
   } else {
     eng_.fock_apply(v, v + ov, p, p + ov, s);
@@ -330,7 +332,7 @@ void Solver::lanczos_block(hipStream_t s) {
 
 namespace {
 
-// Brackets every fused A_F kernel node of a recorded graph with two event
+// Brackets every virtual A_F kernel node of a recorded graph with two event
 // record nodes (ev[2k], ev[2k+1]) so each launch's duration can be read
 // after a replay. Returns the number of nodes bracketed, -1 on error.
 int bracket_fock_nodes(hipGraph_t g, hipEvent_t* ev, int max_pairs) {
@@ -345,7 +347,7 @@ int bracket_fock_nodes(hipGraph_t g, hipEvent_t* ev, int max_pairs) {
     if (type != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams kp{};
     if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) return -1;
-    if (!fock_op_is_lanczos_kernel(kp.func)) continue;
+    if (!fock_op_is_virtual_kernel(kp.func)) continue;
     if (k >= max_pairs) return -1;
     size_t nd = 0, ns = 0;
     if (hipGraphNodeGetDependencies(node, nullptr, &nd) != hipSuccess) return -1;

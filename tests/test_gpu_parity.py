@@ -198,6 +198,24 @@ def test_precond_solve_symmetric_fock_operator(handle, lib):
         assert np.abs(host(s2) - e2).max() <= 1e-10 * np.abs(e2).max()
 
 
+def test_fock_operator_large_doubles_block(handle, lib):
+    """o = 14, v = 130 (26 MB doubles block): the occupied terms leave the
+    fused kernel's epilogue for two streaming passes, and the inner solve
+    uses the unfused Lanczos step."""
+    p = make_problem(14, 130, 20, 55, gauge="haar")
+    x1, x2 = random_amplitudes(14, 130, 56, scale=1.0)
+    P = lib.DeviceProblem.from_problem(p)
+    y1, y2 = handle.fock_apply(P, dev(x1), dev(x2))
+    a1, a2 = solvers.fock_apply(p.f_oo, p.f_ov, p.f_vv, x1, x2)
+    assert np.abs(host(y1) - a1).max() <= 1e-13 * np.abs(a1).max()
+    assert np.abs(host(y2) - a2).max() <= 1e-13 * np.abs(a2).max()
+    s1, s2, iters, ok = handle.precond_solve(P, dev(x1), dev(x2), rtol=1e-12, maxit=300)
+    e1, e2 = solvers.fock_solve_exact(p.f_oo, p.f_ov, p.f_vv, x1, x2)
+    assert ok and 0 < iters < 300
+    assert np.abs(host(s1) - e1).max() <= 1e-10 * np.abs(e1).max()
+    assert np.abs(host(s2) - e2).max() <= 1e-10 * np.abs(e2).max()
+
+
 def test_repeated_products_replay_graphs_exactly(handle, lib):
     """The third and later residual / J v calls with the same buffers replay
     recorded HIP graphs; every replay matches the first (eager) evaluation
