@@ -385,38 +385,20 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   }
 }
 
-double util(int64_t M, int64_t N, int bm, int bn) {
-  return (double)(M * N) / (double)(ceil_div(M, bm) * bm * ceil_div(N, bn) * bn);
-}
 
-// Tile choice. FP64: 64 output columns per workgroup (more resident waves
-// per SIMD hide LDS and global latency better than wider tiles; measured on
-// MI355X) and the row height among 128/112/96/80 that wastes the fewest rows
-// (M = nocc^2 or nocc(nocc+1)/2 is rarely a multiple of 128). FP32/BF16:
-// 128 x 128. Small products: 64 x 64 (split-K fills the GPU).
+// Tile choice. FP64: 64 x 64 with 16-deep panels (a sweep over 32/64/96/128
+// x 64 tiles and 16/32-deep panels on MI355X put it at or within 3 % of the
+// best for square products from 900 to 3600 and for the ladder shapes);
+// thin products (at most 64 rows) with a long contraction stream their wide
+// operand from HBM and take 32-deep panels (about 20 % faster there).
+// FP32/BF16: 128 x 128. Small products: 64 x 64 (split-K fills the GPU).
 template <class Mma, typename TA, typename TB, typename TC, int BK>
 void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, void* C,
                   hipStream_t s) {
   const int64_t nb = (int64_t)d.nb0 * d.nb1;
   if constexpr (sizeof(typename Mma::L) == 8) {
-    const int64_t tiles = ceil_div(d.M, 128) * ceil_div(d.N, 64) * nb;
-    if (d.M >= 64 && d.N >= 64 && tiles >= 256) {
-      struct Opt { int bm; double score; };
-      const Opt opts[] = {{128, util(d.M, d.N, 128, 64)},
-                          {112, 0.99 * util(d.M, d.N, 112, 64)},
-                          {96, 0.98 * util(d.M, d.N, 96, 64)},
-                          {80, 0.98 * util(d.M, d.N, 80, 64)}};
-      Opt best = opts[0];
-      for (const Opt& o : opts)
-        if (o.score > best.score + 1e-9) best = o;
-      switch (best.bm) {
-        case 112: launch_cfg<Mma, TA, TB, TC, 112, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
-        case 96: launch_cfg<Mma, TA, TB, TC, 96, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
-        case 80: launch_cfg<Mma, TA, TB, TC, 80, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
-        default: launch_cfg<Mma, TA, TB, TC, 128, 64, BK, 2>(d, A, B, A2, B2, C, s); return;
-      }
-    }
-    launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
+    if (d.M <= 64 && d.K >= 1024) launch_cfg<Mma, TA, TB, TC, 64, 64, 32, 2>(d, A, B, A2, B2, C, s);
+    else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
     return;
   }
   const int64_t big = ceil_div(d.M, 128) * ceil_div(d.N, 128) * nb;
