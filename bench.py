@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2_haar"
+# HBM bytes per launch of the virtual A_F kernel on this workload, from the
+# rocprofv3 FETCH_SIZE / WRITE_SIZE passes in
+# profiles/fock_vir_kernel_c2_haar_counters.md (scaled by the same counters
+# for a copy kernel of known size). Set to None when the kernel changes.
+FOCK_VIR_TRAFFIC_BYTES = 13497750
 
 
 def nominal_residual_flops(o, v, naux):
@@ -88,18 +93,7 @@ def cpu_baseline(problem, counts, t1_gpu, t2_gpu, e_gpu):
     return out, check
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU (asked for {args.gpus}): one solve is not sharded across GPUs here; "
-              "see the design notes for how it would shard", file=sys.stderr)
-        sys.exit(2)
-
+def bench_c2(args):
     import torch
 
     import paper_2608_06669_amd as pk
@@ -155,7 +149,7 @@ def main():
     if af_ms:
         ach = af_flops / (af_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                "frac": ach / FP64_PEAK_TFLOPS, "traffic": FOCK_VIR_TRAFFIC_BYTES,
                 "kernel": "fock_vir_kernel (A_F virtual contractions, FP64 4x4x4 MFMA)",
                 "launches": n_afm, "avg_us": af_ms * 1e3, "flops_per_launch": af_flops,
                 "hbm_bytes_per_launch": af_bytes,
@@ -196,6 +190,154 @@ def main():
         out.update(check)
     print(json.dumps(out), flush=True)
     h.close()
+
+
+def bench_large(args):
+    """One PNK solve of a larger workload (near-degenerate o=16/v=144 or the
+    mixed-precision o=20/v=180), J v in the requested precision; prints one
+    JSON line with the time to solution and the operation counts."""
+    import torch
+
+    import paper_2608_06669_amd as pk
+    from gen import make_config
+
+    pk.load()
+    p = make_config(args.workload)
+    o, v, naux = p.nocc, p.nvir, p.naux
+    tol = p.meta["tol"]
+    h = pk.Handle(0)
+    P = pk.DeviceProblem.from_problem(p)
+    torch.cuda.synchronize()
+    h.timing(True)
+    t0 = time.perf_counter()
+    t1, t2, info = h.solve_pnk(P, tol_inf=tol, max_newton=args.max_newton, jvp_prec=args.prec)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    n_res, ms_res = h.timing_read(1)
+    n_jvp, ms_jvp = h.timing_read(2)
+    n_pre, ms_pre = h.timing_read(4)
+    h.timing(False)
+    hist = h.history()
+    F_R = nominal_residual_flops(o, v, naux)
+    out = {"workload": args.workload, "nocc": o, "nvir": v, "naux": naux, "tol_inf": tol, "jvp_prec": args.prec,
+           "status": info["status"], "seconds": dt, "e_corr": info["e_corr"], "res_inf": info["res_inf"],
+           "counts": {k: info[k] for k in ("newton_iters", "n_residual", "n_jvp", "n_afmv")},
+           "residual_ms": ms_res / max(n_res, 1), "residual_tflops_fp64_nominal": F_R / (ms_res / max(n_res, 1) * 1e-3) / 1e12,
+           "jvp_ms": ms_jvp / max(n_jvp, 1), "precond_solve_ms": ms_pre / max(n_pre, 1),
+           "res_inf_history": [float(x) for x in hist[:, 1][:: max(1, len(hist) // 40)]]}
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+def bench_serving(args):
+    """Serving stream: seeded requests with nocc ~ U{4..16}, nvir = nocc *
+    U{5..9}, naux = 3 (nocc + nvir), alternating canonical and rotated
+    gauges. The closed-loop rate mu (all requests queued at once) is measured
+    first, then an open-loop Poisson stream at 0.7 mu; both for FP64 J v and
+    for the mixed-precision (BF16 J v) path. Prints one JSON line."""
+    import numpy as np
+
+    import paper_2608_06669_amd as pk
+    from gen import make_serving_request, poisson_arrivals, serving_request_shapes
+
+    pk.load()
+    reqs = [make_serving_request(s) for s in serving_request_shapes(args.requests)]
+    res = {}
+
+    def run(prec, arrivals=None):
+        srv = pk.Server(0, max_slots=args.slots)
+        try:
+            t0 = time.perf_counter()
+            ids = []
+            for k, r in enumerate(reqs):
+                if arrivals is not None:
+                    wait = arrivals[k] - (time.perf_counter() - t0)
+                    if wait > 0:
+                        time.sleep(wait)
+                ids.append(srv.submit(r, tol_inf=1e-8, max_newton=args.max_newton, jvp_prec=prec))
+            srv.drain()
+            wall = time.perf_counter() - t0
+            out = [srv.poll(i, want_amplitudes=False) for i in ids]
+            times = [srv.times(i) for i in ids]
+            stats = srv.stats()
+        finally:
+            srv.close()
+        lat = sorted(1000.0 * (f - s) for (s, _, f) in times)
+        return dict(wall=wall, solves_per_s=len(reqs) / wall, p50_ms=float(np.percentile(lat, 50)),
+                    p99_ms=float(np.percentile(lat, 99)), peak_running=stats["peak_running"],
+                    peak_bytes=stats["peak_bytes"], budget=stats["budget"],
+                    converged=sum(1 for x in out if x["status"] == "CC_OK"), energies=[x["e_corr"] for x in out])
+
+    closed = {prec: run(prec) for prec in ("fp64", "bf16")}
+    mu = closed["fp64"]["solves_per_s"]
+    lam = 0.7 * mu
+    arr = poisson_arrivals(len(reqs), lam)
+    opened = {prec: run(prec, arr) for prec in ("fp64", "bf16")}
+    de = max(abs(a - b) for a, b in zip(closed["fp64"]["energies"], closed["bf16"]["energies"]))
+    for d in (closed, opened):
+        for x in d.values():
+            x.pop("energies")
+    sizes = [(r.nocc, r.nvir) for r in reqs]
+    out = {"workload": f"serving stream, {len(reqs)} requests (C5 sample), PNK to ||r||_inf<1e-8, {args.slots} slots",
+           "request_sizes": sizes, "closed_loop": closed, "poisson_rate_per_s": lam, "open_loop": opened,
+           "max_abs_dE_bf16_vs_fp64": de}
+    print(json.dumps(out), flush=True)
+
+
+def bench_inner(args):
+    """Inner A_F solves alone (the C2 shapes): `steps` solves of A_F x = b
+    with a seeded pair-symmetric b; used for kernel counters. Each solve
+    ends with one copy of the N-vector (a copy kernel of known size)."""
+    import torch
+
+    import paper_2608_06669_amd as pk
+    from gen import make_config, random_amplitudes
+
+    pk.load()
+    p = make_config(WORKLOAD)
+    o, v = p.nocc, p.nvir
+    h = pk.Handle(0)
+    P = pk.DeviceProblem.from_problem(p)
+    b1, b2 = (torch.as_tensor(a, device="cuda") for a in random_amplitudes(o, v, 77, scale=1.0))
+    h.precond_solve(P, b1, b2)  # warm-up: integral preparation and graph recording
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters = 0
+    for _ in range(args.steps):
+        _, _, it, _ = h.precond_solve(P, b1, b2)
+        iters += it
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"workload": "inner A_F solves, o=10 v=90", "solves": args.steps, "products": iters,
+                      "us_per_product": 1e6 * dt / max(iters, 1), "n_vector": o * v + o * o * v * v}), flush=True)
+    h.close()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner"],
+                    help="default: the bench line; the others print their own measurement line")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"], help="J v precision (c3/c4)")
+    ap.add_argument("--max-newton", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=40)
+    ap.add_argument("--slots", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU (asked for {args.gpus}): one solve is not sharded across GPUs here; "
+              "see the design notes for how it would shard", file=sys.stderr)
+        sys.exit(2)
+    if args.workload == WORKLOAD:
+        bench_c2(args)
+    elif args.workload == "serving":
+        bench_serving(args)
+    elif args.workload == "inner":
+        bench_inner(args)
+    else:
+        bench_large(args)
 
 
 if __name__ == "__main__":

@@ -27,7 +27,7 @@ namespace {
 using namespace tiles;
 
 struct VirArgs {
-  int v, tiles_m;
+  int v, tiles_m, tiles, units, per_xcd;
   int vec;  // 16-byte operand loads allowed
   const double* f_vv;
   const double* x2;
@@ -53,9 +53,15 @@ __global__ __launch_bounds__(256) void fock_vir_kernel(VirArgs p) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  const int m0 = (blockIdx.x % p.tiles_m) * BM;
-  const int n0 = (blockIdx.x / p.tiles_m) * BN;
-  const double* __restrict__ X = p.x2 + (int64_t)blockIdx.y * vv;
+  // Workgroups are dispatched round-robin over the 8 XCDs; consecutive
+  // units (the tiles of one pair) are given to one XCD so the pair's slab
+  // of x is fetched into that XCD's L2 once.
+  const int u = (int)(blockIdx.x % 8) * p.per_xcd + (int)(blockIdx.x / 8);
+  if (u >= p.units) return;
+  const int pair = u / p.tiles, tile = u % p.tiles;
+  const int m0 = (tile % p.tiles_m) * BM;
+  const int n0 = (tile / p.tiles_m) * BN;
+  const double* __restrict__ X = p.x2 + (int64_t)pair * vv;
   const double* __restrict__ F = p.f_vv;
   const bool vec = p.vec != 0;
   const int nkp = (v + BK - 1) / BK;
@@ -104,7 +110,7 @@ __global__ __launch_bounds__(256) void fock_vir_kernel(VirArgs p) {
     __syncthreads();
   }
 
-  double* __restrict__ Y = p.y2 + (int64_t)blockIdx.y * vv;
+  double* __restrict__ Y = p.y2 + (int64_t)pair * vv;
 #pragma unroll
   for (int a = 0; a < TMI; ++a)
 #pragma unroll
@@ -226,11 +232,14 @@ void launch_vir(const FockOp& op, const double* x2, double* y2, hipStream_t s) {
   VirArgs a;
   a.v = op.v;
   a.tiles_m = (int)ceil_div(op.v, op.bm);
+  a.tiles = op.tiles;
+  a.units = op.tiles * op.o * op.o;
+  a.per_xcd = (int)ceil_div(a.units, 8);
   a.vec = (op.v % 2 == 0 && aligned16(x2) && aligned16(op.f_vv)) ? 1 : 0;
   a.f_vv = op.f_vv;
   a.x2 = x2;
   a.y2 = y2;
-  dim3 grid((unsigned)op.tiles, (unsigned)(op.o * op.o));
+  dim3 grid((unsigned)(8 * a.per_xcd));
   // contraction panels of 32 for the 32-wide blocks when that pads v no
   // more than panels of 16 (measured: the wider blocks run better with 16)
   const bool bk32 = op.bm == 32 && ceil_div(op.v, 32) * 32 <= ceil_div(op.v, 16) * 16;
@@ -274,8 +283,9 @@ void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1
 // Virtual kernel: the block edge among 32 / 48 / 64 that wastes the fewest
 // padded outputs (v^2 / (tiles * bm^2)); among near-ties the largest edge
 // that still gives at least 512 workgroups (two per CU), else the smallest.
-// Occupied kernel: the widest chunk (64 .. 8 elements) whose LDS stays
-// within 64 KB (two workgroups per CU) and that still gives 512 workgroups.
+// Occupied kernel: the widest chunk (64 .. 16 elements, 8 only when 16 does
+// not fit) whose LDS stays within 64 KB (two workgroups per CU) and that
+// still gives 512 workgroups.
 bool fock_op_plan(FockOp& op) {
   if (op.o < 1 || op.v < 1 || op.o > kFockOpMaxOcc) return false;
   const int cand[3] = {32, 48, 64};
@@ -299,16 +309,17 @@ bool fock_op_plan(FockOp& op) {
   op.tiles = (int)(tm * tm);
 
   const int64_t vv = (int64_t)op.v * op.v;
+  // (at least 16 elements: a full 128-byte line per pair and chunk)
   op.ch = 0;
   for (int ch : {64, 32, 16, 8}) {
     if (occ_lds_bytes(op.o, ch) > 64 * 1024) continue;
     if (op.ch == 0) op.ch = ch;  // widest that fits, whatever the count
-    if (ceil_div(vv, ch) >= 512) { op.ch = ch; break; }
+    if (ceil_div(vv, ch) >= 512 || ch == 16) { op.ch = ch; break; }
   }
   if (op.ch == 0) return false;
   op.nchunks = (int)ceil_div(vv, op.ch);
   op.nsingles = (int)ceil_div((int64_t)op.o * op.v, 16);
-  return op.tiles <= 65535 && op.o * op.o <= 65535 && op.nparts() <= 0x7fffffff;
+  return (int64_t)op.tiles * op.o * op.o < (1ll << 31) - 8 && op.nparts() <= 0x7fffffff;
 }
 
 bool fock_op_is_virtual_kernel(const void* func) {
