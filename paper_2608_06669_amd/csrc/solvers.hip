@@ -593,6 +593,9 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     hist_.push_back(rinf);
     st->res_inf = rinf;
     st->res_2 = rn;
+    if (verbose_)
+      std::fprintf(stderr, "pnk newton %d: |r|_inf %.3e |r|_2 %.3e, %d J v, %d A_F products\n", k, rinf, rn,
+                   st->n_jvp, st->n_afmv);
     if (!std::isfinite(rn)) { st->diverged = 1; break; }
     if (rinf < opt.tol_inf) { st->converged = 1; break; }
     if (k >= opt.max_newton) break;
@@ -729,6 +732,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     hist_.push_back(rinf);
     st->res_inf = rinf;
     st->res_2 = rn;
+    if (verbose_) std::fprintf(stderr, "fp+diis iteration %d: |r|_inf %.3e |r|_2 %.3e\n", it, rinf, rn);
     if (!std::isfinite(rn)) { st->diverged = 1; break; }
     if (rinf < opt.tol_inf) { st->converged = 1; break; }
     if (it >= opt.max_iter || rn > 1e6) break;

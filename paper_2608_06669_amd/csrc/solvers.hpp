@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <cstdlib>
 #include <vector>
 
 #include "ccsd.hpp"
@@ -92,6 +93,8 @@ class Solver {
   hipStream_t alloc_stream_;
   bool async_;
   bool sym_inner_ = true;
+  // one line per outer iteration on stderr when PNK_VERBOSE is set
+  bool verbose_ = std::getenv("PNK_VERBOSE") != nullptr;
   bool use_graphs_ = true;
   bool lz_graph_failed_ = false;
   hipGraphExec_t lz_exec_ = nullptr;
