@@ -12,15 +12,9 @@
 // touch o slices of x per output; done per output they re-read x 2o times.
 // Instead one workgroup stages x[:, :, chunk] (all o^2 pairs for a chunk of
 // ch consecutive (a, b)) in LDS once and forms both sums for every pair
-// from there, so x is read from memory once. Trailing workgroups compute
-// the singles, 16 lanes per output.
-//
-// In the inner Lanczos solve the two launches are independent: the virtual
-// kernel writes its part of A_F v_k into p, the occupied kernel writes
-// -(occupied part) - beta_k v_{k-1} into a separate buffer t (and the
-// singles of p), each with per-workgroup partial sums of its share of
-// <v_k, p>; the next kernel adds t and reads both sets of partials. The
-// solver runs the two launches on two streams.
+// from there, so x is read from memory once. The same launch adds the
+// virtual part, applies the Lanczos update and sums <v_k, p> per workgroup.
+// Trailing workgroups compute the singles, 16 lanes per output.
 
 #include "fock_op.hpp"
 #include "mfma_tiles.hpp"
@@ -38,10 +32,9 @@ struct VirArgs {
   const double* f_vv;
   const double* x2;
   double* y2;
-  double* partials;  // LZ: per-workgroup <x2, y2> over its block
 };
 
-template <int BM, int WGM, int BK, bool LZ>
+template <int BM, int WGM, int BK>
 __global__ __launch_bounds__(256) void fock_vir_kernel(VirArgs p) {
   using Mma = MmaF64;
   constexpr int BN = BM;
@@ -64,11 +57,7 @@ __global__ __launch_bounds__(256) void fock_vir_kernel(VirArgs p) {
   // units (the tiles of one pair) are given to one XCD so the pair's slab
   // of x is fetched into that XCD's L2 once.
   const int u = (int)(blockIdx.x % 8) * p.per_xcd + (int)(blockIdx.x / 8);
-  if (u >= p.units) {  // padding workgroup of the XCD grouping
-    if constexpr (LZ)
-      if (tid == 0) p.partials[blockIdx.x] = 0.0;
-    return;
-  }
+  if (u >= p.units) return;
   const int pair = u / p.tiles, tile = u % p.tiles;
   const int m0 = (tile % p.tiles_m) * BM;
   const int n0 = (tile / p.tiles_m) * BN;
@@ -122,30 +111,14 @@ __global__ __launch_bounds__(256) void fock_vir_kernel(VirArgs p) {
   }
 
   double* __restrict__ Y = p.y2 + (int64_t)pair * vv;
-  double dot = 0.0;
 #pragma unroll
   for (int a = 0; a < TMI; ++a)
 #pragma unroll
     for (int b = 0; b < TNI; ++b) {
       const int ga = m0 + wm * WTM + a * 4 + (lane >> 4);
       const int gb = n0 + wn * WTN + b * 16 + (lane & 15);
-      if (ga < v && gb < v) {
-        const int64_t ab = (int64_t)ga * v + gb;
-        Y[ab] = acc[a][b];
-        if constexpr (LZ) dot += X[ab] * acc[a][b];
-      }
+      if (ga < v && gb < v) Y[(int64_t)ga * v + gb] = acc[a][b];
     }
-  if constexpr (LZ) {
-    // (As is free after the last barrier of the K loop)
-    double* red = As[0];
-    red[tid] = dot;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    if (tid == 0) p.partials[blockIdx.x] = red[0];
-  }
 }
 
 struct OccArgs {
@@ -155,8 +128,7 @@ struct OccArgs {
   const double* x1;
   const double* x2;
   double* y1;
-  double* y2;  // plain: holds the virtual part on entry
-  double* t2;  // Lanczos: receives -(occupied part) - beta vprev (doubles)
+  double* y2;  // holds the virtual part on entry
   const double* vprev1;
   const double* vprev2;
   const double* beta;
@@ -197,8 +169,8 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
         for (int r = 0; r < R; ++r) {
           const int pr = pr0 + r * groups;
           const int64_t idx = (int64_t)(pr < oo ? pr : 0) * vv + ab0 + e;
+          yin[r] = p.y2[idx];
           if constexpr (LZ) vin[r] = p.vprev2[idx];
-          else yin[r] = p.y2[idx];
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -209,12 +181,13 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
           for (int k = 0; k < o; ++k)
             occ += fo[k * o + i] * xs[(k * o + j) * ch + e] + fo[k * o + j] * xs[(i * o + k) * ch + e];
           const int64_t idx = (int64_t)pr * vv + ab0 + e;
+          const double y = yin[r] - occ;
           if constexpr (LZ) {
-            const double q = -occ - beta * vin[r];
-            p.t2[idx] = q;
+            const double q = y - beta * vin[r];
+            p.y2[idx] = q;
             dot += xs[pr * ch + e] * q;
           } else {
-            p.y2[idx] = yin[r] - occ;
+            p.y2[idx] = y;
           }
         }
       }
@@ -255,30 +228,28 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
 
 bool aligned16(const void* q) { return ((uintptr_t)q & 15u) == 0; }
 
-template <bool LZ>
-void launch_vir(const FockOp& op, const double* x2, double* y2, double* partials, hipStream_t s) {
+void launch_vir(const FockOp& op, const double* x2, double* y2, hipStream_t s) {
   VirArgs a;
-  a.partials = partials;
   a.v = op.v;
   a.tiles_m = (int)ceil_div(op.v, op.bm);
   a.tiles = op.tiles;
   a.units = op.tiles * op.o * op.o;
-  a.per_xcd = op.vir_blocks() / 8;
+  a.per_xcd = (int)ceil_div(a.units, 8);
   a.vec = (op.v % 2 == 0 && aligned16(x2) && aligned16(op.f_vv)) ? 1 : 0;
   a.f_vv = op.f_vv;
   a.x2 = x2;
   a.y2 = y2;
-  dim3 grid((unsigned)op.vir_blocks());
+  dim3 grid((unsigned)(8 * a.per_xcd));
   // contraction panels of 32 for the 32-wide blocks when that pads v no
   // more than panels of 16 (measured: the wider blocks run better with 16)
   const bool bk32 = op.bm == 32 && ceil_div(op.v, 32) * 32 <= ceil_div(op.v, 16) * 16;
   switch (op.bm * 2 + (bk32 ? 1 : 0)) {
-    case 64: fock_vir_kernel<32, 2, 16, LZ><<<grid, 256, 0, s>>>(a); break;
-    case 65: fock_vir_kernel<32, 2, 32, LZ><<<grid, 256, 0, s>>>(a); break;
-    case 96: fock_vir_kernel<48, 4, 16, LZ><<<grid, 256, 0, s>>>(a); break;
-    case 97: fock_vir_kernel<48, 4, 32, LZ><<<grid, 256, 0, s>>>(a); break;
-    case 128: fock_vir_kernel<64, 2, 16, LZ><<<grid, 256, 0, s>>>(a); break;
-    default: fock_vir_kernel<64, 2, 32, LZ><<<grid, 256, 0, s>>>(a); break;
+    case 64: fock_vir_kernel<32, 2, 16><<<grid, 256, 0, s>>>(a); break;
+    case 65: fock_vir_kernel<32, 2, 32><<<grid, 256, 0, s>>>(a); break;
+    case 96: fock_vir_kernel<48, 4, 16><<<grid, 256, 0, s>>>(a); break;
+    case 97: fock_vir_kernel<48, 4, 32><<<grid, 256, 0, s>>>(a); break;
+    case 128: fock_vir_kernel<64, 2, 16><<<grid, 256, 0, s>>>(a); break;
+    default: fock_vir_kernel<64, 2, 32><<<grid, 256, 0, s>>>(a); break;
   }
   PNK_CHECK_LAUNCH();
 }
@@ -286,10 +257,9 @@ void launch_vir(const FockOp& op, const double* x2, double* y2, double* partials
 size_t occ_lds_bytes(int o, int ch) { return sizeof(double) * ((size_t)o * o * ch + (size_t)o * o); }
 
 template <bool LZ>
-void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, double* t2,
-                const double* vprev1, const double* vprev2, const double* beta, double* partials, hipStream_t s) {
+void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, const double* vprev1,
+                const double* vprev2, const double* beta, double* partials, hipStream_t s) {
   OccArgs a;
-  a.t2 = t2;
   a.o = op.o;
   a.v = op.v;
   a.ch = op.ch;
@@ -353,34 +323,34 @@ bool fock_op_plan(FockOp& op) {
 }
 
 bool fock_op_is_virtual_kernel(const void* func) {
-  return func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 16, true>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 32, true>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 16, true>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 32, true>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 16, true>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 32, true>);
+  return func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 16>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 32>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 16>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 32>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 16>) ||
+         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 32>);
 }
 
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(x1 != y1 && x2 != y2, "fock_op: output must not alias the input");
-  launch_vir<false>(op, x2, y2, nullptr, s);
-  launch_occ<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, nullptr, s);
+  launch_vir(op, x2, y2, s);
+  launch_occ<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, s);
 }
 
-void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, double* partials, hipStream_t s) {
+void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
   const int64_t ov = (int64_t)op.o * op.v;
-  launch_vir<true>(op, v + ov, p + ov, partials, s);
+  launch_vir(op, v + ov, p + ov, s);
 }
 
 void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                         double* t2, double* partials, hipStream_t s) {
+                         double* partials, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
   const int64_t ov = (int64_t)op.o * op.v;
-  launch_occ<true>(op, v, v + ov, p, nullptr, t2, vprev, vprev + ov, beta, partials, s);
+  launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, s);
 }
 
 }  // namespace pnk

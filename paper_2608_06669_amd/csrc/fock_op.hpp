@@ -28,9 +28,6 @@ struct FockOp {
   int ch = 0, nchunks = 0;  // occupied kernel: ch (ab) elements per workgroup
   int nsingles = 0;         // ... plus workgroups of 16 singles each
   int64_t nparts() const { return (int64_t)nchunks + nsingles; }
-  // workgroups of the virtual kernel (the pair-tile units padded to a
-  // multiple of the 8 XCDs); one partial sum each in the Lanczos form
-  int vir_blocks() const { return 8 * (int)ceil_div((int64_t)tiles * o * o, 8); }
 };
 
 // Picks the launch shapes; false when these kernels do not apply (o too
@@ -40,17 +37,14 @@ bool fock_op_plan(FockOp& op);
 // y = A_F x (y must not alias x)
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s);
 
-// The two launches on packed vectors in the Lanczos form (independent of
-// each other): fock_op_lanczos_vir writes the virtual part G of A_F v into
-// the doubles of p and partials_v[b] = sum over its workgroup b of v . G
-// (op.vir_blocks() entries); fock_op_lanczos_occ writes the singles of
-// A_F v - (*beta) vprev into p, the doubles of -(occupied part) - (*beta)
-// vprev into t2 (o*o*v*v), and partials[b] = its workgroup's share of v . p
-// (op.nparts() entries). p = G + t2 then, and <v, p> is the sum of both
-// sets. Each partial is summed in a fixed order; beta is a device scalar.
-void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, double* partials_v, hipStream_t s);
+// The same two launches on packed vectors with the first Lanczos update:
+// fock_op_lanczos_vir writes the virtual part of A_F v into p; then
+// fock_op_lanczos_occ completes p = A_F v - (*beta) vprev and writes
+// partials[b] = the sum over its workgroup b of v . p (op.nparts() entries,
+// each summed in a fixed order). beta is a device scalar.
+void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s);
 void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                         double* t2, double* partials, hipStream_t s);
+                         double* partials, hipStream_t s);
 
 // True for the virtual-contraction kernel (the launch that does the matrix
 // work), used to find its nodes in a recorded graph.

@@ -95,9 +95,6 @@ Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_
 Solver::~Solver() {
   if (lz_exec_) (void)hipGraphExecDestroy(lz_exec_);
   if (lz_exec_timed_) (void)hipGraphExecDestroy(lz_exec_timed_);
-  if (ev_fork_) (void)hipEventDestroy(ev_fork_);
-  if (ev_join_) (void)hipEventDestroy(ev_join_);
-  if (s2_) (void)hipStreamDestroy(s2_);
   for (hipEvent_t e : lz_ev_)
     if (e) (void)hipEventDestroy(e);
   for (double* p : {Qo_, Qi_, r_, ri_, w_, w2_, hx_, he_, dsc_, partials_})
@@ -202,23 +199,16 @@ __global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ 
   lz_block_partial(acc, sm, part1);
 }
 
-// alpha_k = <v_k, p> (the sum of one or two sets of partial sums, each in a
-// fixed order); when t is given, p += t over the doubles (elements from
-// `off`); then p -= alpha_k v_k and partial sums of <p, p>
+// alpha_k = <v_k, p>; p -= alpha_k v_k; partial sums of <p, p>
 __global__ __launch_bounds__(256) void lz_step2(int64_t n, double* __restrict__ p, const double* __restrict__ v,
                                                 const double* __restrict__ part1, int nparts1,
-                                                const double* __restrict__ part1b, int nparts1b,
-                                                const double* __restrict__ t, int64_t off,
                                                 double* __restrict__ st, double* __restrict__ part2) {
   __shared__ double sm[256];
-  double alpha = lz_block_sum(part1, nparts1, sm);
-  if (part1b) alpha += lz_block_sum(part1b, nparts1b, sm);
+  const double alpha = lz_block_sum(part1, nparts1, sm);
   if (blockIdx.x == 0 && threadIdx.x == 0) st[kAlpha] = alpha;  // read by lz_update only
   double acc = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    double x = p[i];
-    if (t && i >= off) x += t[i - off];
-    x -= alpha * v[i];
+    const double x = p[i] - alpha * v[i];
     p[i] = x;
     acc += x * x;
   }
@@ -302,48 +292,25 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
   const int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
   double* part1 = partials_;
-  double* part1b = partials_ + kMaxFusedParts;
-  double* part2 = partials_ + 2 * kMaxFusedParts;
+  double* part2 = partials_ + kMaxFusedParts;
   const FockOp* op = eng_.fock_op();
-  if (op && fused_lanczos_ok(*op)) {
-    // The virtual launch (stream s) and the occupied launch (stream s2_)
-    // are independent; step 2 joins them: p = G + t, alpha from both sets
-    // of partial sums. The timer covers the virtual launch.
-    double* tbuf = Qi_ + 6 * n;
-    PNK_HIP(hipEventRecord(ev_fork_, s));
-    PNK_HIP(hipStreamWaitEvent(s2_, ev_fork_, 0));
-    fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, tbuf, part1b, s2_);
-    PNK_HIP(hipEventRecord(ev_join_, s2_));
+  int nparts1 = kLzBlocks;
+  if (op && op->nparts() <= kMaxFusedParts) {
+    // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p>; the timer
+    // covers the virtual (matrix-core) launch
     Timers* tm = eng_.timers();
     if (tm) tm->begin(kTimerFock, s);
-    fock_op_lanczos_vir(*op, v, p, part1, s);
+    fock_op_lanczos_vir(*op, v, p, s);
     if (tm) tm->end(kTimerFock, s);
-    PNK_HIP(hipStreamWaitEvent(s, ev_join_, 0));
-    lz_step2<<<kLzBlocks, 256, 0, s>>>(n, p, v, part1, op->vir_blocks(), part1b, (int)op->nparts(), tbuf, ov, st,
-                                       part2);
+    fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, part1, s);
+    nparts1 = (int)op->nparts();
   } else {
     eng_.fock_apply(v, v + ov, p, p + ov, s);
     lz_step1<<<kLzBlocks, 256, 0, s>>>(n, p, vprev, v, st, part1);
-    lz_step2<<<kLzBlocks, 256, 0, s>>>(n, p, v, part1, kLzBlocks, nullptr, 0, nullptr, 0, st, part2);
   }
+  lz_step2<<<kLzBlocks, 256, 0, s>>>(n, p, v, part1, nparts1, st, part2);
   lz_update<<<kLzBlocks, 256, 0, s>>>(n, v, w1, w2, x, p, part2, st, stn);
   PNK_CHECK_LAUNCH();
-}
-
-// The two-stream form needs the fused kernels, a seventh inner vector for t
-// and room for both sets of partial sums; it also creates its stream and
-// events on first use.
-bool Solver::fused_lanczos_ok(const FockOp& op) {
-  if (op.nparts() > kMaxFusedParts || op.vir_blocks() > kMaxFusedParts || restart_ < 6) return false;
-  if (!s2_) {
-    if (hipStreamCreateWithFlags(&s2_, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_fork_, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&ev_join_, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      return false;
-    }
-  }
-  return true;
 }
 
 // Six steps: the buffer rotation (v: period 3, w: period 2, state slot:
@@ -477,7 +444,7 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   PNK_CHECK_LAUNCH();
   Timers* tm = eng_.timers();
   const FockOp* op = eng_.fock_op();
-  const bool fused = op && fused_lanczos_ok(*op);
+  const bool fused = op && op->nparts() <= kMaxFusedParts;
   const bool timed = use_graphs_ && tm && fused && ensure_lanczos_graph(true);
   const bool graph = timed || (use_graphs_ && ensure_lanczos_graph(false));
   int it = 0;

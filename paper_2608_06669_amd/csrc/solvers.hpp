@@ -6,7 +6,6 @@
 #include <vector>
 
 #include "ccsd.hpp"
-#include "fock_op.hpp"
 
 namespace pnk {
 
@@ -100,9 +99,6 @@ class Solver {
   bool lz_graph_failed_ = false;
   hipGraphExec_t lz_exec_ = nullptr;
   hipGraphExec_t lz_exec_timed_ = nullptr;
-  hipStream_t s2_ = nullptr;  // second stream of the inner solve (default priority)
-  hipEvent_t ev_fork_ = nullptr, ev_join_ = nullptr;
-  bool fused_lanczos_ok(const FockOp& op);
   bool lz_timed_failed_ = false;
   hipEvent_t lz_ev_[2 * kLanczosBlock] = {};
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
