@@ -149,6 +149,13 @@ int64_t splitk_elems(const Sizes& z) {
   return std::min<int64_t>(std::max<int64_t>(16 * big, 1 << 16), 3 * 1024 * 1024);
 }
 
+// Rounded copies of FP64 operands for the FP32/BF16 products of J v: room
+// for both operands of the largest dual product (the ring term, 2ov x 2ov).
+int64_t cast_bytes(const Sizes& z, const EngineOptions& opt) {
+  if (!opt.lowp_f32 && !opt.lowp_bf16) return 0;
+  return (opt.lowp_f32 ? 4 : 2) * 4 * z.n2 + 1024;
+}
+
 // Calls `f(count_doubles)` for every FP64 buffer in allocation order, and
 // `g(count_bytes)` for the low-precision copies.
 template <class F, class G>
@@ -162,6 +169,7 @@ void for_each_buffer(const Sizes& z, const EngineOptions& opt, F f, G g) {
   f(o * v * v * v); f(n2); f(n2); f(n2); f(n2); f(n2);
   if (opt.lowp_f32) { g(4 * p2 * p2); g(4 * p2m * p2m); g(4 * o * v * v * v); g(4 * n2); g(4 * n2); g(4 * n2); g(4 * n2); }
   if (opt.lowp_bf16) { g(2 * p2 * p2); g(2 * p2m * p2m); g(2 * o * v * v * v); g(2 * n2); g(2 * n2); g(2 * n2); g(2 * n2); }
+  g(cast_bytes(z, opt));
   // intermediates, value and tangent
   for (int rep = 0; rep < 2; ++rep) {
     f(np * o * o); f(np * ov); f(np * v * v); f(naux); f(naux * o * o); f(naux * ov);
@@ -217,6 +225,8 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
     Ioovv.lp16 = arena_.take<uint16_t>(N2); Iovov.lp16 = arena_.take<uint16_t>(N2);
     Ix.lp16 = arena_.take<uint16_t>(N2); Ikldc.lp16 = arena_.take<uint16_t>(N2);
   }
+  cast_bytes_ = cast_bytes(z, opt);
+  if (cast_bytes_) cast_ws_ = arena_.take<char>((size_t)cast_bytes_);
   Ten* inter[] = {&Loo, &Lvo, &Lvv, &this->D, &LooT, &LvoT, &Foo, &Fov, &Fvo, &Fvv,
                   &U, &Tail, &Tsail, &Uail, &Ukdic, &Uklca, &Uiakc, &Tmp, &X,
                   &Gv, &Go, &Kilj, &Wkl, &Y, &Z, &J, &Kp, &Q, &QT, &LvvT, &Kilc, &KilcT,

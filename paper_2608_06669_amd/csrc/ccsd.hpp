@@ -188,9 +188,13 @@ class Engine {
   bool graph_ready(GraphSlot* slot, const void* k0, const void* k1, const void* k2, const void* k3, Mode m);
   double* ws_ = nullptr;  // split-K partial sums
   int64_t ws_elems_ = 0;
+  void* cast_ws_ = nullptr;  // rounded operand copies for FP32/BF16 products
+  int64_t cast_bytes_ = 0;
   GemmDesc with_ws(GemmDesc d) const {
     d.ws = ws_;
     d.ws_elems = ws_elems_;
+    d.cast_ws = cast_ws_;
+    d.cast_ws_bytes = cast_bytes_;
     return d;
   }
 };

@@ -410,11 +410,118 @@ void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A
 
 namespace {
 
+// Rounds one FP64 operand of a (batched) product to the compute type and
+// writes it as rows contiguous along k: out[b][r][koff + k] (row length
+// ld) = in[b0 * s_b0 + b1 * s_b1 + r * s_r + k * s_k], b = b1 * nb0 + b0.
+// 32 x 32 tiles through LDS, so reads are coalesced along whichever index
+// is contiguous in the input and writes along k.
+struct PackArgs {
+  const double* in;
+  int64_t s_r, s_k, s_b0, s_b1;
+  int rows, K, nb0, ld, koff;
+  void* out;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void pack_operand(PackArgs p) {
+  __shared__ double tile[32][33];
+  const int tiles_k = (p.K + 31) / 32;
+  const int r0 = (blockIdx.x / tiles_k) * 32, k0 = (blockIdx.x % tiles_k) * 32;
+  const int b = blockIdx.y;
+  const int b0 = b % p.nb0, b1 = b / p.nb0;
+  const double* in = p.in + b0 * p.s_b0 + b1 * p.s_b1;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const bool along_r = p.s_r == 1 && p.s_k != 1;
+  for (int j = ty; j < 32; j += 8) {
+    // along_r: consecutive lanes walk r; otherwise they walk k
+    const int r = along_r ? r0 + tx : r0 + j;
+    const int k = along_r ? k0 + j : k0 + tx;
+    double x = 0.0;
+    if (r < p.rows && k < p.K) x = in[(int64_t)r * p.s_r + (int64_t)k * p.s_k];
+    if (along_r) tile[tx][j] = x;
+    else tile[j][tx] = x;
+  }
+  __syncthreads();
+  T* out = (T*)p.out + (int64_t)b * p.rows * p.ld;
+  for (int j = ty; j < 32; j += 8) {
+    const int r = r0 + j, k = k0 + tx;
+    if (r < p.rows && k < p.K) out[(int64_t)r * p.ld + p.koff + k] = to_lds<double, T>(tile[j][tx]);
+  }
+}
+
+template <typename T>
+void pack(const double* in, int64_t s_r, int64_t s_k, int64_t s_b0, int64_t s_b1, int rows, int K, int nb0, int nb1,
+          int ld, int koff, void* out, hipStream_t s) {
+  PackArgs p{in, s_r, s_k, s_b0, s_b1, rows, K, nb0, ld, koff, out};
+  dim3 grid((unsigned)(ceil_div(rows, 32) * ceil_div(K, 32)), (unsigned)(nb0 * nb1));
+  pack_operand<T><<<grid, 256, 0, s>>>(p);
+  PNK_CHECK_LAUNCH();
+}
+
+void gemm_impl(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, Prec ap, Prec bp,
+               void* C, Prec cp, Prec compute, hipStream_t s);
+
+// FP32/BF16 product with FP64 operands rounded once into d.cast_ws (both
+// products of a dual call side by side along k). Returns false when it does
+// not apply or does not fit.
+bool gemm_precast(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, Prec ap, Prec bp,
+                  void* C, Prec cp, Prec compute, hipStream_t s) {
+  if (!d.cast_ws || (compute != Prec::F32 && compute != Prec::BF16)) return false;
+  const bool pa = ap == Prec::F64, pb = bp == Prec::F64;
+  if (!pa && !pb) return false;
+  const int64_t nb = (int64_t)d.nb0 * d.nb1;
+  if ((double)d.M * d.N * d.K * nb < 1e7) return false;  // small: convert on load
+  const bool dual = A2 != nullptr;
+  if (dual && pa != pb) return false;
+  const int64_t es = compute == Prec::BF16 ? 2 : 4;
+  const int kt = dual ? 2 * d.K : d.K;
+  const int64_t need = es * nb * ((pa ? (int64_t)d.M * kt : 0) + (pb ? (int64_t)d.N * kt : 0)) + 256;
+  if (need > d.cast_ws_bytes) return false;
+  char* base = (char*)d.cast_ws;
+  char* abuf = base;
+  char* bbuf = base + (((pa ? es * nb * (int64_t)d.M * kt : 0) + 255) & ~int64_t(255));
+  GemmDesc e = d;
+  e.cast_ws = nullptr;
+  const void *An = A, *Bn = B;
+  Prec apn = ap, bpn = bp;
+  auto run_pack = [&](const void* src, bool is_a, int koff, void* dst) {
+    const double* in = (const double*)src;
+    const int rows = is_a ? d.M : d.N;
+    const int64_t sr = is_a ? d.a_m : d.b_n, sk = is_a ? d.a_k : d.b_k;
+    const int64_t sb0 = is_a ? d.a_b0 : d.b_b0, sb1 = is_a ? d.a_b1 : d.b_b1;
+    if (es == 2) pack<uint16_t>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, kt, koff, dst, s);
+    else pack<float>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, kt, koff, dst, s);
+  };
+  if (pa) {
+    run_pack(A, true, 0, abuf);
+    if (dual) run_pack(A2, true, d.K, abuf);
+    An = abuf;
+    apn = compute;
+    e.a_m = kt; e.a_k = 1; e.a_b0 = (int64_t)d.M * kt; e.a_b1 = (int64_t)d.nb0 * d.M * kt;
+  }
+  if (pb) {
+    run_pack(B, false, 0, bbuf);
+    if (dual) run_pack(B2, false, d.K, bbuf);
+    Bn = bbuf;
+    bpn = compute;
+    e.b_n = kt; e.b_k = 1; e.b_b0 = (int64_t)d.N * kt; e.b_b1 = (int64_t)d.nb0 * d.N * kt;
+  }
+  if (dual) {
+    // both products packed along k: one product of depth 2K
+    e.K = kt;
+    gemm_impl(e, An, Bn, nullptr, nullptr, apn, bpn, C, cp, compute, s);
+  } else {
+    gemm_impl(e, An, Bn, nullptr, nullptr, apn, bpn, C, cp, compute, s);
+  }
+  return true;
+}
+
 void gemm_impl(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, Prec ap, Prec bp,
                void* C, Prec cp, Prec compute, hipStream_t s) {
   if (d.M <= 0 || d.N <= 0 || d.nb0 <= 0 || d.nb1 <= 0) return;
   PNK_REQUIRE(cp == Prec::F64 || cp == Prec::F32, "gemm: C must be f64 or f32");
   PNK_REQUIRE(d.K > 0, "gemm: K must be positive");
+  if (gemm_precast(d, A, B, A2, B2, ap, bp, C, cp, compute, s)) return;
 #define PNK_GEMM_CASE(MMA, TA, TB, TC, BK) return launch_sized<MMA, TA, TB, TC, BK>(d, A, B, A2, B2, C, s)
   if (compute == Prec::F64) {
     PNK_REQUIRE(ap == Prec::F64 && bp == Prec::F64, "gemm: f64 compute needs f64 operands");

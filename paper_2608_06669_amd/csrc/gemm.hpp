@@ -28,6 +28,12 @@ struct GemmDesc {
   // nb0 * nb1 * M * N doubles; S is reduced to fit ws_elems.
   double* ws = nullptr;
   int64_t ws_elems = 0;
+  // Optional scratch for FP32/BF16 products with FP64 operands: large
+  // products first round each FP64 operand once into this buffer (rows
+  // contiguous along k) instead of converting it in every tile that reads
+  // it. Products whose packed operands do not fit are converted on load.
+  void* cast_ws = nullptr;
+  int64_t cast_ws_bytes = 0;
 };
 
 // Pointers carry their storage precision; `compute` selects the matrix-core
