@@ -133,20 +133,21 @@ struct OccArgs {
   const double* vprev2;
   const double* beta;
   double* partials;
+  double s1;  // factor on the A_F part of the singles
 };
 
 // Dynamic LDS: xs[o*o][ch] then fo[o][o].
 template <bool LZ>
 __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
   extern __shared__ double lds[];
-  __shared__ double red[256];
+  __shared__ double red[3][256];
   const int o = p.o, v = p.v, ch = p.ch;
   const int oo = o * o;
   const int64_t vv = (int64_t)v * v, ov = (int64_t)o * v;
   const int tid = threadIdx.x;
   double beta = 0.0;
   if constexpr (LZ) beta = *p.beta;
-  double dot = 0.0;
+  double dot = 0.0, nrm = 0.0, vv2 = 0.0;
 
   if ((int)blockIdx.x < p.nchunks) {
     double* xs = lds;
@@ -184,8 +185,11 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
           const double y = yin[r] - occ;
           if constexpr (LZ) {
             const double q = y - beta * vin[r];
+            const double vk = xs[pr * ch + e];
             p.y2[idx] = q;
-            dot += xs[pr * ch + e] * q;
+            dot += vk * q;
+            nrm += q * q;
+            vv2 += vk * vk;
           } else {
             p.y2[idx] = y;
           }
@@ -204,11 +208,15 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
     }
     // fixed-order butterfly over the 16 lanes of this output
     for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
+    part *= p.s1;
     if (out < ov && l == 0) {
       if constexpr (LZ) {
         const double q = part - beta * p.vprev1[out];
+        const double vk = p.x1[out];
         p.y1[out] = q;
-        dot += p.x1[out] * q;
+        dot += vk * q;
+        nrm += q * q;
+        vv2 += vk * vk;
       } else {
         p.y1[out] = part;
       }
@@ -216,13 +224,17 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
   }
 
   if constexpr (LZ) {
-    red[tid] = dot;
+    red[0][tid] = dot;
+    red[1][tid] = nrm;
+    red[2][tid] = vv2;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
+      if (tid < s)
+        for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + s];
       __syncthreads();
     }
-    if (tid == 0) p.partials[blockIdx.x] = red[0];
+    if (tid == 0)
+      for (int c = 0; c < 3; ++c) p.partials[c * gridDim.x + blockIdx.x] = red[c][0];
   }
 }
 
@@ -258,7 +270,7 @@ size_t occ_lds_bytes(int o, int ch) { return sizeof(double) * ((size_t)o * o * c
 
 template <bool LZ>
 void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, const double* vprev1,
-                const double* vprev2, const double* beta, double* partials, hipStream_t s) {
+                const double* vprev2, const double* beta, double* partials, double s1, hipStream_t s) {
   OccArgs a;
   a.o = op.o;
   a.v = op.v;
@@ -274,6 +286,7 @@ void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1
   a.vprev2 = vprev2;
   a.beta = beta;
   a.partials = partials;
+  a.s1 = s1;
   fock_occ_kernel<LZ><<<(unsigned)op.nparts(), 256, occ_lds_bytes(op.o, op.ch), s>>>(a);
   PNK_CHECK_LAUNCH();
 }
@@ -335,7 +348,7 @@ void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double*
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(x1 != y1 && x2 != y2, "fock_op: output must not alias the input");
   launch_vir(op, x2, y2, s);
-  launch_occ<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, s);
+  launch_occ<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, 1.0, s);
 }
 
 void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s) {
@@ -346,11 +359,11 @@ void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream
 }
 
 void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                         double* partials, hipStream_t s) {
+                         double* partials, double singles_scale, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
   const int64_t ov = (int64_t)op.o * op.v;
-  launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, s);
+  launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, singles_scale, s);
 }
 
 }  // namespace pnk

@@ -39,12 +39,14 @@ void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double*
 
 // The same two launches on packed vectors with the first Lanczos update:
 // fock_op_lanczos_vir writes the virtual part of A_F v into p; then
-// fock_op_lanczos_occ completes p = A_F v - (*beta) vprev and writes
-// partials[b] = the sum over its workgroup b of v . p (op.nparts() entries,
-// each summed in a fixed order). beta is a device scalar.
+// fock_op_lanczos_occ completes p = S A_F v - (*beta) vprev and writes, for
+// each workgroup b, its shares of v . p, p . p and v . v in partials[b],
+// partials[nparts + b] and partials[2 nparts + b] (nparts = op.nparts(),
+// each share summed in a fixed order). beta is a device scalar; S multiplies the singles rows by
+// singles_scale and leaves the doubles rows alone.
 void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s);
 void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                         double* partials, hipStream_t s);
+                         double* partials, double singles_scale, hipStream_t s);
 
 // True for the virtual-contraction kernel (the launch that does the matrix
 // work), used to find its nodes in a recorded graph.

@@ -155,8 +155,16 @@ namespace {
 enum { kBeta = 0, kAlpha, kBetaN, kC2, kS2, kC1, kS1, kPhiBar, kRho1, kDelta, kEps, kPhi, kRes, kInvB, kNState };
 constexpr int kStateStride = 16;
 constexpr int kLzBlocks = 512;
+// With f_ov = 0, A_F is block diagonal and its doubles block is the
+// Kronecker sum of the singles block with itself (A_F, equation
+// Preconditioner and its working equations): its spectrum spans exactly
+// [2 lmin, 2 lmax] when the singles spectrum spans [lmin, lmax]. The
+// symmetric inner solve therefore runs on D^1/2 A_F D^1/2 with D = 2 on
+// the singles, which brings both blocks onto [2 lmin, 2 lmax] and halves
+// the condition number (about 1/sqrt(2) as many Lanczos steps).
+constexpr double kInnerSinglesScale = 2.0;
 
-constexpr int kMaxFusedParts = 16384;  // partial sums written by the fused A_F launch
+constexpr int kMaxFusedParts = 16384;  // workgroups of the fused A_F launch (three partials each)
 
 // Fixed-order sum of n partials by one workgroup of 256 threads (every
 // workgroup that calls it gets the same bits).
@@ -184,48 +192,50 @@ __device__ inline void lz_block_partial(double acc, double* sm, double* partials
   if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
 }
 
-// p -= beta_k v_{k-1}; partial sums of <v_k, p>
+// p = S p - beta_k v_{k-1} (S scales the first n1 entries by s1); partial
+// sums of <v_k, p>, <p, p> and <v_k, v_k> (part1[b], part1[G + b],
+// part1[2 G + b], G = gridDim.x)
 __global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ p, const double* __restrict__ vprev,
                                                 const double* __restrict__ v, const double* __restrict__ st,
-                                                double* __restrict__ part1) {
+                                                double* __restrict__ part1, int64_t n1, double s1) {
   __shared__ double sm[256];
   const double beta = st[kBeta];
-  double acc = 0.0;
+  double dot = 0.0, nrm = 0.0, vv2 = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double x = p[i] - beta * vprev[i];
+    const double x = (i < n1 ? s1 : 1.0) * p[i] - beta * vprev[i];
+    const double vk = v[i];
     p[i] = x;
-    acc += v[i] * x;
+    dot += vk * x;
+    nrm += x * x;
+    vv2 += vk * vk;
   }
-  lz_block_partial(acc, sm, part1);
+  lz_block_partial(dot, sm, part1);
+  __syncthreads();
+  lz_block_partial(nrm, sm, part1 + gridDim.x);
+  __syncthreads();
+  lz_block_partial(vv2, sm, part1 + 2 * gridDim.x);
 }
 
-// alpha_k = <v_k, p>; p -= alpha_k v_k; partial sums of <p, p>
-__global__ __launch_bounds__(256) void lz_step2(int64_t n, double* __restrict__ p, const double* __restrict__ v,
-                                                const double* __restrict__ part1, int nparts1,
-                                                double* __restrict__ st, double* __restrict__ part2) {
-  __shared__ double sm[256];
-  const double alpha = lz_block_sum(part1, nparts1, sm);
-  if (blockIdx.x == 0 && threadIdx.x == 0) st[kAlpha] = alpha;  // read by lz_update only
-  double acc = 0.0;
-  for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double x = p[i] - alpha * v[i];
-    p[i] = x;
-    acc += x * x;
-  }
-  lz_block_partial(acc, sm, part2);
-}
-
-// beta_{k+1} = ||p||; one Givens rotation of the tridiagonal QR; then
+// alpha_k = <v_k, p> / <v_k, v_k> and beta_{k+1} = ||p - alpha_k v_k||,
+// from ||p||^2 - <v_k, p>^2 / <v_k, v_k> (p - alpha_k v_k is orthogonal to
+// v_k), all from the partials of the launch before. Measuring <v_k, v_k>
+// rather than taking it as 1 keeps a rounding error in the norm of v_k from
+// growing from step to step. Then one Givens rotation of the tridiagonal
+// QR, and
 // w_k = (v_k - delta w_{k-1} - eps w_{k-2}) / rho1 (into the w_{k-2} slot),
-// x += phi w_k, v_{k+1} = p / beta_{k+1} (in place)
+// x += phi w_k, v_{k+1} = (p - alpha_k v_k) / beta_{k+1} (in place)
 __global__ __launch_bounds__(256) void lz_update(int64_t n, const double* __restrict__ v,
                                                  const double* __restrict__ w1, double* __restrict__ w2,
                                                  double* __restrict__ x, double* __restrict__ p,
-                                                 const double* __restrict__ part2, const double* __restrict__ st,
-                                                 double* __restrict__ stn) {
+                                                 const double* __restrict__ part1, int nparts1,
+                                                 const double* __restrict__ st, double* __restrict__ stn) {
   __shared__ double sm[256];
-  const double betan = sqrt(lz_block_sum(part2, kLzBlocks, sm));
-  const double beta = st[kBeta], alpha = st[kAlpha];
+  const double vp = lz_block_sum(part1, nparts1, sm);
+  const double pp = lz_block_sum(part1 + nparts1, nparts1, sm);
+  const double vv = lz_block_sum(part1 + 2 * nparts1, nparts1, sm);
+  const double alpha = vp / vv;
+  const double betan = sqrt(fmax(pp - alpha * vp, 0.0));
+  const double beta = st[kBeta];
   const double c2 = st[kC2], s2 = st[kS2], c1 = st[kC1], s1 = st[kS1];
   const double eps = s2 * beta;
   const double dbar = c2 * beta;
@@ -253,14 +263,14 @@ __global__ __launch_bounds__(256) void lz_update(int64_t n, const double* __rest
     stn[kInvB] = invb;
   }
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const double w = (v[i] - delta * w1[i] - eps * w2[i]) * ir;
+    const double vi = v[i];
+    const double w = (vi - delta * w1[i] - eps * w2[i]) * ir;
     w2[i] = w;
     x[i] += phi * w;
-    p[i] *= invb;
+    p[i] = (p[i] - alpha * vi) * invb;
   }
 }
 
-// state init (slot 0): beta_1 = ||b|| (v_0 = 0)
 __global__ void lz_init(double* st, const double* bnorm) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int k = 0; k < kNState; ++k) st[k] = 0.0;
@@ -292,7 +302,6 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
   const int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
   double* part1 = partials_;
-  double* part2 = partials_ + kMaxFusedParts;
   const FockOp* op = eng_.fock_op();
   int nparts1 = kLzBlocks;
   if (op && op->nparts() <= kMaxFusedParts) {
@@ -302,14 +311,13 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
     if (tm) tm->begin(kTimerFock, s);
     fock_op_lanczos_vir(*op, v, p, s);
     if (tm) tm->end(kTimerFock, s);
-    fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, part1, s);
+    fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, s);
     nparts1 = (int)op->nparts();
   } else {
     eng_.fock_apply(v, v + ov, p, p + ov, s);
-    lz_step1<<<kLzBlocks, 256, 0, s>>>(n, p, vprev, v, st, part1);
+    lz_step1<<<kLzBlocks, 256, 0, s>>>(n, p, vprev, v, st, part1, ov, kInnerSinglesScale);
   }
-  lz_step2<<<kLzBlocks, 256, 0, s>>>(n, p, v, part1, nparts1, st, part2);
-  lz_update<<<kLzBlocks, 256, 0, s>>>(n, v, w1, w2, x, p, part2, st, stn);
+  lz_update<<<kLzBlocks, 256, 0, s>>>(n, v, w1, w2, x, p, part1, nparts1, st, stn);
   PNK_CHECK_LAUNCH();
 }
 
@@ -426,6 +434,8 @@ bool Solver::ensure_lanczos_graph(bool timed) {
 // convergence; they only lower the residual further).
 int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged) {
   const int64_t n = n_;
+  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  const double rs = std::sqrt(kInnerSinglesScale);
   double bn, dummy;
   norms(b, &dummy, &bn, s);
   if (converged) *converged = true;
@@ -435,8 +445,13 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   }
   double* st = lanczos_state();  // slot 0 holds the state after every block
   double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *xi = Qi_ + 5 * n;
+  // scaled system D^1/2 A_F D^1/2 z = D^1/2 b, x = D^1/2 z, D = diag(s I, I)
+  copy(n, b, xi, s);
+  axpby(ov, rs, b, 0.0, xi, s);
+  double bhn;
+  norms(xi, &dummy, &bhn, s);
   lz_init<<<1, 1, 0, s>>>(st, dsc_ + 1);
-  scale_by_inverse(n, b, dsc_ + 1, v, s);  // v_1 = b / ||b||
+  scale_by_inverse(n, xi, dsc_ + 1, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
   fill(n, 0.0, vprev, s);
   fill(n, 0.0, w1, s);
   fill(n, 0.0, w2, s);
@@ -460,11 +475,13 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
         if (hipEventElapsedTime(&ms, lz_ev_[2 * k], lz_ev_[2 * k + 1]) == hipSuccess) tm->add(kTimerFock, 1, ms);
         else (void)hipGetLastError();
       }
+    // ||b - A_F x|| <= ||D^1/2 (b - A_F x)|| = the scaled residual (D >= I)
     const double res = host_[kRes];
     if (!std::isfinite(res)) break;
     if (res <= rtol * bn || host_[kBeta] == 0.0) { conv = true; break; }
   }
   copy(n, xi, x, s);
+  axpby(ov, rs, xi, 0.0, x, s);
   if (converged) *converged = conv;
   return it;
 }
