@@ -299,17 +299,22 @@ def bench_inner(args):
     h = pk.Handle(0)
     P = pk.DeviceProblem.from_problem(p)
     b1, b2 = (torch.as_tensor(a, device="cuda") for a in random_amplitudes(o, v, 77, scale=1.0))
-    h.precond_solve(P, b1, b2)  # warm-up: integral preparation and graph recording
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    iters = 0
-    for _ in range(args.steps):
-        _, _, it, _ = h.precond_solve(P, b1, b2)
-        iters += it
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    print(json.dumps({"workload": "inner A_F solves, o=10 v=90", "solves": args.steps, "products": iters,
-                      "us_per_product": 1e6 * dt / max(iters, 1), "n_vector": o * v + o * o * v * v}), flush=True)
+    out = {"workload": "inner A_F solves, o=10 v=90", "solves": args.steps, "n_vector": o * v + o * o * v * v}
+    # full layout (cc_precond_solve), then the packed pair layout the PNK
+    # solver uses (cc_precond_solve_pairsym)
+    for name, sym in (("full", False), ("pairsym", True)):
+        h.precond_solve(P, b1, b2, pair_symmetric=sym)  # warm-up: preparation and graph recording
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters = 0
+        for _ in range(args.steps):
+            _, _, it, _ = h.precond_solve(P, b1, b2, pair_symmetric=sym)
+            iters += it
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[name] = {"products": iters, "us_per_product": 1e6 * dt / max(iters, 1),
+                     "ms_per_solve": 1e3 * dt / args.steps}
+    print(json.dumps(out), flush=True)
     h.close()
 
 

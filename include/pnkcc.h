@@ -119,12 +119,26 @@ cc_status cc_jvp(cc_handle* h, const cc_problem* p, const double* t1, const doub
 cc_status cc_fock_apply(cc_handle* h, const cc_problem* p, const double* x1, const double* x2, double* y1,
                         double* y2, void* stream);
 
-/* Solve A_F x = b by restarted GMRES (restart 30) to
- * ||b - A_F x||_2 <= rtol ||b||_2 or maxit A_F products; the iteration count
- * goes to iters_out (host, may be NULL). Returns CC_NOT_CONVERGED when maxit
- * is reached first. Synchronises. */
+/* Solve A_F x = b (the preconditioner of equation Preconditioner, inverted
+ * by GMRES as in Algorithm 1) to ||b - A_F x||_2 <= rtol ||b||_2 or maxit
+ * A_F products; the product count goes to iters_out (host, may be NULL).
+ * When f_ov = 0, A_F is symmetric and GMRES takes its Lanczos (MINRES)
+ * form, run on D^1/2 A_F D^1/2 with D = 2 on the singles and 1 on the
+ * doubles (same solution; the scaled residual bounds the true one).
+ * Otherwise restarted GMRES (restart 30). Returns CC_NOT_CONVERGED when
+ * maxit is reached first. Synchronises. */
 cc_status cc_precond_solve(cc_handle* h, const cc_problem* p, const double* b1, const double* b2, double* x1,
                            double* x2, double rtol, int maxit, int* iters_out, void* stream);
+
+/* cc_precond_solve for a pair-symmetric right-hand side, b2[j][i][b][a] =
+ * b2[i][j][a][b], as every closed-shell amplitude vector is (the residual,
+ * J v and their preconditioned images). When f_ov = 0 the Lanczos vectors
+ * then hold only the pairs i <= j, which halves their memory traffic and
+ * the virtual contractions. What is solved is the pair-symmetric part of b
+ * ((b2[i][j] + b2[j][i]^T) / 2); x is pair-symmetric. Same arguments and
+ * errors as cc_precond_solve. */
+cc_status cc_precond_solve_pairsym(cc_handle* h, const cc_problem* p, const double* b1, const double* b2, double* x1,
+                                   double* x2, double rtol, int maxit, int* iters_out, void* stream);
 
 /* PNK options (Appendix F; Section "Adaptive Forcing").
  * tol_inf:   stop when ||r||_inf < tol_inf

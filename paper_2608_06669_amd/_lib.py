@@ -82,6 +82,7 @@ SIGNATURES = {
     "cc_jvp": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, P, P, I, P]),
     "cc_fock_apply": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, P]),
     "cc_precond_solve": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, D, I, ctypes.POINTER(I), P]),
+    "cc_precond_solve_pairsym": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, D, I, ctypes.POINTER(I), P]),
     "cc_pnk_opts_default": (None, [ctypes.POINTER(cc_pnk_opts)]),
     "cc_fp_opts_default": (None, [ctypes.POINTER(cc_fp_opts)]),
     "cc_solve_pnk": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_pnk_opts), P, P,

@@ -135,11 +135,14 @@ class Handle:
                                          _stream(stream)))
         return y1, y2
 
-    def precond_solve(self, p: DeviceProblem, b1, b2, rtol=1e-12, maxit=200, stream=None):
+    def precond_solve(self, p: DeviceProblem, b1, b2, rtol=1e-12, maxit=200, stream=None, pair_symmetric=False):
+        """A_F x = b; pair_symmetric=True calls cc_precond_solve_pairsym (b2
+        must satisfy b2[j, i] = b2[i, j].T)."""
         x1, x2 = torch.empty_like(b1), torch.empty_like(b2)
         it = ctypes.c_int(0)
-        st = self._check(_lib().cc_precond_solve(self._h, ctypes.byref(p.struct), _ptr(b1), _ptr(b2), _ptr(x1),
-                                                 _ptr(x2), rtol, maxit, ctypes.byref(it), _stream(stream)),
+        fn = _lib().cc_precond_solve_pairsym if pair_symmetric else _lib().cc_precond_solve
+        st = self._check(fn(self._h, ctypes.byref(p.struct), _ptr(b1), _ptr(b2), _ptr(x1), _ptr(x2), rtol, maxit,
+                            ctypes.byref(it), _stream(stream)),
                          ok=(L.CC_OK, L.CC_NOT_CONVERGED))
         return x1, x2, it.value, st == L.CC_OK
 

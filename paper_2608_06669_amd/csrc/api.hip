@@ -295,8 +295,9 @@ cc_status cc_fock_apply(cc_handle* h, const cc_problem* p, const double* x1, con
   PNK_API_END
 }
 
-cc_status cc_precond_solve(cc_handle* h, const cc_problem* p, const double* b1, const double* b2, double* x1,
-                           double* x2, double rtol, int maxit, int* iters_out, void* stream) {
+static cc_status precond_solve_impl(cc_handle* h, const cc_problem* p, const double* b1, const double* b2,
+                                    double* x1, double* x2, double rtol, int maxit, int* iters_out, void* stream,
+                                    bool pair_symmetric) {
   PNK_API_BEGIN(h)
   hipStream_t s = (hipStream_t)stream;
   PNK_REQUIRE(b1 && b2 && x1 && x2, "array arguments must not be NULL");
@@ -305,12 +306,22 @@ cc_status cc_precond_solve(cc_handle* h, const cc_problem* p, const double* b1, 
   const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
   pack(ov, n2, b1, b2, H->xb, s);
   bool conv = true;
-  const int it = H->sol->precond_solve(H->xb, H->xa, rtol, maxit, 30, s, &conv);
+  const int it = H->sol->precond_solve(H->xb, H->xa, rtol, maxit, 30, s, &conv, pair_symmetric);
   unpack(ov, n2, H->xa, x1, x2, s);
   PNK_HIP(hipStreamSynchronize(s));
   if (iters_out) *iters_out = it;
   return conv ? CC_OK : CC_NOT_CONVERGED;
   PNK_API_END
+}
+
+cc_status cc_precond_solve(cc_handle* h, const cc_problem* p, const double* b1, const double* b2, double* x1,
+                           double* x2, double rtol, int maxit, int* iters_out, void* stream) {
+  return precond_solve_impl(h, p, b1, b2, x1, x2, rtol, maxit, iters_out, stream, false);
+}
+
+cc_status cc_precond_solve_pairsym(cc_handle* h, const cc_problem* p, const double* b1, const double* b2, double* x1,
+                                   double* x2, double rtol, int maxit, int* iters_out, void* stream) {
+  return precond_solve_impl(h, p, b1, b2, x1, x2, rtol, maxit, iters_out, stream, true);
 }
 
 static void fill_info(const SolveStats& st, cc_info* info) {

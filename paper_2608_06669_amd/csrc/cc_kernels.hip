@@ -137,7 +137,7 @@ __global__ void jacobi_kernel(int o, int v, const double* __restrict__ f_oo, con
 
 __global__ void scale_inv_kernel(int64_t n, const double* __restrict__ x, const double* __restrict__ s,
                                  double* __restrict__ y) {
-  const double inv = 1.0 / *s;
+  const double inv = *s != 0.0 ? 1.0 / *s : 0.0;  // a zero vector stays zero
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = x[i] * inv;
 }

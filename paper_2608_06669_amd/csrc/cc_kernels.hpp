@@ -41,7 +41,7 @@ void ppl_pack_t(int o, int v, const double* t2, const int* pair_a, const int* pa
 // R[i][j][a][b] += sum_cd (ac|bd) t_ij^cd rebuilt from Rp = Tp S, Rm = Tm A.
 void ppl_unpack_add(int o, int v, const double* Rp, const double* Rm, double* R, hipStream_t s);
 
-// y = x / *s_dev (the divisor stays on the device)
+// y = x / *s_dev (the divisor stays on the device; y = 0 when it is 0)
 void scale_by_inverse(int64_t n, const double* x, const double* s_dev, double* y, hipStream_t s);
 
 }  // namespace pnk

@@ -13,10 +13,12 @@
 // Instead one workgroup stages x[:, :, chunk] (all o^2 pairs for a chunk of
 // ch consecutive (a, b)) in LDS once and forms both sums for every pair
 // from there, so x is read from memory once. The same launch adds the
-// virtual part, applies the Lanczos update and sums <v_k, p> per workgroup.
+// virtual part, applies the Lanczos update and sums <v_k, p>, <p, p> and
+// <v_k, v_k> per workgroup.
 // Trailing workgroups compute the singles, 16 lanes per output.
 
 #include "fock_op.hpp"
+#include "block_sum.hpp"
 #include "mfma_tiles.hpp"
 
 #include <algorithm>
@@ -32,6 +34,7 @@ struct VirArgs {
   const double* f_vv;
   const double* x2;
   double* y2;
+  const double* done;  // when set and nonzero on entry, the launch does nothing
 };
 
 template <int BM, int WGM, int BK>
@@ -47,6 +50,7 @@ __global__ __launch_bounds__(256) void fock_vir_kernel(VirArgs p) {
   __shared__ __attribute__((aligned(16))) double As[2][ALDS];
   __shared__ __attribute__((aligned(16))) double Bs[2][BLDS];
 
+  if (p.done && *p.done != 0.0) return;
   const int v = p.v;
   const int64_t vv = (int64_t)v * v;
   const int tid = threadIdx.x;
@@ -133,17 +137,55 @@ struct OccArgs {
   const double* vprev2;
   const double* beta;
   double* partials;
-  double s1;  // factor on the A_F part of the singles
+  double s1;           // factor on the A_F part of the singles
+  const double* done;  // when set and nonzero on entry, the launch does nothing
 };
+
+// Singles rows of A_F (f_ov-free part): 16 outputs per workgroup (its
+// index among the singles workgroups is sb), 16 lanes per output, summed by
+// a fixed-order butterfly. The A_F part is scaled by s1; in the Lanczos
+// form the update and the shares of the three sums are added to dot, nrm,
+// vv2 (weight 1).
+template <bool LZ>
+__device__ inline void singles_part(int o, int v, const double* __restrict__ f_oo, const double* __restrict__ f_vv,
+                                    const double* __restrict__ x1, double* __restrict__ y1,
+                                    const double* __restrict__ vprev1, double beta, double s1, int sb, double& dot,
+                                    double& nrm, double& vv2) {
+  const int tid = threadIdx.x;
+  const int64_t ov = (int64_t)o * v;
+  const int w = tid >> 4, l = tid & 15;
+  const int64_t out = (int64_t)sb * 16 + w;
+  double part = 0.0;
+  if (out < ov) {
+    const int i = (int)(out / v), a = (int)(out % v);
+    for (int c = l; c < v; c += 16) part += f_vv[(int64_t)a * v + c] * x1[(int64_t)i * v + c];
+    for (int k = l; k < o; k += 16) part -= f_oo[(int64_t)k * o + i] * x1[(int64_t)k * v + a];
+  }
+  for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
+  part *= s1;
+  if (out < ov && l == 0) {
+    if constexpr (LZ) {
+      const double q = part - beta * vprev1[out];
+      const double vk = x1[out];
+      y1[out] = q;
+      dot += vk * q;
+      nrm += q * q;
+      vv2 += vk * vk;
+    } else {
+      y1[out] = part;
+    }
+  }
+}
 
 // Dynamic LDS: xs[o*o][ch] then fo[o][o].
 template <bool LZ>
 __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
   extern __shared__ double lds[];
-  __shared__ double red[3][256];
+  __shared__ double red[3][4];
+  if (p.done && *p.done != 0.0) return;
   const int o = p.o, v = p.v, ch = p.ch;
   const int oo = o * o;
-  const int64_t vv = (int64_t)v * v, ov = (int64_t)o * v;
+  const int64_t vv = (int64_t)v * v;
   const int tid = threadIdx.x;
   double beta = 0.0;
   if constexpr (LZ) beta = *p.beta;
@@ -197,60 +239,148 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
       }
     }
   } else {
-    // singles: 16 outputs per workgroup, 16 lanes per output
-    const int w = tid >> 4, l = tid & 15;
-    const int64_t out = (int64_t)(blockIdx.x - p.nchunks) * 16 + w;
-    double part = 0.0;
-    if (out < ov) {
-      const int i = (int)(out / v), a = (int)(out % v);
-      for (int c = l; c < v; c += 16) part += p.f_vv[(int64_t)a * v + c] * p.x1[(int64_t)i * v + c];
-      for (int k = l; k < o; k += 16) part -= p.f_oo[(int64_t)k * o + i] * p.x1[(int64_t)k * v + a];
-    }
-    // fixed-order butterfly over the 16 lanes of this output
-    for (int m = 8; m > 0; m >>= 1) part += __shfl_xor(part, m, 16);
-    part *= p.s1;
-    if (out < ov && l == 0) {
-      if constexpr (LZ) {
-        const double q = part - beta * p.vprev1[out];
-        const double vk = p.x1[out];
-        p.y1[out] = q;
-        dot += vk * q;
-        nrm += q * q;
-        vv2 += vk * vk;
-      } else {
-        p.y1[out] = part;
-      }
-    }
+    singles_part<LZ>(p.o, p.v, p.f_oo, p.f_vv, p.x1, p.y1, p.vprev1, beta, p.s1, blockIdx.x - p.nchunks, dot, nrm,
+                     vv2);
   }
 
   if constexpr (LZ) {
-    red[0][tid] = dot;
-    red[1][tid] = nrm;
-    red[2][tid] = vv2;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (tid < s)
-        for (int c = 0; c < 3; ++c) red[c][tid] += red[c][tid + s];
-      __syncthreads();
-    }
+    double r[3] = {dot, nrm, vv2};
+    block_sum256<3>(r, red);
     if (tid == 0)
-      for (int c = 0; c < 3; ++c) p.partials[c * gridDim.x + blockIdx.x] = red[c][0];
+      for (int c = 0; c < 3; ++c) p.partials[c * gridDim.x + blockIdx.x] = r[c];
   }
+}
+
+// Packed pair layout (pairs i <= j only, P(i, j) = i o - i (i - 1) / 2 +
+// j - i, each a v x v block; x_ji = x_ij^T is implied): the occupied terms
+// need x_kj for k > j, which is x_jk transposed. A workgroup therefore
+// takes a tile A = [a0, a0 + t) x [b0, b0 + t) of the upper tile triangle
+// together with its mirror A^T, stages both for every packed pair, and
+// forms the outputs of both tiles for every packed pair from there.
+struct OccPackedArgs {
+  int o, v, t, ntile, nchunks, npair;
+  const double* f_oo;
+  const double* f_vv;
+  const double* x1;
+  const double* x2;  // packed
+  double* y1;
+  double* y2;  // packed; holds the virtual part on entry
+  const double* vprev1;
+  const double* vprev2;
+  const double* beta;
+  double* partials;
+  double s1;
+  const double* done;
+};
+
+__device__ inline int packed_pair(int i, int j, int o) { return i * o - i * (i - 1) / 2 + (j - i); }  // i <= j
+
+// Dynamic LDS: xs[npair][ns] then fo[o][o]; ns = t^2 (diagonal tile) or 2 t^2.
+__global__ __launch_bounds__(256) void fock_occ_packed_kernel(OccPackedArgs p) {
+  extern __shared__ double lds[];
+  __shared__ double red[3][4];
+  if (p.done && *p.done != 0.0) return;
+  const int o = p.o, v = p.v, t = p.t, npair = p.npair;
+  const int64_t vv = (int64_t)v * v;
+  const int tid = threadIdx.x;
+  const double beta = *p.beta;
+  double dot = 0.0, nrm = 0.0, vv2 = 0.0;
+
+  if ((int)blockIdx.x < p.nchunks) {
+    // chunk -> tile (ta, tb), ta <= tb, row by row over the upper triangle
+    int c = blockIdx.x, ta = 0;
+    while (c >= p.ntile - ta) {
+      c -= p.ntile - ta;
+      ++ta;
+    }
+    const int tb = ta + c;
+    const int a0 = ta * t, b0 = tb * t, tt = t * t;
+    const bool diag = ta == tb;
+    const int ns = diag ? tt : 2 * tt;
+    double* xs = lds;
+    double* fo = lds + (int64_t)npair * ns;
+    // staged element s: s < tt is (a0 + s / t, b0 + s % t) of A, else
+    // (b0 + r / t, a0 + r % t), r = s - tt, of A^T
+    for (int q = tid; q < npair * ns; q += 256) {
+      const int pr = q / ns, s = q % ns;
+      const int r = s < tt ? s : s - tt;
+      const int a = (s < tt ? a0 : b0) + r / t, b = (s < tt ? b0 : a0) + r % t;
+      xs[q] = (a < v && b < v) ? p.x2[(int64_t)pr * vv + (int64_t)a * v + b] : 0.0;
+    }
+    for (int q = tid; q < o * o; q += 256) fo[q] = p.f_oo[q];
+    __syncthreads();
+    const int groups = 256 / ns;
+    const int s = tid % ns, g0 = tid / ns;
+    const int r = s < tt ? s : s - tt;
+    const int a = (s < tt ? a0 : b0) + r / t, b = (s < tt ? b0 : a0) + r % t;
+    // index of the transposed element (b, a) among the staged ones
+    const int sT = diag ? (r % t) * t + r / t : (s < tt ? tt : 0) + (r % t) * t + r / t;
+    if (g0 < groups && a < v && b < v) {
+      const int64_t e = (int64_t)a * v + b;
+      constexpr int R = 4;
+      for (int pr0 = g0; pr0 < npair; pr0 += R * groups) {
+        double yin[R], vin[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int pr = pr0 + u * groups;
+          const int64_t idx = (int64_t)(pr < npair ? pr : 0) * vv + e;
+          yin[u] = p.y2[idx];
+          vin[u] = p.vprev2[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int pr = pr0 + u * groups;
+          if (pr >= npair) break;
+          int i = 0, rem = pr;
+          while (rem >= o - i) {
+            rem -= o - i;
+            ++i;
+          }
+          const int j = i + rem;
+          double occ = 0.0;
+          for (int k = 0; k < o; ++k) {
+            const double xkj = k <= j ? xs[packed_pair(k, j, o) * ns + s] : xs[packed_pair(j, k, o) * ns + sT];
+            const double xik = i <= k ? xs[packed_pair(i, k, o) * ns + s] : xs[packed_pair(k, i, o) * ns + sT];
+            occ += fo[k * o + i] * xkj + fo[k * o + j] * xik;
+          }
+          const int64_t idx = (int64_t)pr * vv + e;
+          const double q = (yin[u] - occ) - beta * vin[u];
+          const double vk = xs[pr * ns + s];
+          const double w = i == j ? 1.0 : 2.0;  // x_ij and x_ji = x_ij^T both count
+          p.y2[idx] = q;
+          dot += w * vk * q;
+          nrm += w * q * q;
+          vv2 += w * vk * vk;
+        }
+      }
+    }
+  } else {
+    singles_part<true>(p.o, p.v, p.f_oo, p.f_vv, p.x1, p.y1, p.vprev1, beta, p.s1, blockIdx.x - p.nchunks, dot, nrm,
+                       vv2);
+  }
+
+  double rr[3] = {dot, nrm, vv2};
+  block_sum256<3>(rr, red);
+  if (tid == 0)
+    for (int c = 0; c < 3; ++c) p.partials[c * gridDim.x + blockIdx.x] = rr[c];
 }
 
 bool aligned16(const void* q) { return ((uintptr_t)q & 15u) == 0; }
 
-void launch_vir(const FockOp& op, const double* x2, double* y2, hipStream_t s) {
+// npairs: o^2 for the full layout, o (o + 1) / 2 for the packed one (the
+// kernel only walks the v x v blocks one after another)
+void launch_vir(const FockOp& op, int npairs, const double* x2, double* y2, const double* done, hipStream_t s) {
   VirArgs a;
   a.v = op.v;
   a.tiles_m = (int)ceil_div(op.v, op.bm);
   a.tiles = op.tiles;
-  a.units = op.tiles * op.o * op.o;
+  a.units = op.tiles * npairs;
   a.per_xcd = (int)ceil_div(a.units, 8);
   a.vec = (op.v % 2 == 0 && aligned16(x2) && aligned16(op.f_vv)) ? 1 : 0;
   a.f_vv = op.f_vv;
   a.x2 = x2;
   a.y2 = y2;
+  a.done = done;
   dim3 grid((unsigned)(8 * a.per_xcd));
   // contraction panels of 32 for the 32-wide blocks when that pads v no
   // more than panels of 16 (measured: the wider blocks run better with 16)
@@ -270,7 +400,8 @@ size_t occ_lds_bytes(int o, int ch) { return sizeof(double) * ((size_t)o * o * c
 
 template <bool LZ>
 void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, const double* vprev1,
-                const double* vprev2, const double* beta, double* partials, double s1, hipStream_t s) {
+                const double* vprev2, const double* beta, double* partials, double s1, const double* done,
+                hipStream_t s) {
   OccArgs a;
   a.o = op.o;
   a.v = op.v;
@@ -287,6 +418,7 @@ void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1
   a.beta = beta;
   a.partials = partials;
   a.s1 = s1;
+  a.done = done;
   fock_occ_kernel<LZ><<<(unsigned)op.nparts(), 256, occ_lds_bytes(op.o, op.ch), s>>>(a);
   PNK_CHECK_LAUNCH();
 }
@@ -332,6 +464,22 @@ bool fock_op_plan(FockOp& op) {
   if (op.ch == 0) return false;
   op.nchunks = (int)ceil_div(vv, op.ch);
   op.nsingles = (int)ceil_div((int64_t)op.o * op.v, 16);
+  // packed layout: the widest tile edge among 8 / 4 / 2 whose staging (two
+  // tiles per packed pair) stays within 64 KB and that gives at least 256
+  // chunks; else the widest that fits
+  op.npair = op.o * (op.o + 1) / 2;
+  op.pt = 0;
+  for (int tt : {8, 4, 2}) {
+    const size_t lds = sizeof(double) * ((size_t)op.npair * 2 * tt * tt + (size_t)op.o * op.o);
+    if (lds > 64 * 1024) continue;
+    const int64_t nt = ceil_div(op.v, tt);
+    if (op.pt == 0) op.pt = tt;
+    if (nt * (nt + 1) / 2 >= 256) { op.pt = tt; break; }
+  }
+  if (op.pt > 0) {
+    op.pntile = (int)ceil_div(op.v, op.pt);
+    op.pnchunks = op.pntile * (op.pntile + 1) / 2;
+  }
   return (int64_t)op.tiles * op.o * op.o < (1ll << 31) - 8 && op.nparts() <= 0x7fffffff;
 }
 
@@ -347,23 +495,59 @@ bool fock_op_is_virtual_kernel(const void* func) {
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(x1 != y1 && x2 != y2, "fock_op: output must not alias the input");
-  launch_vir(op, x2, y2, s);
-  launch_occ<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, 1.0, s);
+  launch_vir(op, op.o * op.o, x2, y2, nullptr, s);
+  launch_occ<false>(op, x1, x2, y1, y2, nullptr, nullptr, nullptr, nullptr, 1.0, nullptr, s);
 }
 
-void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s) {
+void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
   const int64_t ov = (int64_t)op.o * op.v;
-  launch_vir(op, v + ov, p + ov, s);
+  launch_vir(op, op.o * op.o, v + ov, p + ov, done, s);
 }
 
 void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                         double* partials, double singles_scale, hipStream_t s) {
+                         double* partials, double singles_scale, const double* done, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0, "fock_op: not planned");
   PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
   const int64_t ov = (int64_t)op.o * op.v;
-  launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, singles_scale, s);
+  launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, singles_scale, done, s);
+}
+
+void fock_op_lanczos_vir_packed(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s) {
+  PNK_REQUIRE(op.bm > 0 && op.pt > 0, "fock_op: packed form not planned");
+  PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
+  const int64_t ov = (int64_t)op.o * op.v;
+  launch_vir(op, op.npair, v + ov, p + ov, done, s);
+}
+
+void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
+                                double* partials, double singles_scale, const double* done, hipStream_t s) {
+  PNK_REQUIRE(op.bm > 0 && op.pt > 0, "fock_op: packed form not planned");
+  PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
+  const int64_t ov = (int64_t)op.o * op.v;
+  OccPackedArgs a;
+  a.o = op.o;
+  a.v = op.v;
+  a.t = op.pt;
+  a.ntile = op.pntile;
+  a.nchunks = op.pnchunks;
+  a.npair = op.npair;
+  a.f_oo = op.f_oo;
+  a.f_vv = op.f_vv;
+  a.x1 = v;
+  a.x2 = v + ov;
+  a.y1 = p;
+  a.y2 = p + ov;
+  a.vprev1 = vprev;
+  a.vprev2 = vprev + ov;
+  a.beta = beta;
+  a.partials = partials;
+  a.s1 = singles_scale;
+  a.done = done;
+  const size_t lds = sizeof(double) * ((size_t)op.npair * 2 * op.pt * op.pt + (size_t)op.o * op.o);
+  fock_occ_packed_kernel<<<(unsigned)op.nparts_packed(), 256, lds, s>>>(a);
+  PNK_CHECK_LAUNCH();
 }
 
 }  // namespace pnk

@@ -9,8 +9,8 @@
 // [x1 (o*v) | x2 (o*o*v*v)], x1[i][a], x2[i][j][a][b].
 //
 // The occupied launch can also carry the first Lanczos update of the inner
-// solve: p = A_F v_k - beta_k v_{k-1} and per-workgroup partial sums of
-// <v_k, p>.
+// solve: p = A_F v_k - beta_k v_{k-1} (singles rows optionally scaled) and
+// per-workgroup partial sums of <v_k, p>, <p, p> and <v_k, v_k>.
 #pragma once
 
 #include "common.hpp"
@@ -27,7 +27,11 @@ struct FockOp {
   int bm = 0, tiles = 0;    // virtual kernel: bm x bm blocks, tiles per pair
   int ch = 0, nchunks = 0;  // occupied kernel: ch (ab) elements per workgroup
   int nsingles = 0;         // ... plus workgroups of 16 singles each
+  // occupied kernel on the packed pair layout: pt x pt tiles (and their
+  // mirrors), pntile tiles per side, pnchunks = pntile (pntile + 1) / 2
+  int npair = 0, pt = 0, pntile = 0, pnchunks = 0;
   int64_t nparts() const { return (int64_t)nchunks + nsingles; }
+  int64_t nparts_packed() const { return (int64_t)pnchunks + nsingles; }
 };
 
 // Picks the launch shapes; false when these kernels do not apply (o too
@@ -42,11 +46,22 @@ void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double*
 // fock_op_lanczos_occ completes p = S A_F v - (*beta) vprev and writes, for
 // each workgroup b, its shares of v . p, p . p and v . v in partials[b],
 // partials[nparts + b] and partials[2 nparts + b] (nparts = op.nparts(),
-// each share summed in a fixed order). beta is a device scalar; S multiplies the singles rows by
-// singles_scale and leaves the doubles rows alone.
-void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, hipStream_t s);
+// each share summed in a fixed order). beta is a device scalar; S
+// multiplies the singles rows by singles_scale and leaves the doubles rows
+// alone. done is a device flag: when it is nonzero as a launch starts, the
+// launch writes nothing (a converged solve can leave queued steps behind).
+void fock_op_lanczos_vir(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s);
 void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
-                         double* partials, double singles_scale, hipStream_t s);
+                         double* partials, double singles_scale, const double* done, hipStream_t s);
+
+// The same Lanczos step on the packed pair layout of pair-symmetric vectors
+// (x2[j][i] = x2[i][j]^T): [x1 (o*v) | x2 for pairs i <= j, pair P(i, j) =
+// i o - i (i - 1) / 2 + j - i, each v*v]. The three partial sums are those
+// of the full vectors (the blocks of pairs i < j count twice); partials has
+// 3 op.nparts_packed() entries.
+void fock_op_lanczos_vir_packed(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s);
+void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
+                                double* partials, double singles_scale, const double* done, hipStream_t s);
 
 // True for the virtual-contraction kernel (the launch that does the matrix
 // work), used to find its nodes in a recorded graph.

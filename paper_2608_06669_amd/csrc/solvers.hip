@@ -14,6 +14,7 @@
 // solved on the host.
 
 #include "solvers.hpp"
+#include "block_sum.hpp"
 #include "fock_op.hpp"
 
 #include <chrono>
@@ -93,8 +94,10 @@ Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_
 }
 
 Solver::~Solver() {
-  if (lz_exec_) (void)hipGraphExecDestroy(lz_exec_);
-  if (lz_exec_timed_) (void)hipGraphExecDestroy(lz_exec_timed_);
+  for (auto& layout : lz_graphs_)
+    for (auto& row : layout)
+      for (hipGraphExec_t e : row)
+        if (e) (void)hipGraphExecDestroy(e);
   for (hipEvent_t e : lz_ev_)
     if (e) (void)hipEventDestroy(e);
   for (double* p : {Qo_, Qi_, r_, ri_, w_, w2_, hx_, he_, dsc_, partials_})
@@ -152,8 +155,13 @@ namespace {
 // state: [0] beta_k  [1] alpha_k  [2] beta_{k+1}  [3] c_{k-2} [4] s_{k-2}
 //        [5] c_{k-1} [6] s_{k-1}  [7] phibar      [8] rho1    [9] delta
 //        [10] eps    [11] phi     [12] |phibar|   [13] 1/beta_{k+1}
-enum { kBeta = 0, kAlpha, kBetaN, kC2, kS2, kC1, kS1, kPhiBar, kRho1, kDelta, kEps, kPhi, kRes, kInvB, kNState };
+//        [14] done (the stopping test held at an earlier step)
+// A third, fixed slot after the two holds what the host reads: steps run,
+// the last residual estimate and beta, the absolute tolerance, ||b||.
+enum { kBeta = 0, kAlpha, kBetaN, kC2, kS2, kC1, kS1, kPhiBar, kRho1, kDelta, kEps, kPhi, kRes, kInvB, kDone, kNState };
+enum { kFinSteps = 0, kFinRes, kFinBeta, kFinTol, kFinBNorm, kFinBHat, kFinCount };
 constexpr int kStateStride = 16;
+static_assert(kNState <= kStateStride && kFinCount <= kStateStride, "Lanczos state slot too small");
 constexpr int kLzBlocks = 512;
 // With f_ov = 0, A_F is block diagonal and its doubles block is the
 // Kronecker sum of the singles block with itself (A_F, equation
@@ -166,39 +174,14 @@ constexpr double kInnerSinglesScale = 2.0;
 
 constexpr int kMaxFusedParts = 16384;  // workgroups of the fused A_F launch (three partials each)
 
-// Fixed-order sum of n partials by one workgroup of 256 threads (every
-// workgroup that calls it gets the same bits).
-__device__ inline double lz_block_sum(const double* partials, int n, double* sm) {
-  double acc = 0.0;
-  for (int k = threadIdx.x; k < n; k += 256) acc += partials[k];
-  sm[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-    __syncthreads();
-  }
-  const double r = sm[0];
-  __syncthreads();
-  return r;
-}
-
-__device__ inline void lz_block_partial(double acc, double* sm, double* partials) {
-  sm[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if (threadIdx.x < s) sm[threadIdx.x] += sm[threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
-}
-
 // p = S p - beta_k v_{k-1} (S scales the first n1 entries by s1); partial
 // sums of <v_k, p>, <p, p> and <v_k, v_k> (part1[b], part1[G + b],
 // part1[2 G + b], G = gridDim.x)
 __global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ p, const double* __restrict__ vprev,
                                                 const double* __restrict__ v, const double* __restrict__ st,
                                                 double* __restrict__ part1, int64_t n1, double s1) {
-  __shared__ double sm[256];
+  if (st[kDone] != 0.0) return;
+  __shared__ double sm[3][4];
   const double beta = st[kBeta];
   double dot = 0.0, nrm = 0.0, vv2 = 0.0;
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -209,11 +192,10 @@ __global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ 
     nrm += x * x;
     vv2 += vk * vk;
   }
-  lz_block_partial(dot, sm, part1);
-  __syncthreads();
-  lz_block_partial(nrm, sm, part1 + gridDim.x);
-  __syncthreads();
-  lz_block_partial(vv2, sm, part1 + 2 * gridDim.x);
+  double r[3] = {dot, nrm, vv2};
+  block_sum256<3>(r, sm);
+  if (threadIdx.x == 0)
+    for (int c = 0; c < 3; ++c) part1[c * gridDim.x + blockIdx.x] = r[c];
 }
 
 // alpha_k = <v_k, p> / <v_k, v_k> and beta_{k+1} = ||p - alpha_k v_k||,
@@ -223,17 +205,30 @@ __global__ __launch_bounds__(256) void lz_step1(int64_t n, double* __restrict__ 
 // growing from step to step. Then one Givens rotation of the tridiagonal
 // QR, and
 // w_k = (v_k - delta w_{k-1} - eps w_{k-2}) / rho1 (into the w_{k-2} slot),
-// x += phi w_k, v_{k+1} = (p - alpha_k v_k) / beta_{k+1} (in place)
+// x += phi w_k, v_{k+1} = (p - alpha_k v_k) / beta_{k+1} (in place).
+// The stopping test (|phibar| <= tolerance, or beta_{k+1} = 0) is taken
+// here after every step; once it holds, the later steps of the queue pass
+// the done flag on and write nothing else.
 __global__ __launch_bounds__(256) void lz_update(int64_t n, const double* __restrict__ v,
                                                  const double* __restrict__ w1, double* __restrict__ w2,
                                                  double* __restrict__ x, double* __restrict__ p,
                                                  const double* __restrict__ part1, int nparts1,
-                                                 const double* __restrict__ st, double* __restrict__ stn) {
-  __shared__ double sm[256];
-  const double vp = lz_block_sum(part1, nparts1, sm);
-  const double pp = lz_block_sum(part1 + nparts1, nparts1, sm);
-  const double vv = lz_block_sum(part1 + 2 * nparts1, nparts1, sm);
-  const double alpha = vp / vv;
+                                                 const double* __restrict__ st, double* __restrict__ stn,
+                                                 double* __restrict__ fin) {
+  if (st[kDone] != 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) stn[kDone] = 1.0;
+    return;
+  }
+  __shared__ double sm[3][4];
+  double r[3] = {0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < nparts1; k += 256) {
+    r[0] += part1[k];
+    r[1] += part1[nparts1 + k];
+    r[2] += part1[2 * nparts1 + k];
+  }
+  block_sum256<3>(r, sm);
+  const double vp = r[0], pp = r[1], vv = r[2];
+  const double alpha = vv > 0.0 ? vp / vv : 0.0;
   const double betan = sqrt(fmax(pp - alpha * vp, 0.0));
   const double beta = st[kBeta];
   const double c2 = st[kC2], s2 = st[kS2], c1 = st[kC1], s1 = st[kS1];
@@ -259,8 +254,13 @@ __global__ __launch_bounds__(256) void lz_update(int64_t n, const double* __rest
     stn[kDelta] = delta;
     stn[kEps] = eps;
     stn[kPhi] = phi;
-    stn[kRes] = fabs(s * phibar);
+    const double res = fabs(s * phibar);
+    stn[kRes] = res;
     stn[kInvB] = invb;
+    stn[kDone] = (res <= fin[kFinTol] || betan == 0.0) ? 1.0 : 0.0;
+    fin[kFinSteps] += 1.0;
+    fin[kFinRes] = res;
+    fin[kFinBeta] = betan;
   }
   for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const double vi = v[i];
@@ -271,13 +271,158 @@ __global__ __launch_bounds__(256) void lz_update(int64_t n, const double* __rest
   }
 }
 
-__global__ void lz_init(double* st, const double* bnorm) {
+// bnorm: norm of the (scaled) start vector; rhs_norm: ||b||, which with
+// rtol sets the absolute tolerance on the residual estimate.
+__global__ void lz_init(double* st, const double* bnorm, const double* rhs_norm, double rtol) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   for (int k = 0; k < kNState; ++k) st[k] = 0.0;
   st[kC2] = 1.0; st[kC1] = 1.0;
   st[kPhiBar] = *bnorm;
   st[kRes] = *bnorm;
   st[kBeta] = 0.0;
+  st[kStateStride + kDone] = 0.0;
+  double* fin = st + 2 * kStateStride;
+  fin[kFinSteps] = 0.0;
+  fin[kFinRes] = *bnorm;
+  fin[kFinBeta] = 1.0;
+  fin[kFinTol] = rtol * *rhs_norm;
+  fin[kFinBNorm] = *rhs_norm;
+}
+
+// ---- packed pair layout for pair-symmetric vectors (pairs i <= j) ----
+
+__device__ inline int lzp_pair(int i, int j, int o) { return i * o - i * (i - 1) / 2 + (j - i); }  // i <= j
+
+__device__ inline void lzp_decode(int pr, int o, int& i, int& j) {
+  i = 0;
+  while (pr >= o - i) {
+    pr -= o - i;
+    ++i;
+  }
+  j = i + pr;
+}
+
+constexpr int kPackTile = 32;
+constexpr int kPackBlocksX = 16;  // workgroups per pair block (grid-stride over its tiles)
+
+// xp = packed D^1/2 sym(b): singles times rs; for i <= j the block
+// (b_ij + b_ji^T) / 2 (the pair-symmetric part; b_ji^T staged through LDS).
+// Each workgroup writes its shares of ||sym(b)||^2 and ||D^1/2 sym(b)||^2
+// (blocks of pairs i < j counted twice) to parts[g], parts[G + g], g the
+// workgroup's linear index, G the number of workgroups.
+__global__ __launch_bounds__(256) void lzp_pack(int o, int v, const double* __restrict__ b, double rs,
+                                                double* __restrict__ xp, double* __restrict__ parts) {
+  __shared__ double tile[kPackTile][kPackTile + 1];
+  __shared__ double sm[2][4];
+  const int npair = o * (o + 1) / 2;
+  const int64_t vv = (int64_t)v * v, ov = (int64_t)o * v;
+  const int tid = threadIdx.x;
+  double s_plain = 0.0, s_scaled = 0.0;
+  if ((int)blockIdx.y == npair) {
+    for (int64_t e = blockIdx.x * (int64_t)256 + tid; e < ov; e += (int64_t)gridDim.x * 256) {
+      const double x = b[e];
+      xp[e] = rs * x;
+      s_plain += x * x;
+      s_scaled += (rs * x) * (rs * x);
+    }
+  } else {
+    int i, j;
+    lzp_decode(blockIdx.y, o, i, j);
+    const double w = i == j ? 1.0 : 2.0;
+    const double* __restrict__ bij = b + ov + (int64_t)(i * o + j) * vv;
+    const double* __restrict__ bji = b + ov + (int64_t)(j * o + i) * vv;
+    double* __restrict__ out = xp + ov + (int64_t)blockIdx.y * vv;
+    const int nt = (v + kPackTile - 1) / kPackTile;
+    const int tx = tid % kPackTile, ty = tid / kPackTile;
+    for (int tl = blockIdx.x; tl < nt * nt; tl += gridDim.x) {
+      const int a0 = (tl / nt) * kPackTile, b0 = (tl % nt) * kPackTile;
+      __syncthreads();
+      for (int r = ty; r < kPackTile; r += 256 / kPackTile) {  // tile[r][c] = b_ji[b0 + r][a0 + c]
+        const int rr = b0 + r, cc = a0 + tx;
+        tile[r][tx] = (rr < v && cc < v) ? bji[(int64_t)rr * v + cc] : 0.0;
+      }
+      __syncthreads();
+      for (int r = ty; r < kPackTile; r += 256 / kPackTile) {
+        const int a = a0 + r, bb = b0 + tx;
+        if (a < v && bb < v) {
+          const double x = 0.5 * (bij[(int64_t)a * v + bb] + tile[tx][r]);
+          out[(int64_t)a * v + bb] = x;
+          s_plain += w * x * x;
+          s_scaled += w * x * x;
+        }
+      }
+    }
+  }
+  double r2[2] = {s_plain, s_scaled};
+  block_sum256<2>(r2, sm);
+  const int g = blockIdx.y * gridDim.x + blockIdx.x, G = gridDim.x * gridDim.y;
+  if (tid == 0) {
+    parts[g] = r2[0];
+    parts[G + g] = r2[1];
+  }
+}
+
+// x (full layout) = D^1/2 unpack(xp): x_ij = xp_P(i,j) for i <= j, and
+// xp_P(j,i)^T (through LDS) for i > j; singles times rs.
+__global__ __launch_bounds__(256) void lzp_unpack(int o, int v, const double* __restrict__ xp, double rs,
+                                                  double* __restrict__ x) {
+  __shared__ double tile[kPackTile][kPackTile + 1];
+  const int64_t vv = (int64_t)v * v, ov = (int64_t)o * v;
+  const int tid = threadIdx.x;
+  if ((int)blockIdx.y == o * o) {
+    for (int64_t e = blockIdx.x * (int64_t)256 + tid; e < ov; e += (int64_t)gridDim.x * 256) x[e] = rs * xp[e];
+    return;
+  }
+  const int i = blockIdx.y / o, j = blockIdx.y % o;
+  double* __restrict__ out = x + ov + (int64_t)blockIdx.y * vv;
+  if (i <= j) {
+    const double* __restrict__ src = xp + ov + (int64_t)lzp_pair(i, j, o) * vv;
+    for (int64_t e = blockIdx.x * (int64_t)256 + tid; e < vv; e += (int64_t)gridDim.x * 256) out[e] = src[e];
+    return;
+  }
+  const double* __restrict__ src = xp + ov + (int64_t)lzp_pair(j, i, o) * vv;  // x_ij = x_ji^T
+  const int nt = (v + kPackTile - 1) / kPackTile;
+  const int tx = tid % kPackTile, ty = tid / kPackTile;
+  for (int tl = blockIdx.x; tl < nt * nt; tl += gridDim.x) {
+    const int a0 = (tl / nt) * kPackTile, b0 = (tl % nt) * kPackTile;
+    __syncthreads();
+    for (int r = ty; r < kPackTile; r += 256 / kPackTile) {  // tile[r][c] = x_ji[b0 + r][a0 + c]
+      const int rr = b0 + r, cc = a0 + tx;
+      tile[r][tx] = (rr < v && cc < v) ? src[(int64_t)rr * v + cc] : 0.0;
+    }
+    __syncthreads();
+    for (int r = ty; r < kPackTile; r += 256 / kPackTile) {
+      const int a = a0 + r, bb = b0 + tx;
+      if (a < v && bb < v) out[(int64_t)a * v + bb] = tile[tx][r];
+    }
+  }
+}
+
+// lz_init for the packed solve: the two norms from lzp_pack's partials
+// (nparts each, summed in a fixed order by one workgroup).
+__global__ __launch_bounds__(256) void lzp_init(const double* __restrict__ parts, int nparts, double* st,
+                                                double rtol) {
+  __shared__ double sm[2][4];
+  double r[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < nparts; k += 256) {
+    r[0] += parts[k];
+    r[1] += parts[nparts + k];
+  }
+  block_sum256<2>(r, sm);
+  if (threadIdx.x != 0) return;
+  const double bn = sqrt(r[0]), bhat = sqrt(r[1]);
+  for (int k = 0; k < kNState; ++k) st[k] = 0.0;
+  st[kC2] = 1.0; st[kC1] = 1.0;
+  st[kPhiBar] = bhat;
+  st[kRes] = bhat;
+  st[kStateStride + kDone] = 0.0;
+  double* fin = st + 2 * kStateStride;
+  fin[kFinSteps] = 0.0;
+  fin[kFinRes] = bhat;
+  fin[kFinBeta] = 1.0;
+  fin[kFinTol] = rtol * bn;
+  fin[kFinBNorm] = bn;
+  fin[kFinBHat] = bhat;
 }
 
 inline int grid_n(int64_t n) {
@@ -290,34 +435,45 @@ inline int grid_n(int64_t n) {
 // A_F symmetric (f_ov = 0): the Arnoldi process of GMRES reduces to the
 // three-term Lanczos recurrence and the Hessenberg least-squares problem to
 // a tridiagonal one, updated with one Givens rotation per step (GMRES and
-// MINRES coincide in exact arithmetic). Everything stays on the device; the
-// host reads the residual estimate every `check` steps.
+// MINRES coincide in exact arithmetic). Everything stays on the device,
+// including the stopping test; the host reads the outcome once per batch
+// of queued steps.
 // One Lanczos step on fixed buffers (see precond_solve_sym).
 // Device scalars: [0, kMaxBasis) and [kMaxBasis, 2 kMaxBasis) projections,
-// then norms; the Lanczos state's two slots start at 3.5 kMaxBasis.
+// then norms; the Lanczos state's three slots start at 3.5 kMaxBasis.
 double* Solver::lanczos_state() const { return dsc_ + 3 * kMaxBasis + kMaxBasis / 2; }
 
 void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
                           double* stn, hipStream_t s) {
-  const int64_t n = n_;
+  int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
   double* part1 = partials_;
   const FockOp* op = eng_.fock_op();
   int nparts1 = kLzBlocks;
-  if (op && op->nparts() <= kMaxFusedParts) {
+  if (lz_packed_) {
+    // packed pair layout (see precond_solve_sym): the same three launches
+    n = ov + (int64_t)op->npair * eng_.v() * eng_.v();
+    Timers* tm = eng_.timers();
+    if (tm) tm->begin(kTimerFock, s);
+    fock_op_lanczos_vir_packed(*op, v, p, st + kDone, s);
+    if (tm) tm->end(kTimerFock, s);
+    fock_op_lanczos_occ_packed(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, st + kDone, s);
+    nparts1 = (int)op->nparts_packed();
+  } else if (op && op->nparts() <= kMaxFusedParts) {
     // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p>; the timer
     // covers the virtual (matrix-core) launch
     Timers* tm = eng_.timers();
     if (tm) tm->begin(kTimerFock, s);
-    fock_op_lanczos_vir(*op, v, p, s);
+    fock_op_lanczos_vir(*op, v, p, st + kDone, s);
     if (tm) tm->end(kTimerFock, s);
-    fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, s);
+    fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, st + kDone, s);
     nparts1 = (int)op->nparts();
   } else {
     eng_.fock_apply(v, v + ov, p, p + ov, s);
     lz_step1<<<kLzBlocks, 256, 0, s>>>(n, p, vprev, v, st, part1, ov, kInnerSinglesScale);
   }
-  lz_update<<<kLzBlocks, 256, 0, s>>>(n, v, w1, w2, x, p, part1, nparts1, st, stn);
+  lz_update<<<kLzBlocks, 256, 0, s>>>(n, v, w1, w2, x, p, part1, nparts1, st, stn,
+                                      lanczos_state() + 2 * kStateStride);
   PNK_CHECK_LAUNCH();
 }
 
@@ -343,11 +499,34 @@ namespace {
 // Brackets every virtual A_F kernel node of a recorded graph with two event
 // record nodes (ev[2k], ev[2k+1]) so each launch's duration can be read
 // after a replay. Returns the number of nodes bracketed, -1 on error.
-int bracket_fock_nodes(hipGraph_t g, hipEvent_t* ev, int max_pairs) {
+// The nodes of a graph recorded from one stream, in stream order: such a
+// graph is a chain (one root, one dependent per node). Empty if it is not.
+std::vector<hipGraphNode_t> chain_order(hipGraph_t g) {
   size_t nn = 0;
-  if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess) return -1;
-  std::vector<hipGraphNode_t> nodes(nn);
-  if (hipGraphGetNodes(g, nodes.data(), &nn) != hipSuccess) return -1;
+  if (hipGraphGetNodes(g, nullptr, &nn) != hipSuccess || nn == 0) return {};
+  size_t nr = 0;
+  if (hipGraphGetRootNodes(g, nullptr, &nr) != hipSuccess || nr != 1) return {};
+  hipGraphNode_t node;
+  if (hipGraphGetRootNodes(g, &node, &nr) != hipSuccess) return {};
+  std::vector<hipGraphNode_t> out;
+  out.reserve(nn);
+  while (true) {
+    out.push_back(node);
+    size_t ns = 0;
+    if (hipGraphNodeGetDependentNodes(node, nullptr, &ns) != hipSuccess || ns > 1) return {};
+    if (ns == 0) break;
+    if (hipGraphNodeGetDependentNodes(node, &node, &ns) != hipSuccess) return {};
+  }
+  if (out.size() != nn) return {};
+  return out;
+}
+
+// Inserts event record nodes before and after each virtual A_F kernel node
+// of a chain graph: pair k (events ev[2k], ev[2k+1]) brackets the k-th such
+// launch in stream order. Returns the number of pairs, -1 on failure.
+int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
+  const std::vector<hipGraphNode_t> nodes = chain_order(g);
+  if (nodes.empty()) return -1;
   int k = 0;
   for (hipGraphNode_t node : nodes) {
     hipGraphNodeType type;
@@ -381,17 +560,22 @@ int bracket_fock_nodes(hipGraph_t g, hipEvent_t* ev, int max_pairs) {
 
 }  // namespace
 
-// Records the six-step block as a HIP graph. The timed variant also holds
+// Records nb six-step blocks as one HIP graph. The timed variant also holds
 // event record nodes around each fused A_F launch (used only while the
 // engine's timers are on).
-bool Solver::ensure_lanczos_graph(bool timed) {
-  hipGraphExec_t& exec = timed ? lz_exec_timed_ : lz_exec_;
-  bool& failed = timed ? lz_timed_failed_ : lz_graph_failed_;
+bool Solver::ensure_lanczos_graph(bool timed, int nb) {
+  if (nb < 1 || nb > kMaxBatchBlocks) return false;
+  hipGraphExec_t& exec = lz_graphs_[lz_packed_ ? 1 : 0][timed ? 1 : 0][nb];
+  bool& failed = lz_graph_failed_[lz_packed_ ? 1 : 0][timed ? 1 : 0][nb];
   if (exec) return true;
   if (failed) return false;
-  if (timed && !lz_ev_[0]) {
-    for (auto& e : lz_ev_)
+  const int pairs = nb * kLanczosBlock;
+  if (timed) {
+    while ((int)lz_ev_.size() < 2 * pairs) {
+      hipEvent_t e = nullptr;
       if (hipEventCreate(&e) != hipSuccess) { failed = true; return false; }
+      lz_ev_.push_back(e);
+    }
   }
   Timers* tm = eng_.timers();
   eng_.set_timers(nullptr);  // no host-side timer events inside a graph
@@ -403,13 +587,13 @@ bool Solver::ensure_lanczos_graph(bool timed) {
     // a failure while recording must not leave a partial graph behind
     bool threw = false;
     try {
-      lanczos_block(cs);
+      for (int q = 0; q < nb; ++q) lanczos_block(cs);
     } catch (const std::exception& e) {
       threw = true;
       if (std::getenv("PNK_DEBUG")) std::fprintf(stderr, "pnk: graph capture failed: %s\n", e.what());
     }
     if (hipStreamEndCapture(cs, &g) == hipSuccess && g && !threw &&
-        (!timed || bracket_fock_nodes(g, lz_ev_, kLanczosBlock) == kLanczosBlock) &&
+        (!timed || bracket_fock_nodes(g, lz_ev_.data(), pairs) == pairs) &&
         hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
       ok = true;
   }
@@ -418,7 +602,8 @@ bool Solver::ensure_lanczos_graph(bool timed) {
   (void)hipGetLastError();
   eng_.set_timers(tm);
   if (!ok) {
-    if (std::getenv("PNK_DEBUG")) std::fprintf(stderr, "pnk: no %s inner-solve graph\n", timed ? "timed" : "plain");
+    if (std::getenv("PNK_DEBUG"))
+      std::fprintf(stderr, "pnk: no %s inner-solve graph of %d blocks\n", timed ? "timed" : "plain", nb);
     exec = nullptr;
     failed = true;
   }
@@ -432,62 +617,96 @@ bool Solver::ensure_lanczos_graph(bool timed) {
 // blocks of six steps are replayed as one HIP graph, and the host reads the
 // residual estimate after each block (so up to five extra steps run past
 // convergence; they only lower the residual further).
-int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged) {
+int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged,
+                              bool packed) {
   const int64_t n = n_;
-  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  const int o = eng_.o(), vir = eng_.v();
+  const int64_t ov = (int64_t)o * vir;
   const double rs = std::sqrt(kInnerSinglesScale);
-  double bn, dummy;
-  norms(b, &dummy, &bn, s);
-  if (converged) *converged = true;
-  if (bn == 0.0) {
-    fill(n, 0.0, x, s);
-    return 0;
-  }
-  double* st = lanczos_state();  // slot 0 holds the state after every block
+  double* st = lanczos_state();
+  const double* fin = st + 2 * kStateStride;
   double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *xi = Qi_ + 5 * n;
-  // scaled system D^1/2 A_F D^1/2 z = D^1/2 b, x = D^1/2 z, D = diag(s I, I)
-  copy(n, b, xi, s);
-  axpby(ov, rs, b, 0.0, xi, s);
-  double bhn;
-  norms(xi, &dummy, &bhn, s);
-  lz_init<<<1, 1, 0, s>>>(st, dsc_ + 1);
-  scale_by_inverse(n, xi, dsc_ + 1, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
-  fill(n, 0.0, vprev, s);
-  fill(n, 0.0, w1, s);
-  fill(n, 0.0, w2, s);
-  fill(n, 0.0, xi, s);
+  const FockOp* op = eng_.fock_op();
+  lz_packed_ = packed;
+  // scaled system D^1/2 A_F D^1/2 z = D^1/2 b, x = D^1/2 z, D = diag(s I, I).
+  // ||b|| stays on the device (b = 0 gives v_1 = 0, z = 0 and a stop at
+  // the first step).
+  int64_t nl = n;  // length of the Lanczos vectors
+  if (packed) {
+    // pair-symmetric b: the recurrence runs on pairs i <= j, with inner
+    // products that count the blocks of pairs i < j twice (those of the full
+    // vectors), so its steps are those of the full-layout recurrence
+    nl = ov + (int64_t)op->npair * vir * vir;
+    double* parts = partials_ + 3 * kMaxFusedParts;
+    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, xi, parts);
+    lzp_init<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, rtol);
+    scale_by_inverse(nl, xi, fin + kFinBHat, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
+  } else {
+    nrm2(n, b, dsc_ + 2, partials_, s);
+    copy(n, b, xi, s);
+    axpby(ov, rs, b, 0.0, xi, s);
+    nrm2(n, xi, dsc_ + 1, partials_, s);
+    lz_init<<<1, 1, 0, s>>>(st, dsc_ + 1, dsc_ + 2, rtol);
+    scale_by_inverse(n, xi, dsc_ + 1, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
+  }
+  fill(nl, 0.0, vprev, s);
+  fill(nl, 0.0, w1, s);
+  fill(nl, 0.0, w2, s);
+  fill(nl, 0.0, xi, s);
   PNK_CHECK_LAUNCH();
   Timers* tm = eng_.timers();
-  const FockOp* op = eng_.fock_op();
   const bool fused = op && op->nparts() <= kMaxFusedParts;
-  const bool timed = use_graphs_ && tm && fused && ensure_lanczos_graph(true);
-  const bool graph = timed || (use_graphs_ && ensure_lanczos_graph(false));
-  int it = 0;
+  // The first batch queues as many blocks of six steps as the last solve
+  // ran (as one recorded graph), later ones a block each. The device stops
+  // the recurrence at the first step that meets the test, so the batch
+  // size changes the cost only, never the result. With timing on, the
+  // event pairs of the steps that ran are read.
+  int batch = std::min(std::max(1, lz_blocks_hint_), (int)kMaxBatchBlocks);
+  int launched = 0;
+  int steps = 0;
   bool conv = false;
-  while (it < maxit) {
-    if (graph) PNK_HIP(hipGraphLaunch(timed ? lz_exec_timed_ : lz_exec_, s));
-    else lanczos_block(s);
-    it += kLanczosBlock;
-    read_scalars(host_, st, kNState, s);  // synchronises the stream
-    if (timed)
-      for (int k = 0; k < kLanczosBlock; ++k) {
+  while (launched < maxit) {
+    const int nb = (int)std::min<int64_t>(batch, ceil_div(maxit - launched, kLanczosBlock));
+    bool timed = false, graph = false;
+    if (use_graphs_) {
+      timed = tm && fused && ensure_lanczos_graph(true, nb);
+      graph = timed || ensure_lanczos_graph(false, nb);
+    }
+    if (graph) PNK_HIP(hipGraphLaunch(lz_graphs_[lz_packed_ ? 1 : 0][timed ? 1 : 0][nb], s));
+    else
+      for (int q = 0; q < nb; ++q) lanczos_block(s);
+    const int before = launched;
+    launched += nb * kLanczosBlock;
+    batch = 1;
+    read_scalars(host_, fin, kFinCount, s);  // synchronises the stream
+    steps = (int)host_[kFinSteps];
+    if (timed) {
+      const int ran = std::min(nb * kLanczosBlock, steps - before);
+      for (int k = 0; k < ran; ++k) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, lz_ev_[2 * k], lz_ev_[2 * k + 1]) == hipSuccess) tm->add(kTimerFock, 1, ms);
         else (void)hipGetLastError();
       }
+    }
     // ||b - A_F x|| <= ||D^1/2 (b - A_F x)|| = the scaled residual (D >= I)
-    const double res = host_[kRes];
+    const double res = host_[kFinRes], bn = host_[kFinBNorm];
     if (!std::isfinite(res)) break;
-    if (res <= rtol * bn || host_[kBeta] == 0.0) { conv = true; break; }
+    if (res <= rtol * bn || host_[kFinBeta] == 0.0) { conv = true; break; }
   }
-  copy(n, xi, x, s);
-  axpby(ov, rs, xi, 0.0, x, s);
+  lz_blocks_hint_ = (int)ceil_div(steps, kLanczosBlock);
+  if (packed) {
+    lzp_unpack<<<dim3(kPackBlocksX, o * o + 1), 256, 0, s>>>(o, vir, xi, rs, x);
+    PNK_CHECK_LAUNCH();
+  } else {
+    copy(n, xi, x, s);
+    axpby(ov, rs, xi, 0.0, x, s);
+  }
   if (converged) *converged = conv;
-  return it;
+  return steps;
 }
 
 int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s,
-                          bool* converged) {
+                          bool* converged, bool pair_symmetric) {
   PNK_REQUIRE(restart >= 1 && restart <= restart_, "precond_solve: restart exceeds the allocated basis");
   const int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
@@ -497,7 +716,11 @@ int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, in
     Timers* t; hipStream_t s;
     ~EndTimer() { if (t) t->end(kTimerPrecond, s); }
   } end_timer{tm, s};
-  if (eng_.fov_zero() && sym_inner_ && restart_ >= 5) return precond_solve_sym(b, x, rtol, maxit, s, converged);
+  if (eng_.fov_zero() && sym_inner_ && restart_ >= 5) {
+    const FockOp* op = eng_.fock_op();
+    const bool packed = pair_symmetric && op && op->pt > 0 && op->nparts_packed() <= kMaxFusedParts;
+    return precond_solve_sym(b, x, rtol, maxit, s, converged, packed);
+  }
   double bn, dummy;
   norms(b, &dummy, &bn, s);
   fill(n, 0.0, x, s);
@@ -588,7 +811,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
   auto Ainv = [&](const double* b, double* out) {
     bool conv = true;
-    const int it = precond_solve(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv);
+    const int it = precond_solve(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
     st->n_afmv += it;
     st->n_inner_iters += it;
   };
@@ -731,7 +954,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     eng_.residual(eng_.zeros(), eng_.zeros() + ov, r_, r_ + ov, s);
     st->n_residual++;
     bool conv = true;
-    const int it = precond_solve(r_, x, opt.inner_rtol, 200, restart_, s, &conv);
+    const int it = precond_solve(r_, x, opt.inner_rtol, 200, restart_, s, &conv, true);
     st->n_afmv += it;
     st->n_inner_iters += it;
     axpby(n, 0.0, x, -1.0, x, s);

@@ -52,11 +52,16 @@ class Solver {
   static size_t bytes(int64_t nvec, int m_max, int inner_restart, int diis_size);
 
   // A_F x = b by restarted GMRES to ||b - A_F x|| <= rtol ||b||; packed
-  // vectors of length nvec. Returns the number of A_F products.
+  // [t1 | t2] vectors of length nvec. Returns the number of A_F products.
+  // pair_symmetric: b2[j][i] = b2[i][j]^T, as for every closed-shell
+  // amplitude vector; the symmetric solve may then work on pairs i <= j
+  // (it solves for the pair-symmetric part of b).
   int precond_solve(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s,
-                    bool* converged = nullptr);
-  // Symmetric A_F (f_ov = 0): device-resident Lanczos form of GMRES.
-  int precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged);
+                    bool* converged = nullptr, bool pair_symmetric = false);
+  // Symmetric A_F (f_ov = 0): device-resident Lanczos form of GMRES, on
+  // the full or the packed pair layout.
+  int precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged,
+                        bool packed);
   // Use the short-recurrence form when A_F is symmetric (default on).
   void set_symmetric_inner(bool on) { sym_inner_ = on; }
   // Replay recorded HIP graphs for the inner iterations (default on).
@@ -96,17 +101,19 @@ class Solver {
   // one line per outer iteration on stderr when PNK_VERBOSE is set
   bool verbose_ = std::getenv("PNK_VERBOSE") != nullptr;
   bool use_graphs_ = true;
-  bool lz_graph_failed_ = false;
-  hipGraphExec_t lz_exec_ = nullptr;
-  hipGraphExec_t lz_exec_timed_ = nullptr;
-  bool lz_timed_failed_ = false;
-  hipEvent_t lz_ev_[2 * kLanczosBlock] = {};
+  // recorded runs of nb blocks, nb = 1 .. kMaxBatchBlocks
+  static constexpr int kMaxBatchBlocks = 16;
+  hipGraphExec_t lz_graphs_[2][2][kMaxBatchBlocks + 1] = {};  // [packed][timed][nb]
+  bool lz_graph_failed_[2][2][kMaxBatchBlocks + 1] = {};
+  bool lz_packed_ = false;  // layout of the current symmetric solve
+  std::vector<hipEvent_t> lz_ev_;  // event pairs around the A_F launches of a timed run
+  int lz_blocks_hint_ = 0;         // blocks of six steps the last symmetric solve ran
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
                     double* stn, hipStream_t s);
-  // two state slots of the Lanczos recurrence (device scalars)
+  // state slots of the Lanczos recurrence (device scalars)
   double* lanczos_state() const;
   void lanczos_block(hipStream_t s);
-  bool ensure_lanczos_graph(bool timed);
+  bool ensure_lanczos_graph(bool timed, int nb);
   std::vector<double> hist_;
 };
 

@@ -177,6 +177,33 @@ def test_fock_doubles_block_is_symmetric():
     assert np.allclose(A, A.T, atol=1e-15)
 
 
+def test_fock_operator_spectrum_is_a_kronecker_sum_of_the_singles_block():
+    """With f_ov = 0, A_F is block diagonal and its doubles block is the
+    Kronecker sum of the singles block with itself: its eigenvalues are all
+    sums lam_p + lam_q of singles eigenvalues, so its spectrum spans exactly
+    twice the singles range (the fact behind the factor 2 on the singles in
+    the device's symmetric inner solve). Built column by column from the
+    oracle's A_F in a rotated gauge."""
+    p = make_problem(2, 3, 8, 66, gauge="haar")
+    o, v = 2, 3
+    n1, n2 = o * v, o * o * v * v
+    A = np.zeros((n1 + n2, n1 + n2))
+    for k in range(n1 + n2):
+        e = np.zeros(n1 + n2)
+        e[k] = 1.0
+        y1, y2 = solvers.fock_apply(p.f_oo, p.f_ov, p.f_vv, e[:n1].reshape(o, v), e[n1:].reshape(o, o, v, v))
+        A[:, k] = np.concatenate([y1.ravel(), y2.ravel()])
+    assert np.abs(A[:n1, n1:]).max() == 0.0 and np.abs(A[n1:, :n1]).max() == 0.0
+    lam1 = np.linalg.eigvalsh(A[:n1, :n1])
+    lam2 = np.linalg.eigvalsh(A[n1:, n1:])
+    sums = np.sort((lam1[:, None] + lam1[None, :]).ravel())
+    assert np.allclose(lam2, sums, atol=1e-12)
+    assert abs(lam2[0] - 2 * lam1[0]) < 1e-12 and abs(lam2[-1] - 2 * lam1[-1]) < 1e-12
+    # the singles eigenvalues are the orbital-energy gaps eps_a - eps_i
+    gaps = np.sort((np.linalg.eigvalsh(p.f_vv)[None, :] - np.linalg.eigvalsh(p.f_oo)[:, None]).ravel())
+    assert np.allclose(lam1, gaps, atol=1e-12)
+
+
 # ---------------------------------------------------------------- T7 -----
 @pytest.mark.parametrize("seed", [71, 72])
 def test_ccsd_equals_fci_for_one_occupied_orbital(seed):
