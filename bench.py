@@ -29,11 +29,12 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2_haar"
-# HBM bytes per launch of the virtual A_F kernel on this workload, from the
-# rocprofv3 FETCH_SIZE / WRITE_SIZE passes in
-# profiles/fock_vir_kernel_c2_haar_counters.md (scaled by the same counters
-# for a copy kernel of known size). Set to None when the kernel changes.
-FOCK_VIR_TRAFFIC_BYTES = 13497750
+# HBM bytes per launch of the occupied A_F kernel (packed pair layout) on
+# this workload, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes in
+# profiles/fock_occ_packed_kernel_c2_haar_counters.md (each scaled by the
+# same counter for a copy kernel of known size). None when the kernel has
+# changed since the counters were taken.
+FOCK_OCC_TRAFFIC_BYTES = 23901157
 
 
 def nominal_residual_flops(o, v, naux):
@@ -42,16 +43,20 @@ def nominal_residual_flops(o, v, naux):
             + 4 * o * o * v ** 3 + 4 * o ** 3 * v * v)
 
 
-def fock_vir_flops(o, v):
-    """Algorithmic flops of one launch of the virtual A_F kernel: per
-    occupied pair, f_vv x_ij and x_ij f_vv (2 v^3 multiply-adds each)."""
-    return 4 * o * o * v ** 3
+def fock_occ_bytes(o, v):
+    """Algorithmic HBM bytes of one launch of the occupied A_F kernel in the
+    PNK solve's inner Lanczos step, on the packed pairs i <= j (o (o + 1) / 2
+    blocks of v^2): x, the virtual part y and v_{k-1} read and p written once
+    (FP64), for the doubles and the singles, plus f_vv (read by the singles)."""
+    npair = o * (o + 1) // 2
+    return 8 * (4 * npair * v * v + 4 * o * v + v * v)
 
 
-def fock_vir_bytes(o, v):
-    """Algorithmic HBM bytes of one launch: x read and y written once (FP64),
-    plus f_vv."""
-    return 8 * (2 * o * o * v * v + v * v)
+def fock_occ_flops(o, v):
+    """Its flops: per packed doubles element 2o multiply-adds (the two
+    occupied contractions); per singles element v + o."""
+    npair = o * (o + 1) // 2
+    return 4 * o * npair * v * v + 2 * o * v * (v + o)
 
 
 def cpu_baseline(problem, counts, t1_gpu, t2_gpu, e_gpu):
@@ -143,17 +148,16 @@ def bench_c2(args):
     F_R = nominal_residual_flops(o, v, naux)
     res_ms = ms_res / max(n_res, 1)
     af_ms = ms_afm / n_afm if n_afm else None
-    af_flops = fock_vir_flops(o, v)
-    af_bytes = fock_vir_bytes(o, v)
+    af_bytes = fock_occ_bytes(o, v)
     roof = None
     if af_ms:
-        ach = af_flops / (af_ms * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP64_PEAK_TFLOPS, "traffic": FOCK_VIR_TRAFFIC_BYTES,
-                "kernel": "fock_vir_kernel (A_F virtual contractions, FP64 4x4x4 MFMA)",
-                "launches": n_afm, "avg_us": af_ms * 1e3, "flops_per_launch": af_flops,
-                "hbm_bytes_per_launch": af_bytes,
-                "hbm_GBps": af_bytes / (af_ms * 1e-3) / 1e9}
+        gbs = af_bytes / (af_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": FOCK_OCC_TRAFFIC_BYTES,
+                "kernel": "fock_occ_packed_kernel (A_F occupied contractions, singles and Lanczos update on the "
+                          "packed pairs)",
+                "launches": n_afm, "avg_us": af_ms * 1e3, "bytes_per_launch": af_bytes,
+                "flops_per_launch": fock_occ_flops(o, v)}
     out = {
         "metric": "PNK CCSD solves/s + p50/p99 latency at |dE|<1e-6 Eh; residual TFLOP/s vs FP64",
         "value": args.steps / elapsed,
@@ -181,7 +185,7 @@ def bench_c2(args):
         "precond_solve_ms": ms_pre / n_pre if n_pre else None,
         "time_share": {"residual": ms_res / (1000 * elapsed), "jvp": ms_jvp / (1000 * elapsed),
                        "precond_solve": ms_pre / (1000 * elapsed),
-                       "A_F_virtual_kernel": ms_afm / (1000 * elapsed)},
+                       "A_F_occupied_kernel": ms_afm / (1000 * elapsed)},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:
@@ -301,8 +305,11 @@ def bench_inner(args):
     b1, b2 = (torch.as_tensor(a, device="cuda") for a in random_amplitudes(o, v, 77, scale=1.0))
     out = {"workload": "inner A_F solves, o=10 v=90", "solves": args.steps, "n_vector": o * v + o * o * v * v}
     # full layout (cc_precond_solve), then the packed pair layout the PNK
-    # solver uses (cc_precond_solve_pairsym)
-    for name, sym in (("full", False), ("pairsym", True)):
+    # solver uses (cc_precond_solve_pairsym); --layout picks one of them
+    layouts = [("full", False), ("pairsym", True)]
+    if args.layout != "both":
+        layouts = [x for x in layouts if x[0] == args.layout]
+    for name, sym in layouts:
         h.precond_solve(P, b1, b2, pair_symmetric=sym)  # warm-up: preparation and graph recording
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -328,6 +335,8 @@ def main():
                     help="default: the bench line; the others print their own measurement line")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"], help="J v precision (c3/c4)")
     ap.add_argument("--max-newton", type=int, default=200)
+    ap.add_argument("--layout", default="both", choices=["both", "full", "pairsym"],
+                    help="inner: which inner-solve layout to time")
     ap.add_argument("--requests", type=int, default=40)
     ap.add_argument("--slots", type=int, default=4)
     args = ap.parse_args()

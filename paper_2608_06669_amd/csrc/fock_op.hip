@@ -258,7 +258,7 @@ __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
 // together with its mirror A^T, stages both for every packed pair, and
 // forms the outputs of both tiles for every packed pair from there.
 struct OccPackedArgs {
-  int o, v, t, ntile, nchunks, npair;
+  int o, v, t, ntile, nchunks, npair, psplit, dwg;  // dwg: workgroups of the doubles part (a multiple of 8)
   const double* f_oo;
   const double* f_vv;
   const double* x1;
@@ -275,20 +275,33 @@ struct OccPackedArgs {
 
 __device__ inline int packed_pair(int i, int j, int o) { return i * o - i * (i - 1) / 2 + (j - i); }  // i <= j
 
-// Dynamic LDS: xs[npair][ns] then fo[o][o]; ns = t^2 (diagonal tile) or 2 t^2.
+// Dynamic LDS: xs[npair][ns] then fo[o][o]; ns = t^2 (diagonal tile) or
+// 2 t^2. The first dwg workgroups do the doubles: workgroup b takes the
+// unit c = (b % 8) (dwg / 8) + b / 8, i.e. tile c / psplit and the packed
+// pairs pr = c % psplit + psplit m. Workgroups are dispatched round-robin
+// over the 8 XCDs, so the psplit workgroups of a tile run on one XCD and
+// its staged blocks are fetched into that L2 once. Units past
+// nchunks * psplit only write zero partial sums; the remaining workgroups
+// compute the singles.
 __global__ __launch_bounds__(256) void fock_occ_packed_kernel(OccPackedArgs p) {
   extern __shared__ double lds[];
   __shared__ double red[3][4];
+  // (k, j) -> 2 P(min, max) + (k > j): where x_kj sits among the staged
+  // blocks, and whether it is read through the mirror tile
+  __shared__ int tab[kFockOpMaxOcc * kFockOpMaxOcc];
+  __shared__ unsigned char pi_[kFockOpMaxOcc * (kFockOpMaxOcc + 1) / 2], pj_[kFockOpMaxOcc * (kFockOpMaxOcc + 1) / 2];
   if (p.done && *p.done != 0.0) return;
-  const int o = p.o, v = p.v, t = p.t, npair = p.npair;
+  const int o = p.o, v = p.v, t = p.t, npair = p.npair, ps = p.psplit;
   const int64_t vv = (int64_t)v * v;
   const int tid = threadIdx.x;
   const double beta = *p.beta;
   double dot = 0.0, nrm = 0.0, vv2 = 0.0;
 
-  if ((int)blockIdx.x < p.nchunks) {
-    // chunk -> tile (ta, tb), ta <= tb, row by row over the upper triangle
-    int c = blockIdx.x, ta = 0;
+  const int unit = (int)(blockIdx.x % 8) * (p.dwg / 8) + (int)(blockIdx.x / 8);
+  if ((int)blockIdx.x < p.dwg && unit < p.nchunks * ps) {
+    // tile (ta, tb), ta <= tb, row by row over the upper triangle
+    int c = unit / ps, ta = 0;
+    const int part = unit % ps;
     while (c >= p.ntile - ta) {
       c -= p.ntile - ta;
       ++ta;
@@ -299,63 +312,73 @@ __global__ __launch_bounds__(256) void fock_occ_packed_kernel(OccPackedArgs p) {
     const int ns = diag ? tt : 2 * tt;
     double* xs = lds;
     double* fo = lds + (int64_t)npair * ns;
-    // staged element s: s < tt is (a0 + s / t, b0 + s % t) of A, else
-    // (b0 + r / t, a0 + r % t), r = s - tt, of A^T
-    for (int q = tid; q < npair * ns; q += 256) {
-      const int pr = q / ns, s = q % ns;
-      const int r = s < tt ? s : s - tt;
-      const int a = (s < tt ? a0 : b0) + r / t, b = (s < tt ? b0 : a0) + r % t;
-      xs[q] = (a < v && b < v) ? p.x2[(int64_t)pr * vv + (int64_t)a * v + b] : 0.0;
-    }
-    for (int q = tid; q < o * o; q += 256) fo[q] = p.f_oo[q];
-    __syncthreads();
     const int groups = 256 / ns;
     const int s = tid % ns, g0 = tid / ns;
+    // staged element s: s < tt is (a0 + s / t, b0 + s % t) of A, else
+    // (b0 + r / t, a0 + r % t), r = s - tt, of A^T
     const int r = s < tt ? s : s - tt;
     const int a = (s < tt ? a0 : b0) + r / t, b = (s < tt ? b0 : a0) + r % t;
-    // index of the transposed element (b, a) among the staged ones
     const int sT = diag ? (r % t) * t + r / t : (s < tt ? tt : 0) + (r % t) * t + r / t;
-    if (g0 < groups && a < v && b < v) {
-      const int64_t e = (int64_t)a * v + b;
-      constexpr int R = 4;
-      for (int pr0 = g0; pr0 < npair; pr0 += R * groups) {
-        double yin[R], vin[R];
+    const bool active = g0 < groups && a < v && b < v;
+    const int64_t e = active ? (int64_t)a * v + b : 0;
+    // this thread's outputs: pairs part + ps (g0 + groups m), m = 0, 1, ...
+    const int stride = ps * groups;
+    constexpr int R = 4;
+    double yin[R], vin[R];
+    auto fetch = [&](int pr0) {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        const int pr = pr0 + u * stride;
+        const int64_t idx = (int64_t)(pr < npair ? pr : 0) * vv + e;
+        yin[u] = p.y2[idx];
+        vin[u] = p.vprev2[idx];
+      }
+    };
+    const int first = part + ps * g0;
+    if (active) fetch(first);  // in flight during the staging
+    for (int q = tid; q < npair * ns; q += 256) {
+      const int pr = q / ns, sq = q % ns;
+      const int rq = sq < tt ? sq : sq - tt;
+      const int aq = (sq < tt ? a0 : b0) + rq / t, bq = (sq < tt ? b0 : a0) + rq % t;
+      xs[q] = (aq < v && bq < v) ? p.x2[(int64_t)pr * vv + (int64_t)aq * v + bq] : 0.0;
+    }
+    for (int q = tid; q < o * o; q += 256) {
+      fo[q] = p.f_oo[q];
+      const int k = q / o, j = q % o;
+      tab[q] = 2 * (k <= j ? packed_pair(k, j, o) : packed_pair(j, k, o)) + (k > j ? 1 : 0);
+      if (k <= j) {
+        pi_[packed_pair(k, j, o)] = (unsigned char)k;
+        pj_[packed_pair(k, j, o)] = (unsigned char)j;
+      }
+    }
+    __syncthreads();
+    if (active) {
+      for (int pr0 = first; pr0 < npair; pr0 += R * stride) {
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          const int pr = pr0 + u * groups;
-          const int64_t idx = (int64_t)(pr < npair ? pr : 0) * vv + e;
-          yin[u] = p.y2[idx];
-          vin[u] = p.vprev2[idx];
-        }
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const int pr = pr0 + u * groups;
+          const int pr = pr0 + u * stride;
           if (pr >= npair) break;
-          int i = 0, rem = pr;
-          while (rem >= o - i) {
-            rem -= o - i;
-            ++i;
-          }
-          const int j = i + rem;
+          const int i = pi_[pr], j = pj_[pr];
           double occ = 0.0;
           for (int k = 0; k < o; ++k) {
-            const double xkj = k <= j ? xs[packed_pair(k, j, o) * ns + s] : xs[packed_pair(j, k, o) * ns + sT];
-            const double xik = i <= k ? xs[packed_pair(i, k, o) * ns + s] : xs[packed_pair(k, i, o) * ns + sT];
+            const int t1 = tab[k * o + j], t2 = tab[i * o + k];
+            const double xkj = xs[(t1 >> 1) * ns + ((t1 & 1) ? sT : s)];
+            const double xik = xs[(t2 >> 1) * ns + ((t2 & 1) ? sT : s)];
             occ += fo[k * o + i] * xkj + fo[k * o + j] * xik;
           }
-          const int64_t idx = (int64_t)pr * vv + e;
           const double q = (yin[u] - occ) - beta * vin[u];
           const double vk = xs[pr * ns + s];
           const double w = i == j ? 1.0 : 2.0;  // x_ij and x_ji = x_ij^T both count
-          p.y2[idx] = q;
+          p.y2[(int64_t)pr * vv + e] = q;
           dot += w * vk * q;
           nrm += w * q * q;
           vv2 += w * vk * vk;
         }
+        if (pr0 + R * stride < npair) fetch(pr0 + R * stride);
       }
     }
-  } else {
-    singles_part<true>(p.o, p.v, p.f_oo, p.f_vv, p.x1, p.y1, p.vprev1, beta, p.s1, blockIdx.x - p.nchunks, dot, nrm,
+  } else if ((int)blockIdx.x >= p.dwg) {
+    singles_part<true>(p.o, p.v, p.f_oo, p.f_vv, p.x1, p.y1, p.vprev1, beta, p.s1, blockIdx.x - p.dwg, dot, nrm,
                        vv2);
   }
 
@@ -479,17 +502,19 @@ bool fock_op_plan(FockOp& op) {
   if (op.pt > 0) {
     op.pntile = (int)ceil_div(op.v, op.pt);
     op.pnchunks = op.pntile * (op.pntile + 1) / 2;
+    // split the packed pairs of a tile over up to 4 workgroups (each stages
+    // the whole tile) until there are about 1024 of them: the kernel is
+    // bound by latency, which more resident waves hide
+    op.psplit = 1;
+    while (op.psplit < 4 && (int64_t)op.pnchunks * op.psplit < 1024 && op.npair >= 8 * 2 * op.psplit) ++op.psplit;
+    op.pdwg = (int)(8 * ceil_div((int64_t)op.pnchunks * op.psplit, 8));
   }
   return (int64_t)op.tiles * op.o * op.o < (1ll << 31) - 8 && op.nparts() <= 0x7fffffff;
 }
 
-bool fock_op_is_virtual_kernel(const void* func) {
-  return func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 16>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<32, 2, 32>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 16>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<48, 4, 32>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 16>) ||
-         func == reinterpret_cast<const void*>(&fock_vir_kernel<64, 2, 32>);
+bool fock_op_is_occupied_lanczos_kernel(const void* func) {
+  return func == reinterpret_cast<const void*>(&fock_occ_packed_kernel) ||
+         func == reinterpret_cast<const void*>(&fock_occ_kernel<true>);
 }
 
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s) {
@@ -533,6 +558,8 @@ void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double*
   a.ntile = op.pntile;
   a.nchunks = op.pnchunks;
   a.npair = op.npair;
+  a.psplit = op.psplit;
+  a.dwg = op.pdwg;
   a.f_oo = op.f_oo;
   a.f_vv = op.f_vv;
   a.x1 = v;

@@ -29,9 +29,11 @@ struct FockOp {
   int nsingles = 0;         // ... plus workgroups of 16 singles each
   // occupied kernel on the packed pair layout: pt x pt tiles (and their
   // mirrors), pntile tiles per side, pnchunks = pntile (pntile + 1) / 2
-  int npair = 0, pt = 0, pntile = 0, pnchunks = 0;
+  // psplit workgroups share a tile, each taking every psplit-th pair;
+  // pdwg = pnchunks * psplit rounded up to a multiple of 8 (XCD grouping)
+  int npair = 0, pt = 0, pntile = 0, pnchunks = 0, psplit = 1, pdwg = 0;
   int64_t nparts() const { return (int64_t)nchunks + nsingles; }
-  int64_t nparts_packed() const { return (int64_t)pnchunks + nsingles; }
+  int64_t nparts_packed() const { return (int64_t)pdwg + nsingles; }
 };
 
 // Picks the launch shapes; false when these kernels do not apply (o too
@@ -63,8 +65,8 @@ void fock_op_lanczos_vir_packed(const FockOp& op, const double* v, double* p, co
 void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
                                 double* partials, double singles_scale, const double* done, hipStream_t s);
 
-// True for the virtual-contraction kernel (the launch that does the matrix
-// work), used to find its nodes in a recorded graph.
-bool fock_op_is_virtual_kernel(const void* func);
+// True for the occupied kernel of either Lanczos form (the launch timed
+// in a recorded graph).
+bool fock_op_is_occupied_lanczos_kernel(const void* func);
 
 }  // namespace pnk

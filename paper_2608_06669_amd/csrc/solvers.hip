@@ -454,19 +454,19 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
     // packed pair layout (see precond_solve_sym): the same three launches
     n = ov + (int64_t)op->npair * eng_.v() * eng_.v();
     Timers* tm = eng_.timers();
-    if (tm) tm->begin(kTimerFock, s);
     fock_op_lanczos_vir_packed(*op, v, p, st + kDone, s);
-    if (tm) tm->end(kTimerFock, s);
+    if (tm) tm->begin(kTimerFock, s);
     fock_op_lanczos_occ_packed(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, st + kDone, s);
+    if (tm) tm->end(kTimerFock, s);
     nparts1 = (int)op->nparts_packed();
   } else if (op && op->nparts() <= kMaxFusedParts) {
     // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p>; the timer
-    // covers the virtual (matrix-core) launch
+    // covers the occupied launch
     Timers* tm = eng_.timers();
-    if (tm) tm->begin(kTimerFock, s);
     fock_op_lanczos_vir(*op, v, p, st + kDone, s);
-    if (tm) tm->end(kTimerFock, s);
+    if (tm) tm->begin(kTimerFock, s);
     fock_op_lanczos_occ(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, st + kDone, s);
+    if (tm) tm->end(kTimerFock, s);
     nparts1 = (int)op->nparts();
   } else {
     eng_.fock_apply(v, v + ov, p, p + ov, s);
@@ -496,9 +496,6 @@ void Solver::lanczos_block(hipStream_t s) {
 
 namespace {
 
-// Brackets every virtual A_F kernel node of a recorded graph with two event
-// record nodes (ev[2k], ev[2k+1]) so each launch's duration can be read
-// after a replay. Returns the number of nodes bracketed, -1 on error.
 // The nodes of a graph recorded from one stream, in stream order: such a
 // graph is a chain (one root, one dependent per node). Empty if it is not.
 std::vector<hipGraphNode_t> chain_order(hipGraph_t g) {
@@ -521,9 +518,10 @@ std::vector<hipGraphNode_t> chain_order(hipGraph_t g) {
   return out;
 }
 
-// Inserts event record nodes before and after each virtual A_F kernel node
-// of a chain graph: pair k (events ev[2k], ev[2k+1]) brackets the k-th such
-// launch in stream order. Returns the number of pairs, -1 on failure.
+// Inserts event record nodes before and after each occupied A_F kernel
+// node (the Lanczos form) of a chain graph: pair k (events ev[2k],
+// ev[2k+1]) brackets the k-th such launch in stream order, so its duration
+// can be read after a replay. Returns the number of pairs, -1 on failure.
 int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
   const std::vector<hipGraphNode_t> nodes = chain_order(g);
   if (nodes.empty()) return -1;
@@ -534,7 +532,7 @@ int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
     if (type != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams kp{};
     if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) return -1;
-    if (!fock_op_is_virtual_kernel(kp.func)) continue;
+    if (!fock_op_is_occupied_lanczos_kernel(kp.func)) continue;
     if (k >= max_pairs) return -1;
     size_t nd = 0, ns = 0;
     if (hipGraphNodeGetDependencies(node, nullptr, &nd) != hipSuccess) return -1;
