@@ -325,13 +325,54 @@ def bench_inner(args):
     h.close()
 
 
+def bench_protocols(args):
+    """The method table on the device: PNK, NK, INK, FP and SFP+DIIS on C1
+    (canonical) and C2 (Haar-rotated), at the CCSD and the CCD level. Prints
+    one JSON line with, per run, the residual evaluations (residuals plus
+    Jacobian products, the paper's cost measure), A_F products, steps, time,
+    energy and whether ||r||_inf < tol was reached."""
+    import torch
+
+    import paper_2608_06669_amd as pk
+    from gen import make_config
+
+    pk.load()
+    h = pk.Handle(0)
+    out = {"workload": "protocols (method table) on c1_canonical and c2_haar, CCSD and CCD", "runs": []}
+    runs = [("PNK", "pnk", {}), ("NK", "pnk", {"protocol": "nk"}), ("INK", "pnk", {"protocol": "ink"}),
+            ("FP", "fp", {"diis_size": 0}), ("SFP+DIIS", "fp", {"level_shift": 0.2})]
+    for cfg in ("c1_canonical", "c2_haar"):
+        p = make_config(cfg)
+        tol = p.meta["tol"]
+        P = pk.DeviceProblem.from_problem(p)
+        for level in ("ccsd", "ccd"):
+            for name, kind, opts in runs:
+                o = dict(opts, tol_inf=tol, ccd=int(level == "ccd"))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if kind == "pnk":
+                    _, _, info = h.solve_pnk(P, max_newton=args.max_newton, **o)
+                else:
+                    _, _, info = h.solve_fp_diis(P, max_iter=max(args.max_newton, 200), **o)
+                dt = time.perf_counter() - t0
+                out["runs"].append({"config": cfg, "level": level, "protocol": name,
+                                    "converged": info["status"] == "CC_OK",
+                                    "residual_evaluations": info["n_residual"] + info["n_jvp"],
+                                    "n_residual": info["n_residual"], "n_jvp": info["n_jvp"],
+                                    "n_afmv": info["n_afmv"], "steps": info["newton_iters"],
+                                    "seconds": dt, "e_corr": info["e_corr"], "res_inf": info["res_inf"]})
+                print(f"{cfg} {level} {name}: {out['runs'][-1]}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner", "protocols"],
                     help="default: the bench line; the others print their own measurement line")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"], help="J v precision (c3/c4)")
     ap.add_argument("--max-newton", type=int, default=200)
@@ -350,6 +391,8 @@ def main():
         bench_serving(args)
     elif args.workload == "inner":
         bench_inner(args)
+    elif args.workload == "protocols":
+        bench_protocols(args)
     else:
         bench_large(args)
 

@@ -151,7 +151,18 @@ cc_status cc_precond_solve_pairsym(cc_handle* h, const cc_problem* p, const doub
  * use_fd_jvp: 1 = forward-difference product of equation
  *            jacobian_vector_product_via_finite_difference instead of the
  *            analytic one (FP64 only)
- * init_mp2:  1 = start from theta = -A_F^{-1} r(0); 0 = start from t1/t2 */
+ * init_mp2:  1 = start from theta = -A_F^{-1} r(0); 0 = start from t1/t2
+ * protocol:  outer solver of the method table: CC_PNK (Newton-GMRES
+ *            preconditioned by A_F, Algorithm 1); CC_NK (the same without
+ *            preconditioner; like every protocol it starts from the MP2
+ *            amplitudes when init_mp2); CC_INK (t <- t + dt with
+ *            A_F dt = -r(t), equation inexact_newton_update: one residual
+ *            and one inner solve per step, max_newton of them; m_max and
+ *            the forcing terms are unused)
+ * ccd:       1 = the paper's CCD level: t1 is held at zero and the singles
+ *            equations are dropped (t1 in and out is zero) */
+typedef enum { CC_PNK = 0, CC_NK = 1, CC_INK = 2 } cc_protocol;
+
 typedef struct {
   double tol_inf;
   int max_newton;
@@ -163,12 +174,14 @@ typedef struct {
   cc_precision jvp_prec;
   int use_fd_jvp;
   int init_mp2;
+  cc_protocol protocol;
+  int ccd;
 } cc_pnk_opts;
 
 /* FP (+ level shift, + DIIS) options: t <- t - r/(D + level_shift) with D
  * from the diagonal of f in the given gauge (equation Commutator_MO;
  * Appendix D), DIIS over the last diis_size (amplitude, step) pairs from
- * iteration diis_start on (diis_size 0: plain FP). */
+ * iteration diis_start on (diis_size 0: plain FP); ccd as for PNK. */
 typedef struct {
   double tol_inf;
   int max_iter;
@@ -176,6 +189,7 @@ typedef struct {
   int diis_start;
   double level_shift;
   int init_mp2;
+  int ccd;
 } cc_fp_opts;
 
 /* Solve statistics (host). n_residual and n_jvp count residual evaluations
@@ -189,10 +203,10 @@ typedef struct {
 
 /* Defaults: tol 1e-8, 100 Newton steps, m_max 20, gamma 0.9, alpha 1.5,
  * eta0 0.5, eta_max 0.9, inner rtol 1e-12, inner maxit 200, restart 30,
- * FP64 products, analytic J v, MP2 start. */
+ * FP64 products, analytic J v, MP2 start, PNK, CCSD. */
 void cc_pnk_opts_default(cc_pnk_opts* o);
 /* Defaults: tol 1e-8, 500 iterations, DIIS 8 from iteration 2, no shift,
- * MP2 start. */
+ * MP2 start, CCSD. */
 void cc_fp_opts_default(cc_fp_opts* o);
 
 /* PNK solve. t1/t2: in = initial guess when !init_mp2, out = solution (or

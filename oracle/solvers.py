@@ -164,18 +164,31 @@ class SolveInfo:
 
 
 class _Problem:
-    def __init__(self, f_oo, f_ov, f_vv, L):
+    """The maps the solvers iterate on. ccd=True is the paper's CCD level:
+    t1 is held at zero and the singles equations are dropped, i.e. every
+    vector (amplitudes, residual, J v, A_F^-1 b) has its singles part set to
+    zero. With t1 = 0 the doubles residual of the T1-dressed equations is the
+    CCD residual."""
+
+    def __init__(self, f_oo, f_ov, f_vv, L, ccd=False):
         self.f_oo, self.f_ov, self.f_vv, self.L = f_oo, f_ov, f_vv, L
         self.o, self.v = f_oo.shape[0], f_vv.shape[0]
+        self.ccd = ccd
+
+    def mask(self, x):
+        if self.ccd:
+            x = x.copy()
+            x[: self.o * self.v] = 0.0
+        return x
 
     def residual(self, x):
-        return pack(*ccsd.residual(self.f_oo, self.f_ov, self.f_vv, self.L, *unpack(x, self.o, self.v)))
+        return self.mask(pack(*ccsd.residual(self.f_oo, self.f_ov, self.f_vv, self.L, *unpack(x, self.o, self.v))))
 
     def jvp(self, x, q, mode="complex", r=None, delta=None):
         t1, t2 = unpack(x, self.o, self.v)
         v1, v2 = unpack(q, self.o, self.v)
         if mode == "complex":
-            return pack(*ccsd.jvp_complex_step(self.f_oo, self.f_ov, self.f_vv, self.L, t1, t2, v1, v2))
+            return self.mask(pack(*ccsd.jvp_complex_step(self.f_oo, self.f_ov, self.f_vv, self.L, t1, t2, v1, v2)))
         # forward difference (the paper's form), r = r(x) given
         p = self.residual(x + delta * q)
         return (p - r) / delta
@@ -184,11 +197,14 @@ class _Problem:
         return float(ccsd.energy(self.f_oo, self.f_ov, self.f_vv, self.L, *unpack(x, self.o, self.v)))
 
     def precond(self, b, rtol, maxit, restart, info):
+        # A_F has no doubles <- singles coupling (its doubles rows involve x2
+        # only), so for b1 = 0 the doubles of A_F^-1 b are A_dd^-1 b2: the
+        # CCD preconditioner once the singles are dropped
         res = gmres(lambda y: pack(*fock_apply(self.f_oo, self.f_ov, self.f_vv, *unpack(y, self.o, self.v))),
                     b, rtol=rtol, maxit=maxit, restart=restart)
         info.n_afmv += res.iters
         info.n_inner_iters += res.iters
-        return res.x
+        return self.mask(res.x)
 
 
 def mp2_guess(f_oo, f_ov, f_vv, L, inner_rtol=1e-12, inner_maxit=200, inner_restart=30):
@@ -218,10 +234,11 @@ def forcing_term(k, rn, rn_prev, eta_prev, tol, gamma=0.9, alpha=1.5,
 def solve_pnk(f_oo, f_ov, f_vv, L, tol=1e-8, max_newton=100, m_max=20,
               gamma=0.9, alpha=1.5, eta0=0.5, eta_max=0.9, inner_rtol=1e-12,
               inner_maxit=200, inner_restart=30, jvp="complex", x0=None,
-              precond=True):
-    """PNK (precond=True) or unpreconditioned NK (precond=False)."""
+              precond=True, ccd=False):
+    """PNK (precond=True) or unpreconditioned NK (precond=False), Algorithm 1
+    and the method table; ccd=True at the CCD level (see _Problem)."""
     t_start = time.perf_counter()
-    P = _Problem(f_oo, f_ov, f_vv, L)
+    P = _Problem(f_oo, f_ov, f_vv, L, ccd)
     info = SolveInfo()
     N = P.o * P.v + P.o ** 2 * P.v ** 2
 
@@ -231,11 +248,13 @@ def solve_pnk(f_oo, f_ov, f_vv, L, tol=1e-8, max_newton=100, m_max=20,
         return P.precond(b, inner_rtol, inner_maxit, inner_restart, info)
 
     if x0 is None:
+        # MP2-type start for every protocol (the numerics section uses it in
+        # all examples): -A_F^-1 r(0), also for NK
         r0 = P.residual(np.zeros(N))
         info.n_residual += 1
-        x = -Ainv(r0)
+        x = -P.precond(r0, inner_rtol, inner_maxit, inner_restart, info)
     else:
-        x = x0.copy()
+        x = P.mask(x0)
     rn_prev = None
     eta = eta0
     k = 0
@@ -315,17 +334,18 @@ def jacobi_denominators(f_oo, f_vv, shift=0.0):
 
 def solve_fp_diis(f_oo, f_ov, f_vv, L, tol=1e-8, max_iter=500, diis_size=8,
                   diis_start=2, level_shift=0.0, x0=None, init="mp2",
-                  inner_rtol=1e-12, diverge=1e6):
+                  inner_rtol=1e-12, diverge=1e6, ccd=False):
     """(S)FP iteration t <- t - r(t)/D with DIIS over the last `diis_size`
-    (amplitude, Jacobi step) pairs; diis_size = 0 disables DIIS."""
+    (amplitude, Jacobi step) pairs; diis_size = 0 disables DIIS; ccd=True at
+    the CCD level (see _Problem)."""
     t_start = time.perf_counter()
-    P = _Problem(f_oo, f_ov, f_vv, L)
+    P = _Problem(f_oo, f_ov, f_vv, L, ccd)
     info = SolveInfo()
     N = P.o * P.v + P.o ** 2 * P.v ** 2
     d1, d2 = jacobi_denominators(f_oo, f_vv, level_shift)
     D = pack(d1, d2)
     if x0 is not None:
-        x = x0.copy()
+        x = P.mask(x0)
     elif init == "mp2":
         r0 = P.residual(np.zeros(N))
         info.n_residual += 1
@@ -368,6 +388,48 @@ def solve_fp_diis(f_oo, f_ov, f_vv, L, tol=1e-8, max_iter=500, diis_size=8,
                 c = np.linalg.lstsq(B, rhs, rcond=None)[0][:m]
                 xn = sum(ci * xi for ci, xi in zip(c, hist_x))
         x = xn
+        it += 1
+    info.newton_iters = it
+    info.e_corr = P.energy(x)
+    info.seconds = time.perf_counter() - t_start
+    t1, t2 = unpack(x, P.o, P.v)
+    return t1.copy(), t2.copy(), info
+
+
+def solve_ink(f_oo, f_ov, f_vv, L, tol=1e-8, max_iter=200, inner_rtol=1e-12,
+              inner_maxit=200, inner_restart=30, x0=None, ccd=False, diverge=1e6):
+    """INK (method table): the Newton update with A_F in place of the
+    Jacobian, A_F dt = -r(t) (equation inexact_newton_update), solved by
+    GMRES; t <- t + dt until ||r||_inf < tol. Starts from the MP2 amplitudes
+    -A_F^-1 r(0) unless x0 is given. In the canonical gauge A_F is the
+    diagonal of orbital-energy differences and INK is the plain FP
+    iteration."""
+    t_start = time.perf_counter()
+    P = _Problem(f_oo, f_ov, f_vv, L, ccd)
+    info = SolveInfo()
+    N = P.o * P.v + P.o ** 2 * P.v ** 2
+    if x0 is not None:
+        x = P.mask(x0)
+    else:
+        r0 = P.residual(np.zeros(N))
+        info.n_residual += 1
+        x = -P.precond(r0, inner_rtol, inner_maxit, inner_restart, info)
+    it = 0
+    while True:
+        r = P.residual(x)
+        info.n_residual += 1
+        rinf = float(np.max(np.abs(r)))
+        rn = float(np.linalg.norm(r))
+        info.history.append((info.n_residual, rn, rinf))
+        info.res_inf, info.res_2 = rinf, rn
+        if not np.isfinite(rn) or rn > diverge:
+            break
+        if rinf < tol:
+            info.converged = True
+            break
+        if it >= max_iter:
+            break
+        x = x - P.precond(r, inner_rtol, inner_maxit, inner_restart, info)
         it += 1
     info.newton_iters = it
     info.e_corr = P.energy(x)

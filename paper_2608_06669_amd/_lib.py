@@ -26,6 +26,8 @@ STATUS_NAMES = {0: "CC_OK", 1: "CC_NOT_CONVERGED", -1: "CC_ERR_ARG", -2: "CC_ERR
 
 CC_FP64, CC_FP32, CC_BF16 = 0, 1, 2
 PRECISIONS = {"fp64": CC_FP64, "fp32": CC_FP32, "bf16": CC_BF16}
+CC_PNK, CC_NK, CC_INK = 0, 1, 2
+PROTOCOLS = {"pnk": CC_PNK, "nk": CC_NK, "ink": CC_INK}
 
 
 class cc_problem(ctypes.Structure):
@@ -39,12 +41,13 @@ class cc_pnk_opts(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("alpha", ctypes.c_double), ("eta0", ctypes.c_double),
                 ("eta_max", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("inner_restart", ctypes.c_int), ("jvp_prec", ctypes.c_int), ("use_fd_jvp", ctypes.c_int),
-                ("init_mp2", ctypes.c_int)]
+                ("init_mp2", ctypes.c_int), ("protocol", ctypes.c_int), ("ccd", ctypes.c_int)]
 
 
 class cc_fp_opts(ctypes.Structure):
     _fields_ = [("tol_inf", ctypes.c_double), ("max_iter", ctypes.c_int), ("diis_size", ctypes.c_int),
-                ("diis_start", ctypes.c_int), ("level_shift", ctypes.c_double), ("init_mp2", ctypes.c_int)]
+                ("diis_start", ctypes.c_int), ("level_shift", ctypes.c_double), ("init_mp2", ctypes.c_int),
+                ("ccd", ctypes.c_int)]
 
 
 class cc_info(ctypes.Structure):

@@ -67,6 +67,8 @@ def pnk_opts(**kw) -> cc_pnk_opts:
     for k, v in kw.items():
         if k == "jvp_prec" and isinstance(v, str):
             v = L.PRECISIONS[v]
+        if k == "protocol" and isinstance(v, str):
+            v = L.PROTOCOLS[v]
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)

@@ -146,6 +146,8 @@ PnkOptions to_internal(const cc_pnk_opts& o) {
   r.jvp_prec = (Prec)o.jvp_prec;
   r.use_fd_jvp = o.use_fd_jvp != 0;
   r.init_mp2 = o.init_mp2 != 0;
+  r.protocol = (int)o.protocol;
+  r.ccd = o.ccd != 0;
   return r;
 }
 
@@ -159,6 +161,7 @@ void check_pnk_opts(const cc_pnk_opts& o) {
   PNK_REQUIRE(o.jvp_prec == CC_FP64 || o.jvp_prec == CC_FP32 || o.jvp_prec == CC_BF16, "unknown jvp_prec");
   PNK_REQUIRE(!(o.use_fd_jvp && o.jvp_prec != CC_FP64), "the finite-difference product is FP64 only");
   PNK_REQUIRE(o.eta_max > 0 && o.eta_max < 1 && o.eta0 > 0 && o.eta0 < 1, "forcing terms must be in (0, 1)");
+  PNK_REQUIRE(o.protocol == CC_PNK || o.protocol == CC_NK || o.protocol == CC_INK, "unknown protocol");
 }
 
 int lowp_for(cc_precision p) { return p == CC_FP32 ? 1 : (p == CC_BF16 ? 2 : 0); }
@@ -228,6 +231,8 @@ void cc_pnk_opts_default(cc_pnk_opts* o) {
   o->jvp_prec = CC_FP64;
   o->use_fd_jvp = 0;
   o->init_mp2 = 1;
+  o->protocol = CC_PNK;
+  o->ccd = 0;
 }
 
 void cc_fp_opts_default(cc_fp_opts* o) {
@@ -238,6 +243,7 @@ void cc_fp_opts_default(cc_fp_opts* o) {
   o->diis_start = 2;
   o->level_shift = 0.0;
   o->init_mp2 = 1;
+  o->ccd = 0;
 }
 
 cc_status cc_residual(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, double* r1, double* r2,
@@ -381,6 +387,7 @@ cc_status cc_solve_fp_diis(cc_handle* h, const cc_problem* p, const cc_fp_opts* 
   fo.diis_start = o.diis_start;
   fo.level_shift = o.level_shift;
   fo.init_mp2 = o.init_mp2 != 0;
+  fo.ccd = o.ccd != 0;
   SolveStats st;
   H->sol->solve_fp_diis(H->xa, fo, &st, s);
   unpack(ov, n2, H->xa, t1, t2, s);

@@ -806,25 +806,50 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   hist_.clear();
   PNK_REQUIRE(opt.m_max >= 1 && opt.m_max <= m_max_, "pnk: m_max exceeds the allocated basis");
   const int64_t n = n_;
-  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  const int o = eng_.o(), vir = eng_.v();
+  const int64_t ov = (int64_t)o * vir;
+  PNK_REQUIRE(opt.protocol == PnkOptions::kPNK || opt.protocol == PnkOptions::kNK ||
+                  opt.protocol == PnkOptions::kINK,
+              "pnk: unknown protocol");
+  // CCD level: every vector keeps zero singles
+  auto mask = [&](double* y) {
+    if (opt.ccd) fill(ov, 0.0, y, s);
+  };
   auto Ainv = [&](const double* b, double* out) {
-    bool conv = true;
-    const int it = precond_solve(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
-    st->n_afmv += it;
-    st->n_inner_iters += it;
+    if (opt.protocol == PnkOptions::kNK) {
+      // no preconditioner: the identity on pair-symmetric vectors, applied
+      // as the projection (b2 + b2^T over pairs) / 2 so that rounding-level
+      // antisymmetric parts do not enter the Krylov space
+      copy(ov, b, out, s);
+      fill(n - ov, 0.0, out + ov, s);
+      pair_symmetrize_add(o, vir, b + ov, 0.5, out + ov, s);
+    } else {
+      bool conv = true;
+      const int it = precond_solve(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
+      st->n_afmv += it;
+      st->n_inner_iters += it;
+    }
+    mask(out);
   };
   if (opt.init_mp2) {
+    // MP2-type start for every protocol (NK included): -A_F^-1 r(0)
     eng_.residual(eng_.zeros(), eng_.zeros() + ov, r_, r_ + ov, s);
     st->n_residual++;
-    Ainv(r_, x);
+    mask(r_);
+    bool conv = true;
+    const int it = precond_solve(r_, x, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
+    st->n_afmv += it;
+    st->n_inner_iters += it;
     axpby(n, 0.0, x, -1.0, x, s);
   }
+  mask(x);
   double rn_prev = 0.0, eta = opt.eta0;
   int k = 0;
   std::vector<double> H, cs, sn, g, h;
   while (true) {
     eng_.residual(x, x + ov, r_, r_ + ov, s);
     st->n_residual++;
+    mask(r_);
     double rinf, rn;
     norms(r_, &rinf, &rn, s);
     hist_.push_back(rn);
@@ -837,6 +862,15 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     if (!std::isfinite(rn)) { st->diverged = 1; break; }
     if (rinf < opt.tol_inf) { st->converged = 1; break; }
     if (k >= opt.max_newton) break;
+    if (opt.protocol == PnkOptions::kINK) {
+      // A_F dt = -r(t): one inner solve per step, no Jacobian products
+      if (rn > 1e6) break;  // diverging, as FP ends it
+      Ainv(r_, w_);
+      axpby(n, -1.0, w_, 1.0, x, s);
+      rn_prev = rn;
+      ++k;
+      continue;
+    }
     eta = forcing(k, rn, rn_prev, eta, opt.tol_inf, opt);
     // z = A_F^{-1} r, q_1 = z / beta
     Ainv(r_, w_);
@@ -870,6 +904,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
         eng_.jvp(q, q + ov, w_, w_ + ov, opt.jvp_prec, s);
       }
       st->n_jvp++;
+      mask(w_);
       Ainv(w_, wv);
       const double hn = orthogonalise(Qo_, n, m + 1, wv, h, s);
       for (int i = 0; i <= m; ++i) H[i + (size_t)m * (M + 1)] = h[i];
@@ -948,15 +983,20 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
   PNK_REQUIRE(opt.diis_size <= diis_, "fp: DIIS size exceeds the allocated history");
   const int64_t n = n_;
   const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  auto mask = [&](double* y) {
+    if (opt.ccd) fill(ov, 0.0, y, s);
+  };
   if (opt.init_mp2) {
     eng_.residual(eng_.zeros(), eng_.zeros() + ov, r_, r_ + ov, s);
     st->n_residual++;
+    mask(r_);
     bool conv = true;
     const int it = precond_solve(r_, x, opt.inner_rtol, 200, restart_, s, &conv, true);
     st->n_afmv += it;
     st->n_inner_iters += it;
     axpby(n, 0.0, x, -1.0, x, s);
   }
+  mask(x);
   const int nd = opt.diis_size;
   std::vector<int> slots;  // slot ids in age order (oldest first)
   std::vector<double> Bfull((size_t)std::max(nd, 1) * std::max(nd, 1), 0.0);
@@ -964,6 +1004,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
   while (true) {
     eng_.residual(x, x + ov, r_, r_ + ov, s);
     st->n_residual++;
+    mask(r_);
     double rinf, rn;
     norms(r_, &rinf, &rn, s);
     hist_.push_back(rn);

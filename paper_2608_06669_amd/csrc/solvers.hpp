@@ -20,6 +20,12 @@ struct PnkOptions {
   Prec jvp_prec = Prec::F64;
   bool use_fd_jvp = false;
   bool init_mp2 = true;
+  // outer protocol (the method table): PNK; NK (Newton-GMRES without
+  // preconditioner); INK (t <- t - A_F^-1 r(t), the Newton update with A_F
+  // in place of the Jacobian)
+  enum Protocol { kPNK = 0, kNK = 1, kINK = 2 };
+  int protocol = kPNK;
+  bool ccd = false;  // CCD level: t1 held at zero, singles equations dropped
 };
 
 struct FpOptions {
@@ -30,6 +36,7 @@ struct FpOptions {
   double level_shift = 0.0;
   bool init_mp2 = true;
   double inner_rtol = 1e-12;
+  bool ccd = false;  // CCD level: t1 held at zero, singles equations dropped
 };
 
 struct SolveStats {

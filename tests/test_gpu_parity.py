@@ -323,6 +323,47 @@ def test_fp_diis_c1_matches_oracle(handle, lib):
     assert info6["n_residual"] == ia6.n_residual
 
 
+@pytest.mark.parametrize("ccd", [False, True])
+def test_protocols_match_the_oracle(handle, lib, ccd):
+    """The method table on the device: PNK, NK (no preconditioner) and INK
+    (A_F dt = -r) in a rotated gauge, at the CCSD and the CCD level, against
+    the oracle's solvers: same root, same energy, same number of steps."""
+    p = make_problem(3, 7, 14, 97, gauge="haar")
+    P = lib.DeviceProblem.from_problem(p)
+    cases = {
+        "pnk": ({}, dict()),
+        "nk": ({"max_newton": 200}, dict(precond=False, max_newton=200)),
+    }
+    for name, (gopt, oopt) in cases.items():
+        t1, t2, info = handle.solve_pnk(P, tol_inf=1e-10, protocol=name, ccd=int(ccd), **gopt)
+        a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-10, ccd=ccd, **oopt)
+        assert info["status"] == "CC_OK" and ia.converged, name
+        assert abs(info["e_corr"] - ia.e_corr) < 1e-9, name
+        assert np.abs(host(t2) - a2).max() < 1e-8 and np.abs(host(t1) - a1).max() < 1e-8, name
+        assert info["newton_iters"] == ia.newton_iters, name
+        if ccd:
+            assert not np.any(host(t1)), name
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-10, protocol="ink", ccd=int(ccd), max_newton=200)
+    a1, a2, ia = solvers.solve_ink(*_args(p), tol=1e-10, ccd=ccd)
+    assert info["status"] == "CC_OK" and ia.converged
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-9
+    assert np.abs(host(t2) - a2).max() < 1e-8
+    assert info["newton_iters"] == ia.newton_iters and info["n_residual"] == ia.n_residual
+    assert info["n_jvp"] == 0
+
+
+def test_sfp_diis_ccd_matches_the_oracle(handle, lib):
+    """SFP+DIIS (level shift 0.2) at the CCD level, far from DIIS's noise
+    floor: the same path as the oracle, and t1 stays zero."""
+    p = make_problem(3, 7, 14, 97, gauge="canonical")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_fp_diis(P, tol_inf=1e-7, level_shift=0.2, ccd=1)
+    a1, a2, ia = solvers.solve_fp_diis(*_args(p), tol=1e-7, level_shift=0.2, ccd=True)
+    assert info["status"] == "CC_OK" and ia.converged
+    assert not np.any(host(t1))
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-8
+    assert info["n_residual"] == ia.n_residual
+
 
 def test_timed_solve_matches_untimed(handle, lib):
     """Timing instrumentation (events around the fused A_F launches inside

@@ -260,6 +260,62 @@ def test_fp_diverges_or_slows_in_rotated_gauge_while_pnk_does_not():
     assert (not fh.converged) or fh.n_residual > fc.n_residual
 
 
+# ------------------------------------------------- protocols, CCD ------
+@pytest.mark.parametrize("o,v,naux,seed", [(2, 3, 6, 94), (2, 4, 5, 95)])
+def test_ccd_root_zeroes_the_determinant_space_doubles(o, v, naux, seed):
+    """The CCD level (t1 held at 0, singles equations dropped): PNK's root
+    makes the doubles projections of exp(-T2) H exp(T2) vanish when they are
+    evaluated literally in the determinant space, and its energy is the
+    determinant-space one; the singles projections do not vanish (it is not
+    the CCSD root)."""
+    p = make_general(o, v, naux, seed, sigma=0.15, fov_scale=0.05)
+    t1, t2, info = solvers.solve_pnk(*_args(p), tol=1e-12, ccd=True)
+    assert info.converged and not np.any(t1)
+    h = ccsd.core_hamiltonian(p.fock(), p.L, o)
+    r1b, r2b, eb = brute.brute_force(h, _eri(p.L), o, t1, t2)
+    assert np.abs(r2b).max() < 1e-11
+    assert np.abs(r1b).max() > 1e-6
+    assert abs(eb - info.e_corr) < 1e-12
+
+
+def test_ink_is_the_fixed_point_iteration_in_the_canonical_gauge():
+    """With a diagonal Fock matrix A_F is the diagonal of orbital-energy
+    differences, so INK (A_F dt = -r) takes the same steps as plain FP
+    (t <- t - r / D, no DIIS, no shift), from the same MP2 start."""
+    p = make_problem(3, 8, 16, 96, gauge="canonical")
+    _, _, ink = solvers.solve_ink(*_args(p), tol=1e-9)
+    _, _, fp = solvers.solve_fp_diis(*_args(p), tol=1e-9, diis_size=0)
+    assert ink.converged and fp.converged
+    assert ink.n_residual == fp.n_residual
+    assert abs(ink.e_corr - fp.e_corr) < 1e-12
+    hi = np.array([h[2] for h in ink.history])
+    hf = np.array([h[2] for h in fp.history])
+    assert np.allclose(hi, hf, rtol=1e-6, atol=0)  # GMRES to 1e-12 vs an exact division
+
+
+@pytest.mark.parametrize("ccd", [False, True])
+def test_protocols_reach_one_root_in_a_rotated_gauge(ccd):
+    """NK, PNK, INK and SFP+DIIS (the method table) land on the same
+    amplitudes and energy at the CCSD and at the CCD level; INK and NK are
+    gauge invariant, so INK's history is that of the canonical problem."""
+    p = make_problem(3, 7, 14, 97, gauge="haar")
+    runs = {
+        "pnk": solvers.solve_pnk(*_args(p), tol=1e-10, ccd=ccd),
+        "nk": solvers.solve_pnk(*_args(p), tol=1e-10, precond=False, ccd=ccd, max_newton=200),
+        "ink": solvers.solve_ink(*_args(p), tol=1e-10, ccd=ccd),
+        "sfp": solvers.solve_fp_diis(*_args(p), tol=1e-10, level_shift=0.2, ccd=ccd),
+    }
+    ref1, ref2, ref = runs["pnk"]
+    for name, (t1, t2, info) in runs.items():
+        assert info.converged, name
+        assert abs(info.e_corr - ref.e_corr) < 1e-9, name
+        assert np.abs(t2 - ref2).max() < 1e-8 and np.abs(t1 - ref1).max() < 1e-8, name
+    pc = make_problem(3, 7, 14, 97, gauge="canonical")
+    _, _, inkc = solvers.solve_ink(*_args(pc), tol=1e-10, ccd=ccd)
+    assert inkc.n_residual == runs["ink"][2].n_residual
+    assert abs(inkc.e_corr - ref.e_corr) < 1e-9
+
+
 # ---------------------------------------------------------- constants ----
 def test_paper_constants():
     with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
