@@ -366,13 +366,53 @@ def bench_protocols(args):
     h.close()
 
 
+def bench_levelshift(args):
+    """The regularization study: at the PNK root of C1 (canonical) and C2
+    (Haar-rotated), the spectral radius of the (S)FP map's Jacobian for a
+    range of level shifts (30 Arnoldi steps from a seeded pair-symmetric
+    start), and what SFP does from the MP2 start at each shift (without
+    DIIS and with DIIS(8)). One JSON line."""
+    import torch
+
+    import paper_2608_06669_amd as pk
+    from gen import make_config, random_amplitudes
+
+    pk.load()
+    h = pk.Handle(0)
+    shifts = [0.0, 0.1, 0.25, 0.5, 1.0, 2.0]
+    out = {"workload": "level-shift study at the PNK root (c1_canonical, c2_haar)", "m": 30, "shifts": shifts,
+           "configs": []}
+    for cfg in ("c1_canonical", "c2_haar"):
+        p = make_config(cfg)
+        tol = p.meta["tol"]
+        P = pk.DeviceProblem.from_problem(p)
+        t1, t2, info = h.solve_pnk(P, tol_inf=tol, max_newton=args.max_newton)
+        q1, q2 = (torch.as_tensor(a, device="cuda") for a in random_amplitudes(p.nocc, p.nvir, 4242, scale=1.0))
+        rec = {"config": cfg, "pnk_converged": info["status"] == "CC_OK", "e_corr": info["e_corr"], "rho": [],
+               "sfp": [], "sfp_diis": []}
+        for s in shifts:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            rho, _ = h.fp_spectral_radius(P, t1, t2, q1, q2, shift=s, m=30)
+            rec["rho"].append({"shift": s, "rho": rho, "seconds": time.perf_counter() - t0})
+            for key, nd in (("sfp", 0), ("sfp_diis", 8)):
+                _, _, fi = h.solve_fp_diis(P, tol_inf=tol, level_shift=s, diis_size=nd, max_iter=200)
+                rec[key].append({"shift": s, "converged": fi["status"] == "CC_OK", "n_residual": fi["n_residual"],
+                                 "res_inf": fi["res_inf"]})
+            print(f"{cfg} shift {s}: rho {rho:.4f} sfp {rec['sfp'][-1]} sfp+diis {rec['sfp_diis'][-1]}",
+                  file=sys.stderr, flush=True)
+        out["configs"].append(rec)
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner", "protocols"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner", "protocols", "levelshift"],
                     help="default: the bench line; the others print their own measurement line")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"], help="J v precision (c3/c4)")
     ap.add_argument("--max-newton", type=int, default=200)
@@ -393,6 +433,8 @@ def main():
         bench_inner(args)
     elif args.workload == "protocols":
         bench_protocols(args)
+    elif args.workload == "levelshift":
+        bench_levelshift(args)
     else:
         bench_large(args)
 

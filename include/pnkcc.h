@@ -221,6 +221,22 @@ cc_status cc_solve_pnk(cc_handle* h, const cc_problem* p, const cc_pnk_opts* opt
 cc_status cc_solve_fp_diis(cc_handle* h, const cc_problem* p, const cc_fp_opts* opts, double* t1, double* t2,
                            cc_info* info, void* stream);
 
+/* Spectral radius of the Jacobian of the (S)FP map t -> t - r(t) / (D +
+ * shift), G = I - diag(D + shift)^-1 J(t), with D the Jacobi denominators of
+ * the diagonal of f in the given gauge (Section "Regularization": FP
+ * converges locally when this radius is below one; the shift is the Ridge
+ * term of Appendix D). J is linearised at (t1, t2) (device). G acts on
+ * pair-symmetric vectors: m Arnoldi steps (CGS2) from the start vector (q1,
+ * q2) (device, nonzero, pair-symmetric), the projection (x2[i][j] +
+ * x2[j][i]^T) / 2 after every product. rho_out (host) receives the largest
+ * modulus of the Ritz values; ritz_re / ritz_im (host, m entries each, may
+ * be NULL) the Ritz values, n_ritz (may be NULL) their number (less than m
+ * when the Krylov space became invariant). CC_ERR_ARG for a zero start or
+ * m outside 1..200. Synchronises. */
+cc_status cc_fp_spectral_radius(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, const double* q1,
+                                const double* q2, double shift, int m, double* rho_out, double* ritz_re,
+                                double* ritz_im, int* n_ritz, void* stream);
+
 /* Residual history of the last solve on the handle: pairs (||r||_2,
  * ||r||_inf) per outer residual evaluation, up to max_pairs written to
  * `pairs` (host, 2 * max_pairs doubles); returns the number available. */
@@ -284,6 +300,12 @@ void cc_server_destroy(cc_server* s);
  * of one slot. */
 cc_status cc_diag_timing(cc_handle* h, int enable);
 cc_status cc_diag_timing_read(cc_handle* h, int slot, int* count, double* total_ms);
+
+/* Eigenvalues of an m x m real upper Hessenberg matrix H (host, row-major;
+ * entries below the subdiagonal ignored) into re[m], im[m] (host), by the
+ * shifted QR iteration the spectral-radius call uses (host code, no GPU).
+ * CC_NOT_CONVERGED if the iteration stalls. */
+cc_status cc_diag_hessenberg_eigenvalues(int m, const double* H, double* re, double* im);
 
 cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_t a_k, const double* B,
                        int64_t b_k, int64_t b_n, double* C, int64_t c_m, int64_t c_n, double alpha, double beta,

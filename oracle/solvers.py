@@ -436,3 +436,49 @@ def solve_ink(f_oo, f_ov, f_vv, L, tol=1e-8, max_iter=200, inner_rtol=1e-12,
     info.seconds = time.perf_counter() - t_start
     t1, t2 = unpack(x, P.o, P.v)
     return t1.copy(), t2.copy(), info
+
+
+def pair_symmetrize(x, o, v):
+    """Orthogonal projection onto pair-symmetric vectors: doubles
+    (x_ij^ab + x_ji^ba) / 2, singles unchanged."""
+    x1, x2 = unpack(x, o, v)
+    return pack(x1, 0.5 * (x2 + np.transpose(x2, (1, 0, 3, 2))))
+
+
+def fp_jacobian_spectral_radius(f_oo, f_ov, f_vv, L, t1, t2, shift=0.0, m=30, seed=0, ccd=False, q0=None):
+    """Spectral radius of the Jacobian G = I - diag(D + shift)^-1 J(t) of the
+    (S)FP map t -> t - r(t) / (D + shift) at t, with D the Jacobi
+    denominators of the current gauge (Section "Regularization" ties FP's
+    convergence to this radius being below one; Appendix D, the shift as a
+    Ridge term). G acts on pair-symmetric vectors (the amplitude space; the
+    projection is applied after every product). Arnoldi with modified
+    Gram-Schmidt for m steps from q0 (projected), else a seeded
+    pair-symmetric start; returns the
+    largest modulus of the Ritz values (exact once the Krylov space is
+    invariant) and the Ritz values."""
+    P = _Problem(f_oo, f_ov, f_vv, L, ccd)
+    o, v = P.o, P.v
+    x = pack(t1, t2)
+    d1, d2 = jacobi_denominators(f_oo, f_vv, shift)
+    D = pack(d1, d2)
+    if q0 is None:
+        q0 = np.random.default_rng(seed).standard_normal(x.size)
+    q = P.mask(pair_symmetrize(np.asarray(q0, dtype=float), o, v))
+    Q = [q / np.linalg.norm(q)]
+    H = np.zeros((m + 1, m))
+    k = 0
+    for k in range(m):
+        w = Q[k] - P.jvp(x, Q[k]) / D
+        w = P.mask(pair_symmetrize(w, o, v))
+        for i in range(k + 1):
+            H[i, k] = np.dot(Q[i], w)
+            w = w - H[i, k] * Q[i]
+        H[k + 1, k] = np.linalg.norm(w)
+        if H[k + 1, k] <= 1e-12 * max(1.0, abs(H[k, k])):
+            k += 1
+            break
+        Q.append(w / H[k + 1, k])
+    else:
+        k = m
+    ritz = np.linalg.eigvals(H[:k, :k])
+    return float(np.max(np.abs(ritz))), ritz

@@ -86,6 +86,9 @@ SIGNATURES = {
     "cc_fock_apply": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, P]),
     "cc_precond_solve": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, D, I, ctypes.POINTER(I), P]),
     "cc_precond_solve_pairsym": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, D, I, ctypes.POINTER(I), P]),
+    "cc_fp_spectral_radius": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, D, I, ctypes.POINTER(D), P, P,
+                                  ctypes.POINTER(I), P]),
+    "cc_diag_hessenberg_eigenvalues": (I, [I, P, P, P]),
     "cc_pnk_opts_default": (None, [ctypes.POINTER(cc_pnk_opts)]),
     "cc_fp_opts_default": (None, [ctypes.POINTER(cc_fp_opts)]),
     "cc_solve_pnk": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_pnk_opts), P, P,

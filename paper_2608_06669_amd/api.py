@@ -169,6 +169,18 @@ class Handle:
                          ok=(L.CC_OK, L.CC_NOT_CONVERGED, L.CC_ERR_NAN))
         return t1, t2, dict(info.as_dict(), status=L.STATUS_NAMES[st])
 
+    def fp_spectral_radius(self, p: DeviceProblem, t1, t2, q1, q2, shift=0.0, m=30, stream=None):
+        """Spectral radius of the (S)FP map's Jacobian at (t1, t2) by m Arnoldi
+        steps from (q1, q2); returns (rho, Ritz values as a complex array)."""
+        rho = ctypes.c_double(0.0)
+        nr = ctypes.c_int(0)
+        re = np.zeros(m)
+        im = np.zeros(m)
+        self._check(_lib().cc_fp_spectral_radius(self._h, ctypes.byref(p.struct), _ptr(t1), _ptr(t2), _ptr(q1),
+                                                 _ptr(q2), float(shift), int(m), ctypes.byref(rho),
+                                                 re.ctypes.data, im.ctypes.data, ctypes.byref(nr), _stream(stream)))
+        return rho.value, (re + 1j * im)[: nr.value]
+
     def timing(self, enable: bool = True):
         self._check(_lib().cc_diag_timing(self._h, 1 if enable else 0))
 
@@ -194,6 +206,19 @@ def diag_gemm(A, B, C, a_strides, b_strides, c_strides, M, N, K, alpha=1.0, beta
     if st != L.CC_OK:
         raise CCError(st, "cc_diag_gemm failed")
     return C
+
+
+def hessenberg_eigenvalues(H) -> np.ndarray:
+    """Eigenvalues of a real upper Hessenberg matrix by the library's host
+    QR iteration (cc_diag_hessenberg_eigenvalues; no GPU needed)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    m = H.shape[0]
+    re = np.zeros(m)
+    im = np.zeros(m)
+    st = _lib().cc_diag_hessenberg_eigenvalues(m, H.ctypes.data, re.ctypes.data, im.ctypes.data)
+    if st != L.CC_OK:
+        raise CCError(st, "cc_diag_hessenberg_eigenvalues failed")
+    return re + 1j * im
 
 
 def workspace_bytes(nocc, nvir, naux, lowp_flags=0, m_max=20, inner_restart=30, diis_size=0) -> int:

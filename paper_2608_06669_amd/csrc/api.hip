@@ -5,9 +5,11 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <vector>
 
 #include "../../include/pnkcc.h"
 #include "api_internal.hpp"
+#include "eig.hpp"
 #include "gemm.hpp"
 #include "tensor_ops.hpp"
 
@@ -330,6 +332,29 @@ cc_status cc_precond_solve_pairsym(cc_handle* h, const cc_problem* p, const doub
   return precond_solve_impl(h, p, b1, b2, x1, x2, rtol, maxit, iters_out, stream, true);
 }
 
+cc_status cc_fp_spectral_radius(cc_handle* h, const cc_problem* p, const double* t1, const double* t2, const double* q1,
+                                const double* q2, double shift, int m, double* rho_out, double* ritz_re,
+                                double* ritz_im, int* n_ritz, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(t1 && t2 && q1 && q2 && rho_out, "array arguments must not be NULL");
+  PNK_REQUIRE(m >= 1 && m <= 200, "m must be in 1..200");
+  PNK_REQUIRE(std::isfinite(shift), "shift must be finite");
+  H->ensure(p, 0, m, 1, 0, s);
+  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
+  pack(ov, n2, t1, t2, H->xa, s);
+  pack(ov, n2, q1, q2, H->xb, s);
+  std::vector<double> re, im;
+  *rho_out = H->sol->fp_spectral_radius(H->xa, H->xb, shift, m, s, &re, &im);
+  for (size_t i = 0; i < re.size(); ++i) {
+    if (ritz_re) ritz_re[i] = re[i];
+    if (ritz_im) ritz_im[i] = im[i];
+  }
+  if (n_ritz) *n_ritz = (int)re.size();
+  return CC_OK;
+  PNK_API_END
+}
+
 static void fill_info(const SolveStats& st, cc_info* info) {
   if (!info) return;
   info->e_corr = st.e_corr;
@@ -433,6 +458,11 @@ cc_status cc_diag_timing_read(cc_handle* h, int slot, int* count, double* total_
   H->timers->read(slot, count, total_ms);
   return CC_OK;
   PNK_API_END
+}
+
+cc_status cc_diag_hessenberg_eigenvalues(int m, const double* H, double* re, double* im) {
+  if (m < 1 || !H || !re || !im) return CC_ERR_ARG;
+  return hessenberg_eigenvalues(H, m, re, im) ? CC_OK : CC_NOT_CONVERGED;
 }
 
 cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_t a_k, const double* B,

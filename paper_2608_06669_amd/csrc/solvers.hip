@@ -15,6 +15,7 @@
 
 #include "solvers.hpp"
 #include "block_sum.hpp"
+#include "eig.hpp"
 #include "fock_op.hpp"
 
 #include <chrono>
@@ -936,6 +937,59 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   read_scalars(host_, dsc_, 1, s);
   st->e_corr = host_[0];
   st->seconds = now_s() - t0;
+}
+
+// The FP map t -> t - r(t) / (D + s) has the Jacobian G = I - diag(D +
+// s)^-1 J(t); its spectral radius below one is what makes (S)FP converge
+// locally (Section "Regularization"; the shift is the Ridge term of
+// Appendix D). Arnoldi with CGS2 on pair-symmetric vectors (the projection
+// (x2 + x2^T over pairs) / 2 follows every product), Ritz values of the
+// Hessenberg matrix on the host.
+double Solver::fp_spectral_radius(const double* t, const double* q0, double shift, int m, hipStream_t s,
+                                  std::vector<double>* ritz_re, std::vector<double>* ritz_im) {
+  PNK_REQUIRE(m >= 1 && m <= m_max_, "fp_spectral_radius: m exceeds the allocated basis");
+  const int64_t n = n_;
+  const int o = eng_.o(), vir = eng_.v();
+  const int64_t ov = (int64_t)o * vir;
+  eng_.residual(t, t + ov, r_, r_ + ov, s);  // linearise at t
+  double qinf, qn;
+  norms(q0, &qinf, &qn, s);
+  PNK_REQUIRE(qn > 0.0 && std::isfinite(qn), "fp_spectral_radius: the start vector is zero or not finite");
+  scale_by_inverse(n, q0, dsc_ + 1, Qo_, s);
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), h;
+  int k_done = 0;
+  for (int k = 0; k < m; ++k) {
+    double* q = Qo_ + (size_t)k * n;
+    double* wv = Qo_ + (size_t)(k + 1) * n;
+    eng_.jvp(q, q + ov, w_, w_ + ov, Prec::F64, s);
+    copy(n, q, w2_, s);
+    jacobi_update(o, vir, eng_.f_oo(), eng_.f_vv(), shift, w_, w2_, nullptr, s);  // q - J q / (D + s)
+    copy(ov, w2_, wv, s);
+    fill(n - ov, 0.0, wv + ov, s);
+    pair_symmetrize_add(o, vir, w2_ + ov, 0.5, wv + ov, s);
+    const double hn = orthogonalise(Qo_, n, k + 1, wv, h, s);
+    for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = h[i];
+    k_done = k + 1;
+    if (!std::isfinite(hn)) break;
+    double hmax = 0.0;
+    for (int i = 0; i <= k; ++i) hmax = std::max(hmax, std::fabs(h[i]));
+    if (hn <= 1e-12 * std::max(1.0, hmax)) break;  // invariant subspace
+    if (k + 1 < m) {
+      H[(size_t)(k + 1) * m + k] = hn;
+      scale_by_inverse(n, wv, dsc_ + 2 * kMaxBasis, wv, s);
+    }
+  }
+  // the leading k_done x k_done block, row-major
+  std::vector<double> Hk((size_t)k_done * k_done), re(k_done), im(k_done);
+  for (int i = 0; i < k_done; ++i)
+    for (int j = 0; j < k_done; ++j) Hk[(size_t)i * k_done + j] = H[(size_t)i * m + j];
+  PNK_REQUIRE(hessenberg_eigenvalues(Hk.data(), k_done, re.data(), im.data()),
+              "fp_spectral_radius: the Hessenberg eigenvalue iteration did not converge");
+  double rho = 0.0;
+  for (int i = 0; i < k_done; ++i) rho = std::max(rho, std::hypot(re[i], im[i]));
+  if (ritz_re) *ritz_re = re;
+  if (ritz_im) *ritz_im = im;
+  return rho;
 }
 
 namespace {

@@ -65,6 +65,13 @@ class Solver {
   // (it solves for the pair-symmetric part of b).
   int precond_solve(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s,
                     bool* converged = nullptr, bool pair_symmetric = false);
+  // Spectral radius of the Jacobian of the (S)FP map, G = I - diag(D +
+  // shift)^-1 J(t), on pair-symmetric vectors: m Arnoldi steps from q0
+  // (device, packed, pair-symmetric, nonzero) with the Jacobian linearised
+  // at t (device, packed); m <= the basis allocated for PNK. Returns the
+  // largest Ritz modulus and the Ritz values (host).
+  double fp_spectral_radius(const double* t, const double* q0, double shift, int m, hipStream_t s,
+                            std::vector<double>* ritz_re, std::vector<double>* ritz_im);
   // Symmetric A_F (f_ov = 0): device-resident Lanczos form of GMRES, on
   // the full or the packed pair layout.
   int precond_solve_sym(const double* b, double* x, double rtol, int maxit, hipStream_t s, bool* converged,

@@ -65,3 +65,28 @@ def test_null_arguments_are_rejected_without_a_device():
     assert lib.cc_create(None, 0, 0) == _lib.CC_ERR_ARG
     assert lib.cc_server_submit(None, None, None, None) == _lib.CC_ERR_ARG
     assert lib.cc_diag_gemm(0, 1, 1, None, 0, 0, None, 0, 0, None, 0, 0, 1.0, 0.0, 0, None) == _lib.CC_ERR_ARG
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_host_hessenberg_eigenvalues_match_numpy():
+    """The host QR iteration behind cc_fp_spectral_radius (runs without a
+    GPU) against numpy's eigenvalues: random Hessenberg matrices with real
+    and complex spectra, a rotation with a purely imaginary pair, a zero
+    matrix, a 1 x 1 case and a Jordan-like block."""
+    import numpy as np
+
+    import paper_2608_06669_amd as pk
+    rng = np.random.default_rng(7)
+    cases = [np.triu(rng.standard_normal((m, m)), -1) for m in (2, 3, 5, 12, 30, 60)]
+    cases.append(np.array([[0.0, 1.0], [-1.0, 0.0]]))
+    cases.append(np.zeros((4, 4)))
+    cases.append(np.array([[2.5]]))
+    cases.append(np.diag(np.full(5, 0.3)) + np.diag(np.ones(4), 1) + np.diag(np.full(4, 1e-3), -1))
+    for H in cases:
+        got = pk.hessenberg_eigenvalues(H)
+        ref = np.linalg.eigvals(H)
+        scale = max(1.0, np.abs(H).max())
+        # match each reference eigenvalue to its nearest computed one
+        for lam in ref:
+            assert np.min(np.abs(got - lam)) < 1e-9 * scale * H.shape[0], (H.shape, lam)
+        assert abs(np.max(np.abs(got)) - np.max(np.abs(ref))) < 1e-9 * scale * H.shape[0]

@@ -328,3 +328,60 @@ def test_paper_constants():
     lam = np.linalg.eigvalsh(M)
     assert abs(M[0, 0] - M[1, 1]) == pytest.approx(g["conclusion_diag_gap"], abs=1e-12)
     assert abs(lam[1] - lam[0]) == pytest.approx(g["conclusion_spectral_gap_approx"], rel=1e-3)
+
+
+# ------------------------------------------------------- level shift -----
+def _dense_fp_jacobian_sym(p, t1, t2, shift):
+    """G = I - diag(D + s)^-1 J on pair-symmetric vectors, built column by
+    column from complex-step products on an orthonormal basis of that space."""
+    o, v = p.nocc, p.nvir
+    n = o * v + o * o * v * v
+    cols = []
+    for k in range(n):
+        e = np.zeros(n)
+        e[k] = 1.0
+        s = solvers.pair_symmetrize(e, o, v)
+        if np.linalg.norm(s) > 0:
+            cols.append(s)
+    U, sv, _ = np.linalg.svd(np.array(cols).T, full_matrices=False)
+    rank = int(np.sum(sv > 1e-10 * sv[0]))
+    B = U[:, :rank]  # orthonormal basis of the pair-symmetric space
+    d1, d2 = solvers.jacobi_denominators(p.f_oo, p.f_vv, shift)
+    D = solvers.pack(d1, d2)
+    G = np.zeros((rank, rank))
+    for c in range(rank):
+        q1, q2 = solvers.unpack(B[:, c], o, v)
+        j1, j2 = ccsd.jvp_complex_step(*_args(p), t1, t2, q1, q2)
+        G[:, c] = B.T @ (B[:, c] - solvers.pack(j1, j2) / D)
+    return G
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_fp_spectral_radius_equals_the_dense_jacobian(shift):
+    """Arnoldi over the whole pair-symmetric space finds the eigenvalues of
+    the dense FP Jacobian built from unit-vector products."""
+    p = make_problem(2, 3, 6, 98, gauge="haar")
+    t1, t2, info = solvers.solve_pnk(*_args(p), tol=1e-10)
+    assert info.converged
+    G = _dense_fp_jacobian_sym(p, t1, t2, shift)
+    rho_dense = np.max(np.abs(np.linalg.eigvals(G)))
+    rho, _ = solvers.fp_jacobian_spectral_radius(*_args(p), t1, t2, shift=shift, m=G.shape[0])
+    assert abs(rho - rho_dense) < 1e-9 * max(1.0, rho_dense)
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_fp_contraction_rate_is_the_spectral_radius(shift):
+    """The FP Jacobian at the root decides (S)FP's local behaviour: started
+    close to the root, plain shifted FP (no DIIS) contracts by a factor that
+    tends to the spectral radius; the last step's ratio matches it. A shift
+    where none is needed raises the radius (slower steps)."""
+    p = make_problem(3, 8, 16, 99, gauge="canonical")
+    t1, t2, info = solvers.solve_pnk(*_args(p), tol=1e-11)
+    rho, _ = solvers.fp_jacobian_spectral_radius(*_args(p), t1, t2, shift=shift, m=60)
+    rho0, _ = solvers.fp_jacobian_spectral_radius(*_args(p), t1, t2, shift=0.0, m=60)
+    assert rho < 1.0 and (shift == 0.0 or rho > rho0)
+    x0 = solvers.pack(t1, t2) + 1e-4 * solvers.pair_symmetrize(
+        np.random.default_rng(5).standard_normal(3 * 8 + 9 * 64), 3, 8)
+    _, _, fp = solvers.solve_fp_diis(*_args(p), tol=1e-13, diis_size=0, level_shift=shift, x0=x0, max_iter=400)
+    h = np.array([r[1] for r in fp.history])
+    assert fp.converged and abs(h[-1] / h[-2] - rho) < 0.02
