@@ -177,6 +177,244 @@ __device__ inline void singles_part(int o, int v, const double* __restrict__ f_o
   }
 }
 
+// ---- packed Lanczos step, virtual part fused with the previous update ----
+struct VirLzArgs {
+  int v, tiles_m, tiles, units, per_xcd, vec, npair, nsw;  // nsw: workgroups for the singles
+  int64_t ov;
+  const double* f_vv;
+  const double* P;  // p_{k-1} (raw product of the last step)
+  const double* V;  // v_{k-1}
+  double* Vn;       // v_k (out)
+  double* Y;        // virtual part of A_F v_k (out, doubles)
+  double* w1;       // w_{k-2}
+  double* w2;       // w_{k-3}, overwritten with w_{k-1}
+  double* x;        // MINRES iterate
+  const double* partials;  // shares of <v,p>, <p,p>, <v,v> from the last occupied launch
+  int nparts;
+  const double* st;  // state after step k-1
+  double* stn;       // state after step k (written by workgroup 0)
+  double* fin;
+};
+
+// Step k of the packed symmetric solve, first launch. Every workgroup sums
+// the shares of the last occupied launch (fixed order) into alpha_{k-1} =
+// <v,p>/<v,v> and beta_k = ||p - alpha v|| and takes step k-1's Givens
+// rotation of the tridiagonal QR and the stopping test (the work of a
+// separate update launch). Each workgroup then writes, for the elements of
+// its own output tile (or, for the trailing workgroups, of the singles),
+// v_k = (p - alpha v_{k-1}) / beta_k and the MINRES updates w_{k-1} =
+// (v_{k-1} - delta w_{k-2} - eps w_{k-3}) / rho, x += phi w_{k-1}; and
+// forms y_k = f_vv v_k + v_k f_vv for its tile with v_k built while the
+// panels load. The first step of a solve (flag in the state) only
+// normalises: p is the start vector, v_{-1} is zero and the shares are
+// (0, ||p||^2, 0). A step whose test holds skips the matrix product.
+template <int BM, int WGM, int BK>
+__global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
+  using Mma = MmaF64;
+  constexpr int BN = BM;
+  constexpr int WGN = 4 / WGM;
+  constexpr int WTM = BM / WGM, WTN = BN / WGN;
+  constexpr int TMI = WTM / Mma::TM, TNI = WTN / Mma::TN;
+  constexpr int ALDS = lds_elems<Mma, BM, BK>();
+  constexpr int BLDS = lds_elems<Mma, BN, BK>();
+  __shared__ __attribute__((aligned(16))) double As[2][ALDS];
+  __shared__ __attribute__((aligned(16))) double Bs[2][BLDS];
+  __shared__ double red[3][4];
+
+  const int tid = threadIdx.x;
+  if (p.st[kLzDone] != 0.0) {
+    if (blockIdx.x == 0 && tid == 0) p.stn[kLzDone] = 1.0;
+    return;
+  }
+  const int dwg = 8 * p.per_xcd;
+  const int u = (int)(blockIdx.x % 8) * p.per_xcd + (int)(blockIdx.x / 8);
+  if ((int)blockIdx.x < dwg && u >= p.units) return;  // padding of the XCD grouping
+
+  // The elements this workgroup updates: its own output tile, or for the
+  // trailing workgroups 1024 singles. Their loads are issued before the
+  // scalars are formed, so both latencies overlap.
+  constexpr int EPT = (BM * BN + 255) / 256;
+  static_assert(EPT >= 4, "the singles workgroups need four elements per thread");
+  const int v = p.v;
+  const int64_t vv = (int64_t)v * v;
+  const bool singles_wg = (int)blockIdx.x >= dwg;
+  const int pair = singles_wg ? 0 : u / p.tiles, tile = singles_wg ? 0 : u % p.tiles;
+  const int m0 = (tile % p.tiles_m) * BM;
+  const int n0 = (tile / p.tiles_m) * BN;
+  const int64_t off = p.ov + (int64_t)pair * vv;
+  const double* __restrict__ gP = p.P;
+  const double* __restrict__ gV = p.V;
+  const double* __restrict__ gW1 = p.w1;
+  double* __restrict__ gW2 = p.w2;
+  double* __restrict__ gX = p.x;
+  double* __restrict__ gVn = p.Vn;
+  int64_t idx[EPT];
+  double ep[EPT], ev[EPT], e1[EPT], e2[EPT], ex[EPT];
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int q = tid + 256 * j;
+    idx[j] = -1;
+    if (singles_wg) {
+      const int64_t e = (int64_t)(blockIdx.x - dwg) * 1024 + q;
+      if (q < 1024 && e < p.ov) idx[j] = e;
+    } else {
+      const int gm = m0 + q / BN, gn = n0 + q % BN;
+      if (q < BM * BN && gm < v && gn < v) idx[j] = off + (int64_t)gm * v + gn;
+    }
+    ep[j] = ev[j] = e1[j] = e2[j] = ex[j] = 0.0;
+    if (idx[j] >= 0) {
+      ep[j] = gP[idx[j]];
+      ev[j] = gV[idx[j]];
+      e1[j] = gW1[idx[j]];
+      e2[j] = gW2[idx[j]];
+      ex[j] = gX[idx[j]];
+    }
+  }
+
+  // scalars (every workgroup, same bits)
+  double r3[3] = {0.0, 0.0, 0.0};
+  for (int k = tid; k < p.nparts; k += 256) {
+    r3[0] += p.partials[k];
+    r3[1] += p.partials[p.nparts + k];
+    r3[2] += p.partials[2 * p.nparts + k];
+  }
+  block_sum256<3>(r3, red);
+  const double vp = r3[0], pp = r3[1], vnorm2 = r3[2];
+  const double alpha = vnorm2 > 0.0 ? vp / vnorm2 : 0.0;
+  const double betan = sqrt(fmax(pp - alpha * vp, 0.0));
+  const double invb = betan != 0.0 ? 1.0 / betan : 0.0;
+  const bool first = p.st[kLzFirst] != 0.0;
+  double delta = 0.0, eps = 0.0, ir = 0.0, phi = 0.0;
+  bool done_now;
+  if (first) {
+    done_now = !(betan > p.fin[kLzFinTol]) || betan == 0.0;
+    if (blockIdx.x == 0 && tid == 0) {
+      for (int q = 0; q < kLzNState; ++q) p.stn[q] = 0.0;
+      p.stn[kLzBeta] = betan;
+      p.stn[kLzC2] = 1.0;
+      p.stn[kLzC1] = 1.0;
+      p.stn[kLzPhiBar] = betan;
+      p.stn[kLzRes] = betan;
+      p.stn[kLzDone] = done_now ? 1.0 : 0.0;
+      p.fin[kLzFinRes] = betan;
+      p.fin[kLzFinBeta] = betan;
+    }
+  } else {
+    const double beta = p.st[kLzBeta];
+    const double c2 = p.st[kLzC2], s2 = p.st[kLzS2], c1 = p.st[kLzC1], s1 = p.st[kLzS1];
+    eps = s2 * beta;
+    const double dbar = c2 * beta;
+    delta = c1 * dbar + s1 * alpha;
+    const double gbar = -s1 * dbar + c1 * alpha;
+    const double rho1 = hypot(gbar, betan);
+    const double c = rho1 != 0.0 ? gbar / rho1 : 1.0;
+    const double s = rho1 != 0.0 ? betan / rho1 : 0.0;
+    const double phibar = p.st[kLzPhiBar];
+    phi = c * phibar;
+    ir = rho1 != 0.0 ? 1.0 / rho1 : 0.0;
+    const double res = fabs(s * phibar);
+    done_now = res <= p.fin[kLzFinTol] || betan == 0.0;
+    if (blockIdx.x == 0 && tid == 0) {
+      p.stn[kLzBeta] = betan;
+      p.stn[kLzAlpha] = alpha;
+      p.stn[kLzBetaN] = betan;
+      p.stn[kLzC2] = c1; p.stn[kLzS2] = s1;
+      p.stn[kLzC1] = c; p.stn[kLzS1] = s;
+      p.stn[kLzPhiBar] = -s * phibar;
+      p.stn[kLzRho1] = rho1;
+      p.stn[kLzDelta] = delta;
+      p.stn[kLzEps] = eps;
+      p.stn[kLzPhi] = phi;
+      p.stn[kLzRes] = res;
+      p.stn[kLzInvB] = invb;
+      p.stn[kLzDone] = done_now ? 1.0 : 0.0;
+      p.stn[kLzFirst] = 0.0;
+      p.fin[kLzFinSteps] += 1.0;
+      p.fin[kLzFinRes] = res;
+      p.fin[kLzFinBeta] = betan;
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    if (idx[j] < 0) continue;
+    gVn[idx[j]] = (ep[j] - alpha * ev[j]) * invb;
+    if (!first) {
+      const double w = (ev[j] - delta * e1[j] - eps * e2[j]) * ir;
+      gW2[idx[j]] = w;
+      gX[idx[j]] = ex[j] + phi * w;
+    }
+  }
+  if (singles_wg) return;
+  if (done_now) return;  // converged: y_k is not needed
+
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave / WGN, wn = wave % WGN;
+  const double* __restrict__ Xp = p.P + off;
+  const double* __restrict__ Xv = p.V + off;
+  const double* __restrict__ F = p.f_vv;
+  const bool vec = p.vec != 0;
+  const int nkp = (v + BK - 1) / BK;
+  const int nk = 2 * nkp;
+  double acc[TMI][TNI];
+#pragma unroll
+  for (int a = 0; a < TMI; ++a)
+#pragma unroll
+    for (int b = 0; b < TNI; ++b) acc[a][b] = 0.0;
+  // phase 0: F[a][c] x v_k[c][b]; phase 1: v_k[a][c] x F[c][b]; the v_k
+  // panel is (p - alpha v) / beta of the two loaded panels
+  Panel<Mma, double, BM, BK, true> pa;
+  Panel<Mma, double, BN, BK, false> pb;
+  auto load = [&](int t) {
+    if (t >= nkp) {
+      const int k0 = (t - nkp) * BK;
+      pa.load_diff(Xp, Xv, alpha, invb, v, 1, m0, v, k0, v, vec, tid);
+      pb.load(F, 1, v, n0, v, k0, v, vec, tid);
+    } else {
+      const int k0 = t * BK;
+      pa.load(F, v, 1, m0, v, k0, v, vec, tid);
+      pb.load_diff(Xp, Xv, alpha, invb, 1, v, n0, v, k0, v, vec, tid);
+    }
+  };
+  load(0);
+  pa.store(As[0], tid);
+  pb.store(Bs[0], tid);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    if (kt + 1 < nk) load(kt + 1);
+    const double* Ac = As[cur];
+    const double* Bc = Bs[cur];
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += Mma::KSTEP) {
+      const int kk = ks + (lane >> 4);
+      double af[TMI], bf[TNI];
+#pragma unroll
+      for (int a = 0; a < TMI; ++a) af[a] = Ac[kk * (BM + kPad) + wm * WTM + a * 4 + (lane & 3)];
+#pragma unroll
+      for (int b = 0; b < TNI; ++b) bf[b] = Bc[kk * (BN + kPad) + wn * WTN + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < TMI; ++a)
+#pragma unroll
+        for (int b = 0; b < TNI; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) {
+      pa.store(As[cur ^ 1], tid);
+      pb.store(Bs[cur ^ 1], tid);
+    }
+    __syncthreads();
+  }
+  double* __restrict__ Yo = p.Y + off;
+#pragma unroll
+  for (int a = 0; a < TMI; ++a)
+#pragma unroll
+    for (int b = 0; b < TNI; ++b) {
+      const int ga = m0 + wm * WTM + a * 4 + (lane >> 4);
+      const int gb = n0 + wn * WTN + b * 16 + (lane & 15);
+      if (ga < v && gb < v) Yo[(int64_t)ga * v + gb] = acc[a][b];
+    }
+}
+
 // Dynamic LDS: xs[o*o][ch] then fo[o][o].
 template <bool LZ>
 __global__ __launch_bounds__(256) void fock_occ_kernel(OccArgs p) {
@@ -539,11 +777,45 @@ void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev,
   launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, singles_scale, done, s);
 }
 
-void fock_op_lanczos_vir_packed(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s) {
+void fock_op_lanczos_vir_fused(const FockOp& op, const double* P, const double* V, double* Vn, double* Y, double* w1,
+                               double* w2, double* x, const double* partials, int nparts, const double* st,
+                               double* stn, double* fin, hipStream_t s) {
   PNK_REQUIRE(op.bm > 0 && op.pt > 0, "fock_op: packed form not planned");
-  PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
-  const int64_t ov = (int64_t)op.o * op.v;
-  launch_vir(op, op.npair, v + ov, p + ov, done, s);
+  PNK_REQUIRE(Vn != P && Vn != V && Y != P && Y != V && Y != Vn, "fock_op: fused step buffers must be distinct");
+  VirLzArgs a;
+  a.v = op.v;
+  a.tiles_m = (int)ceil_div(op.v, op.bm);
+  a.tiles = op.tiles;
+  a.units = op.tiles * op.npair;
+  a.per_xcd = (int)ceil_div(a.units, 8);
+  a.npair = op.npair;
+  a.ov = (int64_t)op.o * op.v;
+  a.nsw = (int)ceil_div(a.ov, 1024);
+  a.vec = (op.v % 2 == 0 && aligned16(P) && aligned16(V) && aligned16(op.f_vv)) ? 1 : 0;
+  a.f_vv = op.f_vv;
+  a.P = P;
+  a.V = V;
+  a.Vn = Vn;
+  a.Y = Y;
+  a.w1 = w1;
+  a.w2 = w2;
+  a.x = x;
+  a.partials = partials;
+  a.nparts = nparts;
+  a.st = st;
+  a.stn = stn;
+  a.fin = fin;
+  dim3 grid((unsigned)(8 * a.per_xcd + a.nsw));
+  const bool bk32 = op.bm == 32 && ceil_div(op.v, 32) * 32 <= ceil_div(op.v, 16) * 16;
+  switch (op.bm * 2 + (bk32 ? 1 : 0)) {
+    case 64: fock_vir_lz_kernel<32, 2, 16><<<grid, 256, 0, s>>>(a); break;
+    case 65: fock_vir_lz_kernel<32, 2, 32><<<grid, 256, 0, s>>>(a); break;
+    case 96: fock_vir_lz_kernel<48, 4, 16><<<grid, 256, 0, s>>>(a); break;
+    case 97: fock_vir_lz_kernel<48, 4, 32><<<grid, 256, 0, s>>>(a); break;
+    case 128: fock_vir_lz_kernel<64, 2, 16><<<grid, 256, 0, s>>>(a); break;
+    default: fock_vir_lz_kernel<64, 2, 32><<<grid, 256, 0, s>>>(a); break;
+  }
+  PNK_CHECK_LAUNCH();
 }
 
 void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,

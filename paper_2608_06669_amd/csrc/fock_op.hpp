@@ -60,10 +60,38 @@ void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev,
 // (x2[j][i] = x2[i][j]^T): [x1 (o*v) | x2 for pairs i <= j, pair P(i, j) =
 // i o - i (i - 1) / 2 + j - i, each v*v]. The three partial sums are those
 // of the full vectors (the blocks of pairs i < j count twice); partials has
-// 3 op.nparts_packed() entries.
-void fock_op_lanczos_vir_packed(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s);
+// 3 op.nparts_packed() entries. The virtual part comes from
+// fock_op_lanczos_vir_fused below.
 void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
                                 double* partials, double singles_scale, const double* done, hipStream_t s);
+
+// State of the symmetric inner solve (device scalars, kLzStateStride
+// doubles per slot; slot j holds the state after step j's update): [0]
+// beta_j, [1] alpha, [2] beta_{j+1}, [3..6] c_{j-1}, s_{j-1}, c_j, s_j, [7]
+// phibar, [8] rho1, [9] delta, [10] eps, [11] phi, [12] |phibar| (the
+// residual estimate), [13] 1/beta, [14] done (the stopping test held), [15]
+// first (the next step only normalises the start vector). A third slot,
+// `fin`, holds what the host reads: steps run, the last residual estimate
+// and beta, the absolute tolerance, ||b|| and the start vector's norm.
+constexpr int kLzStateStride = 16;
+enum { kLzBeta = 0, kLzAlpha, kLzBetaN, kLzC2, kLzS2, kLzC1, kLzS1, kLzPhiBar, kLzRho1, kLzDelta, kLzEps, kLzPhi,
+       kLzRes, kLzInvB, kLzDone, kLzFirst, kLzNState };
+enum { kLzFinSteps = 0, kLzFinRes, kLzFinBeta, kLzFinTol, kLzFinBNorm, kLzFinBHat, kLzFinCount };
+static_assert(kLzNState <= kLzStateStride && kLzFinCount <= kLzStateStride, "Lanczos state slot too small");
+
+// Step k of the packed symmetric solve, first launch: the update of step
+// k-1 fused with the virtual part of step k. From the shares of <v,p>,
+// <p,p>, <v,v> of the last occupied launch (partials, nparts each) it
+// takes alpha_{k-1}, beta_k, the Givens rotation and the stopping test
+// (state st -> stn, fin), writes v_k = (P - alpha V) / beta_k to Vn, the
+// MINRES updates w2 = (V - delta w1 - eps w2) / rho and x += phi w2, and
+// the virtual part of A_F v_k to the doubles of Y. P, V, Vn, Y, w1, w2, x
+// are packed vectors; Vn and Y must differ from P, V and each other. With
+// the first flag set in st it only normalises (P = start vector, V = 0,
+// shares (0, ||P||^2, 0)). When st is done it passes the flag on.
+void fock_op_lanczos_vir_fused(const FockOp& op, const double* P, const double* V, double* Vn, double* Y, double* w1,
+                               double* w2, double* x, const double* partials, int nparts, const double* st,
+                               double* stn, double* fin, hipStream_t s);
 
 // True for the occupied kernel of either Lanczos form (the launch timed
 // in a recorded graph).

@@ -116,6 +116,40 @@ struct Panel {
     }
   }
 
+  // As load, of (g1 - a g2) sc elementwise (g1, g2 with the same layout).
+  __device__ inline void load_diff(const T* __restrict__ g1, const T* __restrict__ g2, T a, T sc, int64_t s_row,
+                                   int64_t s_k, int row0, int rows, int k0, int kend, bool vec_ok, int tid) {
+#pragma unroll
+    for (int e = 0; e < PER; ++e) {
+      const int q = tid + e * 256;
+      if (q >= NVEC) break;
+      int row, kk;
+      coords(q, &row, &kk);
+      const int gr = row0 + row, gk = k0 + kk;
+      bool full;
+      if (KC) full = vec_ok && gr < rows && gk + V <= kend;
+      else full = vec_ok && gr + V <= rows && gk < kend;
+      if (full) {
+        const int64_t off = (int64_t)gr * s_row + (int64_t)gk * s_k;
+        T t1[V], t2[V];
+        const uint4 u1 = *reinterpret_cast<const uint4*>(g1 + off);
+        const uint4 u2 = *reinterpret_cast<const uint4*>(g2 + off);
+        __builtin_memcpy(t1, &u1, sizeof(u1));
+        __builtin_memcpy(t2, &u2, sizeof(u2));
+#pragma unroll
+        for (int u = 0; u < V; ++u) r[e * V + u] = (t1[u] - a * t2[u]) * sc;
+      } else {
+#pragma unroll
+        for (int u = 0; u < V; ++u) {
+          const int rr = KC ? gr : gr + u;
+          const int kx = KC ? gk + u : gk;
+          const int64_t off = (int64_t)rr * s_row + (int64_t)kx * s_k;
+          r[e * V + u] = (rr < rows && kx < kend) ? (g1[off] - a * g2[off]) * sc : T(0);
+        }
+      }
+    }
+  }
+
   __device__ inline void store(L* __restrict__ lds, int tid) const {
 #pragma unroll
     for (int e = 0; e < PER; ++e) {

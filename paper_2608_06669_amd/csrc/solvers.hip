@@ -159,10 +159,13 @@ namespace {
 //        [14] done (the stopping test held at an earlier step)
 // A third, fixed slot after the two holds what the host reads: steps run,
 // the last residual estimate and beta, the absolute tolerance, ||b||.
-enum { kBeta = 0, kAlpha, kBetaN, kC2, kS2, kC1, kS1, kPhiBar, kRho1, kDelta, kEps, kPhi, kRes, kInvB, kDone, kNState };
-enum { kFinSteps = 0, kFinRes, kFinBeta, kFinTol, kFinBNorm, kFinBHat, kFinCount };
-constexpr int kStateStride = 16;
-static_assert(kNState <= kStateStride && kFinCount <= kStateStride, "Lanczos state slot too small");
+// (the layout is shared with the fused packed step in fock_op)
+constexpr int kBeta = kLzBeta, kAlpha = kLzAlpha, kBetaN = kLzBetaN, kC2 = kLzC2, kS2 = kLzS2, kC1 = kLzC1,
+              kS1 = kLzS1, kPhiBar = kLzPhiBar, kRho1 = kLzRho1, kDelta = kLzDelta, kEps = kLzEps, kPhi = kLzPhi,
+              kRes = kLzRes, kInvB = kLzInvB, kDone = kLzDone, kFirst = kLzFirst, kNState = kLzNState;
+constexpr int kFinSteps = kLzFinSteps, kFinRes = kLzFinRes, kFinBeta = kLzFinBeta, kFinTol = kLzFinTol,
+              kFinBNorm = kLzFinBNorm, kFinBHat = kLzFinBHat, kFinCount = kLzFinCount;
+constexpr int kStateStride = kLzStateStride;
 constexpr int kLzBlocks = 512;
 // With f_ov = 0, A_F is block diagonal and its doubles block is the
 // Kronecker sum of the singles block with itself (A_F, equation
@@ -399,10 +402,13 @@ __global__ __launch_bounds__(256) void lzp_unpack(int o, int v, const double* __
   }
 }
 
-// lz_init for the packed solve: the two norms from lzp_pack's partials
-// (nparts each, summed in a fixed order by one workgroup).
+// Set-up of the packed solve: the two norms from lzp_pack's partials
+// (nparts each, summed in a fixed order by one workgroup); the state before
+// step 0 (slot 1) with the first flag; and, in place of the shares of an
+// occupied launch (occ_parts, occ_nparts each), (0, ||start||^2, 0), from
+// which the first fused step normalises the start vector.
 __global__ __launch_bounds__(256) void lzp_init(const double* __restrict__ parts, int nparts, double* st,
-                                                double rtol) {
+                                                double* __restrict__ occ_parts, int occ_nparts, double rtol) {
   __shared__ double sm[2][4];
   double r[2] = {0.0, 0.0};
   for (int k = threadIdx.x; k < nparts; k += 256) {
@@ -410,13 +416,15 @@ __global__ __launch_bounds__(256) void lzp_init(const double* __restrict__ parts
     r[1] += parts[nparts + k];
   }
   block_sum256<2>(r, sm);
+  for (int k = threadIdx.x; k < 3 * occ_nparts; k += 256) occ_parts[k] = 0.0;
+  __syncthreads();
   if (threadIdx.x != 0) return;
   const double bn = sqrt(r[0]), bhat = sqrt(r[1]);
-  for (int k = 0; k < kNState; ++k) st[k] = 0.0;
-  st[kC2] = 1.0; st[kC1] = 1.0;
-  st[kPhiBar] = bhat;
-  st[kRes] = bhat;
-  st[kStateStride + kDone] = 0.0;
+  occ_parts[occ_nparts] = r[1];
+  double* s1 = st + kStateStride;  // the state before step 0
+  for (int k = 0; k < kNState; ++k) s1[k] = 0.0;
+  s1[kFirst] = 1.0;
+  st[kDone] = 0.0;
   double* fin = st + 2 * kStateStride;
   fin[kFinSteps] = 0.0;
   fin[kFinRes] = bhat;
@@ -451,16 +459,7 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
   double* part1 = partials_;
   const FockOp* op = eng_.fock_op();
   int nparts1 = kLzBlocks;
-  if (lz_packed_) {
-    // packed pair layout (see precond_solve_sym): the same three launches
-    n = ov + (int64_t)op->npair * eng_.v() * eng_.v();
-    Timers* tm = eng_.timers();
-    fock_op_lanczos_vir_packed(*op, v, p, st + kDone, s);
-    if (tm) tm->begin(kTimerFock, s);
-    fock_op_lanczos_occ_packed(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, st + kDone, s);
-    if (tm) tm->end(kTimerFock, s);
-    nparts1 = (int)op->nparts_packed();
-  } else if (op && op->nparts() <= kMaxFusedParts) {
+  if (op && op->nparts() <= kMaxFusedParts) {
     // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p>; the timer
     // covers the occupied launch
     Timers* tm = eng_.timers();
@@ -481,9 +480,37 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
 // Six steps: the buffer rotation (v: period 3, w: period 2, state slot:
 // period 2) returns to its start, so the block can be recorded once as a
 // HIP graph and replayed.
+int Solver::lz_block_len() const { return lz_packed_ ? kPackedBlock : kLanczosBlock; }
+
 void Solver::lanczos_block(hipStream_t s) {
   const int64_t n = n_;
   double* st = lanczos_state();
+  if (lz_packed_) {
+    // packed: two launches per step, the update fused into the next step's
+    // virtual launch; four vectors rotate (P = p_{k-1}, V = v_{k-1}, N = v_k,
+    // Y = y_k -> p_k), period 4; w rotates with period 2
+    const FockOp& op = *eng_.fock_op();
+    const int np = (int)op.nparts_packed();
+    double *P = Qi_, *V = Qi_ + n, *N = Qi_ + 2 * n, *Y = Qi_ + 3 * n;
+    double *w1 = Qi_ + 4 * n, *w2 = Qi_ + 5 * n, *x = Qi_ + 6 * n;
+    double* fin = st + 2 * kStateStride;
+    Timers* tm = eng_.timers();
+    for (int k = 0; k < kPackedBlock; ++k) {
+      double* prev = st + ((k + 1) % 2) * kStateStride;  // state after step k-1
+      double* cur = st + (k % 2) * kStateStride;         // state after step k
+      fock_op_lanczos_vir_fused(op, P, V, N, Y, w1, w2, x, partials_, np, prev, cur, fin, s);
+      if (tm) tm->begin(kTimerFock, s);
+      fock_op_lanczos_occ_packed(op, N, V, cur + kBeta, Y, partials_, kInnerSinglesScale, cur + kDone, s);
+      if (tm) tm->end(kTimerFock, s);
+      double* oldP = P;
+      P = Y;     // p_k
+      Y = V;     // free
+      V = N;     // v_k
+      N = oldP;  // free
+      std::swap(w1, w2);
+    }
+    return;
+  }
   double *vprev = Qi_, *v = Qi_ + n, *p = Qi_ + 2 * n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *x = Qi_ + 5 * n;
   for (int k = 0; k < kLanczosBlock; ++k) {
     double* cur = st + (k % 2) * kStateStride;
@@ -568,7 +595,7 @@ bool Solver::ensure_lanczos_graph(bool timed, int nb) {
   bool& failed = lz_graph_failed_[lz_packed_ ? 1 : 0][timed ? 1 : 0][nb];
   if (exec) return true;
   if (failed) return false;
-  const int pairs = nb * kLanczosBlock;
+  const int pairs = nb * lz_block_len();
   if (timed) {
     while ((int)lz_ev_.size() < 2 * pairs) {
       hipEvent_t e = nullptr;
@@ -624,48 +651,58 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   const double rs = std::sqrt(kInnerSinglesScale);
   double* st = lanczos_state();
   const double* fin = st + 2 * kStateStride;
-  double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n, *xi = Qi_ + 5 * n;
   const FockOp* op = eng_.fock_op();
   lz_packed_ = packed;
   // scaled system D^1/2 A_F D^1/2 z = D^1/2 b, x = D^1/2 z, D = diag(s I, I).
-  // ||b|| stays on the device (b = 0 gives v_1 = 0, z = 0 and a stop at
-  // the first step).
-  int64_t nl = n;  // length of the Lanczos vectors
+  // ||b|| stays on the device (b = 0 gives a zero start and a stop at the
+  // first step).
+  double* xi;  // the iterate z
   if (packed) {
     // pair-symmetric b: the recurrence runs on pairs i <= j, with inner
     // products that count the blocks of pairs i < j twice (those of the full
-    // vectors), so its steps are those of the full-layout recurrence
-    nl = ov + (int64_t)op->npair * vir * vir;
+    // vectors), so its steps are those of the full-layout recurrence. The
+    // first fused step normalises the start vector P = D^1/2 b (V = 0).
+    const int64_t nl = ov + (int64_t)op->npair * vir * vir;
+    double *P0 = Qi_, *V0 = Qi_ + n, *w1 = Qi_ + 4 * n, *w2 = Qi_ + 5 * n;
+    xi = Qi_ + 6 * n;
     double* parts = partials_ + 3 * kMaxFusedParts;
-    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, xi, parts);
-    lzp_init<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, rtol);
-    scale_by_inverse(nl, xi, fin + kFinBHat, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
+    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, P0, parts);
+    lzp_init<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, partials_, (int)op->nparts_packed(),
+                                rtol);
+    fill(nl, 0.0, V0, s);
+    fill(nl, 0.0, w1, s);
+    fill(nl, 0.0, w2, s);
+    fill(nl, 0.0, xi, s);
   } else {
+    double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n;
+    xi = Qi_ + 5 * n;
     nrm2(n, b, dsc_ + 2, partials_, s);
     copy(n, b, xi, s);
     axpby(ov, rs, b, 0.0, xi, s);
     nrm2(n, xi, dsc_ + 1, partials_, s);
     lz_init<<<1, 1, 0, s>>>(st, dsc_ + 1, dsc_ + 2, rtol);
     scale_by_inverse(n, xi, dsc_ + 1, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
+    fill(n, 0.0, vprev, s);
+    fill(n, 0.0, w1, s);
+    fill(n, 0.0, w2, s);
+    fill(n, 0.0, xi, s);
   }
-  fill(nl, 0.0, vprev, s);
-  fill(nl, 0.0, w1, s);
-  fill(nl, 0.0, w2, s);
-  fill(nl, 0.0, xi, s);
   PNK_CHECK_LAUNCH();
   Timers* tm = eng_.timers();
-  const bool fused = op && op->nparts() <= kMaxFusedParts;
-  // The first batch queues as many blocks of six steps as the last solve
-  // ran (as one recorded graph), later ones a block each. The device stops
-  // the recurrence at the first step that meets the test, so the batch
-  // size changes the cost only, never the result. With timing on, the
-  // event pairs of the steps that ran are read.
-  int batch = std::min(std::max(1, lz_blocks_hint_), (int)kMaxBatchBlocks);
-  int launched = 0;
-  int steps = 0;
+  const bool fused = packed || (op && op->nparts() <= kMaxFusedParts);
+  const int len = lz_block_len();
+  // The first batch queues as many blocks as the last solve needed steps
+  // (as one recorded graph), later ones a block each. The device stops the
+  // recurrence at the first step that meets the test, so the batch size
+  // changes the cost only, never the result. With timing on, the event
+  // pairs of the occupied launches that ran are read (in the packed form a
+  // step's update completes in the next step's first launch, so an
+  // unfinished batch has run one more occupied launch than updates).
+  int batch = std::min(std::max(1, (int)ceil_div(lz_steps_hint_ + (packed ? 1 : 0), len)), (int)kMaxBatchBlocks);
+  int launched = 0, steps = 0;
   bool conv = false;
   while (launched < maxit) {
-    const int nb = (int)std::min<int64_t>(batch, ceil_div(maxit - launched, kLanczosBlock));
+    const int nb = (int)std::min<int64_t>(batch, ceil_div(maxit - launched, len));
     bool timed = false, graph = false;
     if (use_graphs_) {
       timed = tm && fused && ensure_lanczos_graph(true, nb);
@@ -675,24 +712,26 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
     else
       for (int q = 0; q < nb; ++q) lanczos_block(s);
     const int before = launched;
-    launched += nb * kLanczosBlock;
+    launched += nb * len;
     batch = 1;
     read_scalars(host_, fin, kFinCount, s);  // synchronises the stream
     steps = (int)host_[kFinSteps];
+    // ||b - A_F x|| <= ||D^1/2 (b - A_F x)|| = the scaled residual (D >= I)
+    const double res = host_[kFinRes], bn = host_[kFinBNorm];
+    const bool ok = std::isfinite(res) && (res <= rtol * bn || host_[kFinBeta] == 0.0);
     if (timed) {
-      const int ran = std::min(nb * kLanczosBlock, steps - before);
+      const int ran_total = std::min(launched, (packed && !ok) ? steps + 1 : steps);
+      const int ran = std::min(nb * len, ran_total - before);
       for (int k = 0; k < ran; ++k) {
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, lz_ev_[2 * k], lz_ev_[2 * k + 1]) == hipSuccess) tm->add(kTimerFock, 1, ms);
         else (void)hipGetLastError();
       }
     }
-    // ||b - A_F x|| <= ||D^1/2 (b - A_F x)|| = the scaled residual (D >= I)
-    const double res = host_[kFinRes], bn = host_[kFinBNorm];
     if (!std::isfinite(res)) break;
-    if (res <= rtol * bn || host_[kFinBeta] == 0.0) { conv = true; break; }
+    if (ok) { conv = true; break; }
   }
-  lz_blocks_hint_ = (int)ceil_div(steps, kLanczosBlock);
+  lz_steps_hint_ = steps;
   if (packed) {
     lzp_unpack<<<dim3(kPackBlocksX, o * o + 1), 256, 0, s>>>(o, vir, xi, rs, x);
     PNK_CHECK_LAUNCH();
@@ -717,7 +756,7 @@ int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, in
   } end_timer{tm, s};
   if (eng_.fov_zero() && sym_inner_ && restart_ >= 5) {
     const FockOp* op = eng_.fock_op();
-    const bool packed = pair_symmetric && op && op->pt > 0 && op->nparts_packed() <= kMaxFusedParts;
+    const bool packed = pair_symmetric && op && op->pt > 0 && op->nparts_packed() <= kMaxFusedParts && restart_ >= 6;
     return precond_solve_sym(b, x, rtol, maxit, s, converged, packed);
   }
   double bn, dummy;

@@ -80,7 +80,8 @@ class Solver {
   void set_symmetric_inner(bool on) { sym_inner_ = on; }
   // Replay recorded HIP graphs for the inner iterations (default on).
   void set_graphs(bool on) { use_graphs_ = on; }
-  static constexpr int kLanczosBlock = 6;
+  static constexpr int kLanczosBlock = 6;  // steps per recorded block (full layout)
+  static constexpr int kPackedBlock = 4;   // steps per recorded block (packed layout, fused update)
   void solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s);
   void solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipStream_t s);
 
@@ -121,12 +122,13 @@ class Solver {
   bool lz_graph_failed_[2][2][kMaxBatchBlocks + 1] = {};
   bool lz_packed_ = false;  // layout of the current symmetric solve
   std::vector<hipEvent_t> lz_ev_;  // event pairs around the A_F launches of a timed run
-  int lz_blocks_hint_ = 0;         // blocks of six steps the last symmetric solve ran
+  int lz_steps_hint_ = 0;          // steps the last symmetric solve ran
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
                     double* stn, hipStream_t s);
   // state slots of the Lanczos recurrence (device scalars)
   double* lanczos_state() const;
   void lanczos_block(hipStream_t s);
+  int lz_block_len() const;
   bool ensure_lanczos_graph(bool timed, int nb);
   std::vector<double> hist_;
 };
