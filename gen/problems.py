@@ -176,6 +176,26 @@ def make_general(nocc: int, nvir: int, naux: int, seed: int, *,
                         gauge="general"))
 
 
+def nonorthogonal_gauge(nocc: int, nvir: int, seed: int, cond: float = 4.0):
+    """Invertible, non-orthogonal gauge matrices W_o [o][o] and W_v [v][v]:
+    Q1 diag(s) Q2 with Haar Q1, Q2 and singular values s = cond^u, u
+    uniform on [-1/2, 1/2] with the two ends always drawn, so each block's
+    condition number is `cond` (1 gives an orthogonal gauge). Column mu of
+    W holds the expansion of gauge function mu in the orthonormal orbitals
+    of its block; the gauge functions overlap as S = W^T W."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for m in (nocc, nvir):
+        u = rng.uniform(-0.5, 0.5, m)
+        if m >= 2:
+            u[0], u[1] = -0.5, 0.5
+        s = cond ** u
+        q1 = haar_orthogonal(rng, m)
+        q2 = haar_orthogonal(rng, m)
+        out.append(np.ascontiguousarray((q1 * s[None, :]) @ q2))
+    return out[0], out[1]
+
+
 def random_amplitudes(nocc: int, nvir: int, seed: int, scale: float = 0.05):
     """Random t1 [o][v] and pair-symmetric t2 [o][o][v][v] (t_ij^ab = t_ji^ba)."""
     rng = np.random.default_rng(seed)
@@ -200,6 +220,10 @@ CONFIGS = {
     "c4_mixed": dict(kind="plain", nocc=20, nvir=180, naux=600, seed=1004,
                      sigma=0.05, gauge="haar", tol=1e-8),
 }
+
+# Non-orthogonal gauge workload: the C2 Hamiltonian (Haar-rotated orbitals)
+# solved for the amplitudes in a gauge of condition number `cond` per block.
+GAUGE_WORKLOAD = dict(config="c2_haar", gauge_seed=2002, cond=4.0)
 
 
 def make_config(name: str) -> Problem:

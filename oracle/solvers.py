@@ -207,6 +207,13 @@ class _Problem:
         return self.mask(res.x)
 
 
+def _make_problem(f_oo, f_ov, f_vv, L, ccd, gauge):
+    if gauge is None:
+        return _Problem(f_oo, f_ov, f_vv, L, ccd)
+    from .gauge import GaugeProblem
+    return GaugeProblem(f_oo, f_ov, f_vv, L, gauge[0], gauge[1], ccd)
+
+
 def mp2_guess(f_oo, f_ov, f_vv, L, inner_rtol=1e-12, inner_maxit=200, inner_restart=30):
     """theta^0 = -A_F^{-1} r(0): the generalized MP2 amplitudes
     (equation inexact_newton_update at t = 0)."""
@@ -234,11 +241,13 @@ def forcing_term(k, rn, rn_prev, eta_prev, tol, gamma=0.9, alpha=1.5,
 def solve_pnk(f_oo, f_ov, f_vv, L, tol=1e-8, max_newton=100, m_max=20,
               gamma=0.9, alpha=1.5, eta0=0.5, eta_max=0.9, inner_rtol=1e-12,
               inner_maxit=200, inner_restart=30, jvp="complex", x0=None,
-              precond=True, ccd=False):
+              precond=True, ccd=False, gauge=None):
     """PNK (precond=True) or unpreconditioned NK (precond=False), Algorithm 1
-    and the method table; ccd=True at the CCD level (see _Problem)."""
+    and the method table; ccd=True at the CCD level (see _Problem).
+    gauge=(W_o, W_v) iterates on the amplitudes of that non-orthogonal gauge
+    (oracle.gauge) and returns them."""
     t_start = time.perf_counter()
-    P = _Problem(f_oo, f_ov, f_vv, L, ccd)
+    P = _make_problem(f_oo, f_ov, f_vv, L, ccd, gauge)
     info = SolveInfo()
     N = P.o * P.v + P.o ** 2 * P.v ** 2
 
@@ -334,15 +343,20 @@ def jacobi_denominators(f_oo, f_vv, shift=0.0):
 
 def solve_fp_diis(f_oo, f_ov, f_vv, L, tol=1e-8, max_iter=500, diis_size=8,
                   diis_start=2, level_shift=0.0, x0=None, init="mp2",
-                  inner_rtol=1e-12, diverge=1e6, ccd=False):
+                  inner_rtol=1e-12, diverge=1e6, ccd=False, gauge=None):
     """(S)FP iteration t <- t - r(t)/D with DIIS over the last `diis_size`
     (amplitude, Jacobi step) pairs; diis_size = 0 disables DIIS; ccd=True at
-    the CCD level (see _Problem)."""
+    the CCD level (see _Problem). gauge=(W_o, W_v): the iteration on the
+    amplitudes of that gauge, D from the diagonals of its Fock blocks (the
+    random-gauge FP update)."""
     t_start = time.perf_counter()
-    P = _Problem(f_oo, f_ov, f_vv, L, ccd)
+    P = _make_problem(f_oo, f_ov, f_vv, L, ccd, gauge)
     info = SolveInfo()
     N = P.o * P.v + P.o ** 2 * P.v ** 2
-    d1, d2 = jacobi_denominators(f_oo, f_vv, level_shift)
+    if gauge is not None:
+        d1, d2 = jacobi_denominators(P.Fo, P.Fv, level_shift)
+    else:
+        d1, d2 = jacobi_denominators(f_oo, f_vv, level_shift)
     D = pack(d1, d2)
     if x0 is not None:
         x = P.mask(x0)

@@ -385,3 +385,100 @@ def test_fp_contraction_rate_is_the_spectral_radius(shift):
     _, _, fp = solvers.solve_fp_diis(*_args(p), tol=1e-13, diis_size=0, level_shift=shift, x0=x0, max_iter=400)
     h = np.array([r[1] for r in fp.history])
     assert fp.converged and abs(h[-1] / h[-2] - rho) < 0.02
+
+
+# ------------------------------------------------- non-orthogonal gauge ----
+def _gauge_problem(seed=1101, o=3, v=7, naux=20, cond=4.0, kind="haar"):
+    from gen import nonorthogonal_gauge
+    p = make_general(o, v, naux, seed) if kind == "general" else make_problem(o, v, naux, seed, gauge=kind)
+    Wo, Wv = nonorthogonal_gauge(o, v, seed + 7, cond)
+    return p, Wo, Wv
+
+
+def test_gauge_matrices_have_the_requested_condition_number():
+    from gen import nonorthogonal_gauge
+    Wo, Wv = nonorthogonal_gauge(5, 12, 3, 6.0)
+    assert abs(np.linalg.cond(Wo) - 6.0) < 1e-9 and abs(np.linalg.cond(Wv) - 6.0) < 1e-9
+    Wo, Wv = nonorthogonal_gauge(5, 12, 3, 1.0)
+    assert np.abs(Wo.T @ Wo - np.eye(5)).max() < 1e-13 and np.abs(Wv.T @ Wv - np.eye(12)).max() < 1e-13
+
+
+def test_gauge_orthogonal_case_is_a_rotation_of_the_hamiltonian():
+    """For orthogonal W the gauge amplitudes are those of the rotated
+    orbitals phi W: the gauge residual equals the orbital-basis residual of
+    the Hamiltonian rotated by U = W^T (f -> U f U^T, L^P -> U L^P U^T),
+    singles and f_ov included."""
+    from oracle import gauge
+    p, Wo, Wv = _gauge_problem(kind="general", cond=1.0)
+    o, v = p.f_oo.shape[0], p.f_vv.shape[0]
+    U = np.zeros((o + v, o + v))
+    U[:o, :o], U[o:, o:] = Wo.T, Wv.T
+    f = U @ p.fock() @ U.T
+    Lr = np.einsum("pr,Prs,qs->Ppq", U, p.L, U)
+    th1, th2 = random_amplitudes(o, v, 31, scale=0.1)
+    r1, r2 = gauge.residual(*_args(p), Wo, Wv, th1, th2)
+    q1, q2 = ccsd.residual(f[:o, :o], f[:o, o:], f[o:, o:], Lr, th1, th2)
+    assert np.abs(r1 - q1).max() < 1e-12 and np.abs(r2 - q2).max() < 1e-12
+    e = gauge.energy(*_args(p), Wo, Wv, th1, th2)
+    assert abs(e - ccsd.energy(f[:o, :o], f[:o, o:], f[o:, o:], Lr, th1, th2)) < 1e-13
+
+
+@pytest.mark.parametrize("cond", [2.0, 8.0])
+def test_gauge_residual_equals_the_appendix_random_gauge_equations(cond):
+    """The definition r(theta) = U-bar^(x4) r(t) equals the random-gauge CCD
+    residual written out in the appendix's transformed integrals, Fock
+    blocks and intermediates, for a non-orthogonal gauge."""
+    from oracle import gauge
+    p, Wo, Wv = _gauge_problem(cond=cond)
+    o, v = p.f_oo.shape[0], p.f_vv.shape[0]
+    _, t2 = random_amplitudes(o, v, 32, scale=0.1)
+    _, th2 = gauge.forward(Wo, Wv, np.zeros((o, v)), t2)
+    _, r2 = gauge.residual(*_args(p), Wo, Wv, np.zeros((o, v)), th2)
+    x2 = gauge.residual_ccd_explicit(p.f_oo, p.f_vv, p.L, Wo, Wv, th2)
+    assert np.abs(r2 - x2).max() < 1e-12 * max(1.0, np.abs(r2).max())
+
+
+def test_gauge_fock_operator_is_the_jacobian_without_two_electron_part():
+    """A_F in the gauge (Kronecker sum of Fv and -Fo, f_ov coupling) is the
+    Jacobian of the gauge residual at theta = 0 when L = 0; it is not
+    symmetric for a non-orthogonal gauge."""
+    from oracle import gauge
+    p, Wo, Wv = _gauge_problem(kind="general")
+    o, v = p.f_oo.shape[0], p.f_vv.shape[0]
+    Fo, Fv = gauge.fock_blocks(p.f_oo, p.f_vv, Wo, Wv)
+    x1, x2 = random_amplitudes(o, v, 33)
+    j1, j2 = gauge.jvp_complex_step(p.f_oo, p.f_ov, p.f_vv, np.zeros_like(p.L), Wo, Wv,
+                                    np.zeros((o, v)), np.zeros((o, o, v, v)), x1, x2)
+    a1, a2 = gauge.fock_apply(p.f_ov, Wo, Wv, Fo, Fv, x1, x2)
+    assert np.abs(j1 - a1).max() < 1e-13 and np.abs(j2 - a2).max() < 1e-13
+    assert np.abs(Fv - Fv.T).max() > 1e-3 and np.abs(Fo - Fo.T).max() > 1e-3
+
+
+def test_gauge_fp_in_a_diagonal_gauge_follows_the_orbital_fp():
+    """A diagonal gauge W = diag(s) leaves the diagonals of the Fock blocks
+    unchanged, so the gauge FP step (no DIIS) is the orbital FP step
+    transformed: after k steps theta_k = U-bar^(x4) t_k."""
+    from oracle import gauge
+    p = make_problem(3, 7, 20, 1102, gauge="canonical")
+    rng = np.random.default_rng(4)
+    Wo, Wv = np.diag(rng.uniform(0.5, 2.0, 3)), np.diag(rng.uniform(0.5, 2.0, 7))
+    a1, a2, ia = solvers.solve_fp_diis(*_args(p), tol=1e-30, diis_size=0, max_iter=4, gauge=(Wo, Wv))
+    b1, b2, ib = solvers.solve_fp_diis(*_args(p), tol=1e-30, diis_size=0, max_iter=4)
+    c1, c2 = gauge.forward(Wo, Wv, b1, b2)
+    assert ia.newton_iters == ib.newton_iters == 4
+    assert np.abs(a1 - c1).max() < 1e-13 and np.abs(a2 - c2).max() < 1e-13
+
+
+def test_gauge_pnk_lands_on_the_transformed_root():
+    """PNK on the gauge amplitudes (A_F of the gauge, solved by GMRES)
+    converges to U-bar^(x4) t* with the orbital-basis energy."""
+    from gen import nonorthogonal_gauge
+    from oracle import gauge
+    p = make_problem(4, 16, 48, 1001, gauge="haar")
+    Wo, Wv = nonorthogonal_gauge(4, 16, 2002, 4.0)
+    a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-11, gauge=(Wo, Wv))
+    b1, b2, ib = solvers.solve_pnk(*_args(p), tol=1e-11)
+    c1, c2 = gauge.forward(Wo, Wv, b1, b2)
+    assert ia.converged and ib.converged
+    assert np.abs(a1 - c1).max() < 1e-9 and np.abs(a2 - c2).max() < 1e-9
+    assert abs(ia.e_corr - ib.e_corr) < 1e-10
