@@ -237,6 +237,57 @@ cc_status cc_fp_spectral_radius(cc_handle* h, const cc_problem* p, const double*
                                 const double* q2, double shift, int m, double* rho_out, double* ritz_re,
                                 double* ritz_im, int* n_ritz, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Non-orthogonal orbital gauges (Appendix A, random gauge representation).
+ *
+ * Per orbital block the gauge functions are chi = phi W with W invertible
+ * but not necessarily orthogonal: w_oo [nocc][nocc] and w_vv [nvir][nvir]
+ * (DEVICE, FP64, row-major, caller-owned), column mu holding gauge function
+ * mu expanded in the orthonormal orbitals of the problem (the orbitals f and
+ * L are given in). The gauge functions overlap as S = W^T W. The gauge
+ * amplitudes are the covariant components (the appendix's theta = U-bar^(x4)
+ * t with U-bar = S U = W^T):
+ *   th1[mu][lam]          = sum_ia W_o[i][mu] W_v[a][lam] t1[i][a]
+ *   th2[mu][nu][lam][sig] = sum W_o[i][mu] W_o[j][nu] W_v[a][lam] W_v[b][sig] t2[i][j][a][b]
+ * and the gauge residual is r(theta) = U-bar^(x4) r(t(theta)). The gauge's
+ * Fock blocks W^T f W^-T make its A_F non-symmetric; its inverse is applied
+ * as U-bar^(x4) A_F^-1 (W^-T)^(x4) with the orbital-basis inner solve. The
+ * FP denominators are the diagonals of those blocks (the appendix's FP
+ * update). Each call copies W to the host and inverts it (Gauss-Jordan,
+ * partial pivoting): CC_ERR_ARG for a singular or non-finite W. The handle
+ * keeps 3 N + 2 o^2 v^2 doubles of gauge buffers (N = o v + o^2 v^2) once
+ * a gauge call has run. All calls synchronise.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  const double* w_oo;
+  const double* w_vv;
+} cc_gauge;
+
+/* y = U-bar^(x4) x (to_gauge != 0: orbital amplitudes or residuals to the
+ * gauge's) or its inverse (to_gauge == 0), for (x1 [o][v], x2 [o][o][v][v])
+ * (device); y must not overlap x. */
+cc_status cc_gauge_transform(cc_handle* h, const cc_problem* p, const cc_gauge* g, int to_gauge, const double* x1,
+                             const double* x2, double* y1, double* y2, void* stream);
+
+/* Gauge residual (r1, r2) at gauge amplitudes (th1, th2), all device, and
+ * optionally the correlation energy (gauge invariant) to e_corr_host. */
+cc_status cc_residual_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const double* th1,
+                            const double* th2, double* r1, double* r2, double* e_corr_host, void* stream);
+
+/* J v of the gauge residual at (th1, th2) in direction (v1, v2): the
+ * orbital-basis product of cc_jvp (precision prec) between the transforms. */
+cc_status cc_jvp_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const double* th1, const double* th2,
+                       const double* v1, const double* v2, double* jv1, double* jv2, cc_precision prec,
+                       void* stream);
+
+/* PNK / FP(+DIIS) solves on the gauge amplitudes: the contracts of
+ * cc_solve_pnk / cc_solve_fp_diis with (th1, th2) gauge amplitudes in and
+ * out, the stopping test on the gauge residual's ||r||_inf. */
+cc_status cc_solve_pnk_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const cc_pnk_opts* opts,
+                             double* th1, double* th2, cc_info* info, void* stream);
+cc_status cc_solve_fp_diis_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const cc_fp_opts* opts,
+                                 double* th1, double* th2, cc_info* info, void* stream);
+
 /* Residual history of the last solve on the handle: pairs (||r||_2,
  * ||r||_inf) per outer residual evaluation, up to max_pairs written to
  * `pairs` (host, 2 * max_pairs doubles); returns the number available. */

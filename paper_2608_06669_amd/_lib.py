@@ -50,6 +50,10 @@ class cc_fp_opts(ctypes.Structure):
                 ("ccd", ctypes.c_int)]
 
 
+class cc_gauge(ctypes.Structure):
+    _fields_ = [("w_oo", ctypes.c_void_p), ("w_vv", ctypes.c_void_p)]
+
+
 class cc_info(ctypes.Structure):
     _fields_ = [("e_corr", ctypes.c_double), ("res_inf", ctypes.c_double), ("res_2", ctypes.c_double),
                 ("converged", ctypes.c_int), ("newton_iters", ctypes.c_int), ("n_residual", ctypes.c_int),
@@ -95,6 +99,14 @@ SIGNATURES = {
                          ctypes.POINTER(cc_info), P]),
     "cc_solve_fp_diis": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_fp_opts), P, P,
                              ctypes.POINTER(cc_info), P]),
+    "cc_gauge_transform": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_gauge), I, P, P, P, P, P]),
+    "cc_residual_gauge": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_gauge), P, P, P, P,
+                              ctypes.POINTER(D), P]),
+    "cc_jvp_gauge": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_gauge), P, P, P, P, P, P, I, P]),
+    "cc_solve_pnk_gauge": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_gauge), ctypes.POINTER(cc_pnk_opts),
+                               P, P, ctypes.POINTER(cc_info), P]),
+    "cc_solve_fp_diis_gauge": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_gauge),
+                                   ctypes.POINTER(cc_fp_opts), P, P, ctypes.POINTER(cc_info), P]),
     "cc_last_history": (I, [P, ctypes.POINTER(D), I]),
     "cc_server_create": (I, [PP, I, ctypes.c_size_t, I]),
     "cc_server_submit": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_pnk_opts),

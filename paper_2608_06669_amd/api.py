@@ -9,7 +9,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
-from ._lib import cc_fp_opts, cc_info, cc_pnk_opts, cc_problem, cc_server_stats
+from ._lib import cc_fp_opts, cc_gauge, cc_info, cc_pnk_opts, cc_problem, cc_server_stats
 
 
 class CCError(RuntimeError):
@@ -59,6 +59,16 @@ class DeviceProblem:
         dev = self.f_oo.device
         return (torch.zeros(o, v, dtype=torch.float64, device=dev),
                 torch.zeros(o, o, v, v, dtype=torch.float64, device=dev))
+
+
+class DeviceGauge:
+    """W_o [o][o] and W_v [v][v] of a non-orthogonal gauge as device tensors
+    plus the cc_gauge struct (column mu: gauge function mu in the orbitals)."""
+
+    def __init__(self, w_oo, w_vv, device="cuda"):
+        conv = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device).contiguous()  # noqa: E731
+        self.w_oo, self.w_vv = conv(w_oo), conv(w_vv)
+        self.struct = cc_gauge(_ptr(self.w_oo), _ptr(self.w_vv))
 
 
 def pnk_opts(**kw) -> cc_pnk_opts:
@@ -180,6 +190,52 @@ class Handle:
                                                  _ptr(q2), float(shift), int(m), ctypes.byref(rho),
                                                  re.ctypes.data, im.ctypes.data, ctypes.byref(nr), _stream(stream)))
         return rho.value, (re + 1j * im)[: nr.value]
+
+    # ---- non-orthogonal gauges ----
+    def gauge_transform(self, p: DeviceProblem, g: DeviceGauge, x1, x2, to_gauge=True, stream=None):
+        y1, y2 = torch.empty_like(x1), torch.empty_like(x2)
+        self._check(_lib().cc_gauge_transform(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct),
+                                              1 if to_gauge else 0, _ptr(x1), _ptr(x2), _ptr(y1), _ptr(y2),
+                                              _stream(stream)))
+        return y1, y2
+
+    def residual_gauge(self, p: DeviceProblem, g: DeviceGauge, th1, th2, energy=False, stream=None):
+        r1, r2 = torch.empty_like(th1), torch.empty_like(th2)
+        e = ctypes.c_double(0.0)
+        self._check(_lib().cc_residual_gauge(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct), _ptr(th1),
+                                             _ptr(th2), _ptr(r1), _ptr(r2), ctypes.byref(e) if energy else None,
+                                             _stream(stream)))
+        return (r1, r2, e.value) if energy else (r1, r2)
+
+    def jvp_gauge(self, p: DeviceProblem, g: DeviceGauge, th1, th2, v1, v2, prec="fp64", stream=None):
+        y1, y2 = torch.empty_like(v1), torch.empty_like(v2)
+        pr = L.PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        self._check(_lib().cc_jvp_gauge(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct), _ptr(th1),
+                                        _ptr(th2), _ptr(v1), _ptr(v2), _ptr(y1), _ptr(y2), pr, _stream(stream)))
+        return y1, y2
+
+    def solve_pnk_gauge(self, p: DeviceProblem, g: DeviceGauge, th1=None, th2=None, stream=None, **opts):
+        o = pnk_opts(**opts)
+        if th1 is None:
+            th1, th2 = p.zeros_t()
+            o.init_mp2 = 1 if "init_mp2" not in opts else o.init_mp2
+        info = cc_info()
+        st = self._check(_lib().cc_solve_pnk_gauge(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct),
+                                                   ctypes.byref(o), _ptr(th1), _ptr(th2), ctypes.byref(info),
+                                                   _stream(stream)),
+                         ok=(L.CC_OK, L.CC_NOT_CONVERGED, L.CC_ERR_NAN))
+        return th1, th2, dict(info.as_dict(), status=L.STATUS_NAMES[st])
+
+    def solve_fp_diis_gauge(self, p: DeviceProblem, g: DeviceGauge, th1=None, th2=None, stream=None, **opts):
+        o = fp_opts(**opts)
+        if th1 is None:
+            th1, th2 = p.zeros_t()
+        info = cc_info()
+        st = self._check(_lib().cc_solve_fp_diis_gauge(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct),
+                                                       ctypes.byref(o), _ptr(th1), _ptr(th2), ctypes.byref(info),
+                                                       _stream(stream)),
+                         ok=(L.CC_OK, L.CC_NOT_CONVERGED, L.CC_ERR_NAN))
+        return th1, th2, dict(info.as_dict(), status=L.STATUS_NAMES[st])
 
     def timing(self, enable: bool = True):
         self._check(_lib().cc_diag_timing(self._h, 1 if enable else 0))

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpnkcc.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["gemm.hip", "fock_op.hip", "tensor_ops.hip", "cc_kernels.hip", "ccsd.hip", "solvers.hip", "eig.hip", "api.hip",
+SOURCES = ["gemm.hip", "fock_op.hip", "tensor_ops.hip", "cc_kernels.hip", "ccsd.hip", "solvers.hip", "eig.hip", "gauge.hip", "api.hip",
            "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -10,6 +10,7 @@
 #include "../../include/pnkcc.h"
 #include "api_internal.hpp"
 #include "eig.hpp"
+#include "gauge.hpp"
 #include "gemm.hpp"
 #include "tensor_ops.hpp"
 
@@ -56,6 +57,37 @@ Handle::~Handle() {
   dev_free(xa);
   dev_free(xb);
   dev_free(hash_buf);
+  dev_free(gauge_mem);
+}
+
+Gauge* Handle::ensure_gauge(const cc_gauge* g, hipStream_t s) {
+  PNK_REQUIRE(g && g->w_oo && g->w_vv, "gauge matrices must not be NULL");
+  const int o = eng->o(), v = eng->v();
+  if (!gauge_mem || gauge.o != o || gauge.v != v) {
+    dev_free(gauge_mem);
+    gauge_mem = nullptr;
+    const int64_t me = gauge_matrix_elems(o, v), ve = gauge_vector_elems(o, v);
+    const size_t bytes = (size_t)(me + ve) * sizeof(double) + 16 * 256;
+    if (limit && workspace_bytes(o, v, eng->naux(), 0, sol_m, sol_r, sol_d) + bytes > limit)
+      throw OomError("the gauge buffers (" + std::to_string(bytes) + " bytes) exceed the handle limit");
+    gauge_mem = (double*)dev_alloc(bytes);
+    // 256-byte aligned pieces
+    char* base = (char*)gauge_mem;
+    auto take = [&](int64_t elems) {
+      double* p = (double*)base;
+      base += ((size_t)elems * sizeof(double) + 255) & ~(size_t)255;
+      return p;
+    };
+    const int64_t oo = (int64_t)o * o, vv = (int64_t)v * v, ov = (int64_t)o * v, n2 = ov * ov;
+    gauge.o = o;
+    gauge.v = v;
+    gauge.fwd_o = take(oo); gauge.bwd_o = take(oo); gauge.Fo = take(oo);
+    gauge.fwd_v = take(vv); gauge.bwd_v = take(vv); gauge.Fv = take(vv);
+    gauge.t = take(ov + n2); gauge.w1 = take(ov + n2); gauge.w2 = take(ov + n2);
+    gauge.ta = take(n2); gauge.tb = take(n2);
+  }
+  gauge_setup(gauge, g->w_oo, g->w_vv, eng->f_oo(), eng->f_vv(), s);
+  return &gauge;
 }
 
 void Handle::ensure(const cc_problem* p, int lowp, int m_max, int restart, int diis, hipStream_t s) {
@@ -416,6 +448,144 @@ cc_status cc_solve_fp_diis(cc_handle* h, const cc_problem* p, const cc_fp_opts* 
   SolveStats st;
   H->sol->solve_fp_diis(H->xa, fo, &st, s);
   unpack(ov, n2, H->xa, t1, t2, s);
+  PNK_HIP(hipStreamSynchronize(s));
+  H->history = H->sol->history();
+  fill_info(st, info);
+  if (st.diverged) { H->err = "non-finite residual norm"; return CC_ERR_NAN; }
+  return st.converged ? CC_OK : CC_NOT_CONVERGED;
+  PNK_API_END
+}
+
+cc_status cc_gauge_transform(cc_handle* h, const cc_problem* p, const cc_gauge* g, int to_gauge, const double* x1,
+                             const double* x2, double* y1, double* y2, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(x1 && x2 && y1 && y2, "array arguments must not be NULL");
+  H->ensure(p, 0, 1, 1, 0, s);
+  Gauge* G = H->ensure_gauge(g, s);
+  const int o = H->eng->o(), v = H->eng->v();
+  const int64_t ov = (int64_t)o * v, n2 = H->eng->nvec() - ov;
+  pack(ov, n2, x1, x2, H->xa, s);
+  if (to_gauge) gauge_apply(o, v, G->fwd_o, G->fwd_v, H->xa, H->xb, G->ta, G->tb, s);
+  else gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, H->xb, G->ta, G->tb, s);
+  unpack(ov, n2, H->xb, y1, y2, s);
+  PNK_HIP(hipStreamSynchronize(s));
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_residual_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const double* th1,
+                            const double* th2, double* r1, double* r2, double* e_corr_host, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(th1 && th2 && r1 && r2, "th1, th2, r1, r2 must not be NULL");
+  H->ensure(p, 0, 1, 1, 0, s);
+  Gauge* G = H->ensure_gauge(g, s);
+  const int o = H->eng->o(), v = H->eng->v();
+  const int64_t ov = (int64_t)o * v, n2 = H->eng->nvec() - ov;
+  pack(ov, n2, th1, th2, H->xa, s);
+  gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, G->t, G->ta, G->tb, s);
+  H->eng->residual(G->t, G->t + ov, G->w1, G->w1 + ov, s);
+  gauge_apply(o, v, G->fwd_o, G->fwd_v, G->w1, H->xb, G->ta, G->tb, s);
+  unpack(ov, n2, H->xb, r1, r2, s);
+  if (e_corr_host) {
+    H->eng->energy(G->t, G->t + ov, H->eng->scratch_partials() + 1024, s);
+    PNK_HIP(hipMemcpyAsync(e_corr_host, H->eng->scratch_partials() + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
+  }
+  PNK_HIP(hipStreamSynchronize(s));
+  return CC_OK;
+  PNK_API_END
+}
+
+cc_status cc_jvp_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const double* th1, const double* th2,
+                       const double* v1, const double* v2, double* jv1, double* jv2, cc_precision prec,
+                       void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(th1 && th2 && v1 && v2 && jv1 && jv2, "array arguments must not be NULL");
+  PNK_REQUIRE(prec == CC_FP64 || prec == CC_FP32 || prec == CC_BF16, "unknown precision");
+  H->ensure(p, lowp_for(prec), 1, 1, 0, s);
+  Gauge* G = H->ensure_gauge(g, s);
+  const int o = H->eng->o(), v = H->eng->v();
+  const int64_t ov = (int64_t)o * v, n2 = H->eng->nvec() - ov;
+  // linearise at t(theta), then J_theta v = (W^T)^(x4) J (W^-T)^(x4) v
+  pack(ov, n2, th1, th2, H->xa, s);
+  gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, G->t, G->ta, G->tb, s);
+  H->eng->residual(G->t, G->t + ov, G->w1, G->w1 + ov, s);
+  pack(ov, n2, v1, v2, H->xa, s);
+  gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, G->w1, G->ta, G->tb, s);
+  H->eng->jvp(G->w1, G->w1 + ov, G->w2, G->w2 + ov, (Prec)prec, s);
+  gauge_apply(o, v, G->fwd_o, G->fwd_v, G->w2, H->xb, G->ta, G->tb, s);
+  unpack(ov, n2, H->xb, jv1, jv2, s);
+  PNK_HIP(hipStreamSynchronize(s));
+  return CC_OK;
+  PNK_API_END
+}
+
+namespace {
+// Sets the solver's gauge for the lifetime of the object.
+struct GaugeScope {
+  Solver* sol;
+  GaugeScope(Solver* s, const Gauge* g) : sol(s) { sol->set_gauge(g); }
+  ~GaugeScope() { sol->set_gauge(nullptr); }
+};
+}  // namespace
+
+cc_status cc_solve_pnk_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const cc_pnk_opts* opts,
+                             double* th1, double* th2, cc_info* info, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(th1 && th2, "th1, th2 must not be NULL");
+  cc_pnk_opts o;
+  cc_pnk_opts_default(&o);
+  if (opts) o = *opts;
+  check_pnk_opts(o);
+  H->ensure(p, lowp_for(o.jvp_prec), o.m_max, o.inner_restart, 0, s);
+  Gauge* G = H->ensure_gauge(g, s);
+  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
+  if (!o.init_mp2) pack(ov, n2, th1, th2, H->xa, s);
+  SolveStats st;
+  {
+    GaugeScope scope(H->sol.get(), G);
+    H->sol->solve_pnk(H->xa, to_internal(o), &st, s);
+  }
+  unpack(ov, n2, H->xa, th1, th2, s);
+  PNK_HIP(hipStreamSynchronize(s));
+  H->history = H->sol->history();
+  fill_info(st, info);
+  if (st.diverged) { H->err = "non-finite residual norm"; return CC_ERR_NAN; }
+  return st.converged ? CC_OK : CC_NOT_CONVERGED;
+  PNK_API_END
+}
+
+cc_status cc_solve_fp_diis_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, const cc_fp_opts* opts,
+                                 double* th1, double* th2, cc_info* info, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(th1 && th2, "th1, th2 must not be NULL");
+  cc_fp_opts o;
+  cc_fp_opts_default(&o);
+  if (opts) o = *opts;
+  PNK_REQUIRE(o.tol_inf > 0 && o.max_iter >= 0 && o.diis_size >= 0 && o.diis_size <= 32 && o.diis_start >= 0,
+              "invalid FP options");
+  H->ensure(p, 0, 1, 30, std::max(o.diis_size, 1), s);
+  Gauge* G = H->ensure_gauge(g, s);
+  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
+  if (!o.init_mp2) pack(ov, n2, th1, th2, H->xa, s);
+  FpOptions fo;
+  fo.tol_inf = o.tol_inf;
+  fo.max_iter = o.max_iter;
+  fo.diis_size = o.diis_size;
+  fo.diis_start = o.diis_start;
+  fo.level_shift = o.level_shift;
+  fo.init_mp2 = o.init_mp2 != 0;
+  fo.ccd = o.ccd != 0;
+  SolveStats st;
+  {
+    GaugeScope scope(H->sol.get(), G);
+    H->sol->solve_fp_diis(H->xa, fo, &st, s);
+  }
+  unpack(ov, n2, H->xa, th1, th2, s);
   PNK_HIP(hipStreamSynchronize(s));
   H->history = H->sol->history();
   fill_info(st, info);

@@ -7,6 +7,7 @@
 
 #include "../../include/pnkcc.h"
 #include "ccsd.hpp"
+#include "gauge.hpp"
 #include "solvers.hpp"
 
 namespace pnk {
@@ -37,7 +38,12 @@ struct Handle {
   std::vector<double> history;
   std::string err;
   std::unique_ptr<Timers> timers;  // set when diagnostics timing is on
+  Gauge gauge;                      // buffers of the non-orthogonal gauge entry points
+  double* gauge_mem = nullptr;
   ~Handle();
+  // Size the gauge buffers for the engine's (o, v) and fill its matrices
+  // from g and the prepared problem's Fock blocks (after ensure()).
+  Gauge* ensure_gauge(const cc_gauge* g, hipStream_t s);
   void* dev_alloc(size_t bytes);
   void dev_free(void* p);
   // Size the engine/solver for p and (re)prepare its integrals if the

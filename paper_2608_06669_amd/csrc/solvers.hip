@@ -840,6 +840,44 @@ double forcing(int k, double rn, double rn_prev, double eta_prev, double tol, co
 }
 }  // namespace
 
+// In a gauge: r(theta) = (W^T)^(x4) r(t), t = (W^-T)^(x4) theta (kept in
+// gauge_->t, the point J v is linearised at); A_F of the gauge is inverted
+// as (W^T)^(x4) A_F^-1 (W^-T)^(x4); the energy is that of t.
+void Solver::g_residual(const double* x, double* r, hipStream_t s) {
+  const int o = eng_.o(), vir = eng_.v();
+  const int64_t ov = (int64_t)o * vir;
+  if (!gauge_) {
+    eng_.residual(x, x + ov, r, r + ov, s);
+    return;
+  }
+  const Gauge& g = *gauge_;
+  gauge_apply(o, vir, g.bwd_o, g.bwd_v, x, g.t, g.ta, g.tb, s);
+  eng_.residual(g.t, g.t + ov, g.w1, g.w1 + ov, s);
+  gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w1, r, g.ta, g.tb, s);
+}
+
+int Solver::g_precond(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s, bool* conv) {
+  if (!gauge_) return precond_solve(b, x, rtol, maxit, restart, s, conv, true);
+  const Gauge& g = *gauge_;
+  const int o = eng_.o(), vir = eng_.v();
+  gauge_apply(o, vir, g.bwd_o, g.bwd_v, b, g.w2, g.ta, g.tb, s);
+  const int it = precond_solve(g.w2, g.w1, rtol, maxit, restart, s, conv, true);
+  gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w1, x, g.ta, g.tb, s);
+  return it;
+}
+
+void Solver::g_energy(const double* x, double* e_dev, hipStream_t s) {
+  const int o = eng_.o(), vir = eng_.v();
+  const int64_t ov = (int64_t)o * vir;
+  if (!gauge_) {
+    eng_.energy(x, x + ov, e_dev, s);
+    return;
+  }
+  const Gauge& g = *gauge_;
+  gauge_apply(o, vir, g.bwd_o, g.bwd_v, x, g.w1, g.ta, g.tb, s);
+  eng_.energy(g.w1, g.w1 + ov, e_dev, s);
+}
+
 void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s) {
   const double t0 = now_s();
   *st = SolveStats();
@@ -865,7 +903,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
       pair_symmetrize_add(o, vir, b + ov, 0.5, out + ov, s);
     } else {
       bool conv = true;
-      const int it = precond_solve(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
+      const int it = g_precond(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv);
       st->n_afmv += it;
       st->n_inner_iters += it;
     }
@@ -873,11 +911,11 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   };
   if (opt.init_mp2) {
     // MP2-type start for every protocol (NK included): -A_F^-1 r(0)
-    eng_.residual(eng_.zeros(), eng_.zeros() + ov, r_, r_ + ov, s);
+    g_residual(eng_.zeros(), r_, s);
     st->n_residual++;
     mask(r_);
     bool conv = true;
-    const int it = precond_solve(r_, x, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
+    const int it = g_precond(r_, x, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv);
     st->n_afmv += it;
     st->n_inner_iters += it;
     axpby(n, 0.0, x, -1.0, x, s);
@@ -887,7 +925,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   int k = 0;
   std::vector<double> H, cs, sn, g, h;
   while (true) {
-    eng_.residual(x, x + ov, r_, r_ + ov, s);
+    g_residual(x, r_, s);
     st->n_residual++;
     mask(r_);
     double rinf, rn;
@@ -934,18 +972,39 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     for (int m = 0; m < M; ++m) {
       double* q = Qo_ + (size_t)m * n;
       double* wv = Qo_ + (size_t)(m + 1) * n;
-      if (opt.use_fd_jvp) {
-        // (r(theta + delta q) - r(theta)) / delta, the paper's product
-        copy(n, x, w2_, s);
-        axpby(n, delta, q, 1.0, w2_, s);
-        eng_.residual(w2_, w2_ + ov, w_, w_ + ov, s);
-        axpby(n, -1.0 / delta, r_, 1.0 / delta, w_, s);
+      if (gauge_ && !opt.use_fd_jvp && opt.protocol == PnkOptions::kPNK) {
+        // A_F^-1 J in the gauge is (W^T)^(x4) A_F^-1 J (W^-T)^(x4): the
+        // transforms between the two products cancel
+        const Gauge& g = *gauge_;
+        gauge_apply(o, vir, g.bwd_o, g.bwd_v, q, g.w1, g.ta, g.tb, s);
+        eng_.jvp(g.w1, g.w1 + ov, g.w2, g.w2 + ov, opt.jvp_prec, s);
+        st->n_jvp++;
+        mask(g.w2);
+        bool conv = true;
+        const int it = precond_solve(g.w2, g.w1, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
+        st->n_afmv += it;
+        st->n_inner_iters += it;
+        mask(g.w1);
+        gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w1, wv, g.ta, g.tb, s);
       } else {
-        eng_.jvp(q, q + ov, w_, w_ + ov, opt.jvp_prec, s);
+        if (opt.use_fd_jvp) {
+          // (r(theta + delta q) - r(theta)) / delta, the paper's product
+          copy(n, x, w2_, s);
+          axpby(n, delta, q, 1.0, w2_, s);
+          g_residual(w2_, w_, s);
+          axpby(n, -1.0 / delta, r_, 1.0 / delta, w_, s);
+        } else if (gauge_) {
+          const Gauge& g = *gauge_;
+          gauge_apply(o, vir, g.bwd_o, g.bwd_v, q, g.w1, g.ta, g.tb, s);
+          eng_.jvp(g.w1, g.w1 + ov, g.w2, g.w2 + ov, opt.jvp_prec, s);
+          gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w2, w_, g.ta, g.tb, s);
+        } else {
+          eng_.jvp(q, q + ov, w_, w_ + ov, opt.jvp_prec, s);
+        }
+        st->n_jvp++;
+        mask(w_);
+        Ainv(w_, wv);
       }
-      st->n_jvp++;
-      mask(w_);
-      Ainv(w_, wv);
       const double hn = orthogonalise(Qo_, n, m + 1, wv, h, s);
       for (int i = 0; i <= m; ++i) H[i + (size_t)m * (M + 1)] = h[i];
       for (int i = 0; i < m; ++i) {
@@ -972,7 +1031,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     ++k;
   }
   st->newton_iters = k;
-  eng_.energy(x, x + ov, dsc_, s);
+  g_energy(x, dsc_, s);
   read_scalars(host_, dsc_, 1, s);
   st->e_corr = host_[0];
   st->seconds = now_s() - t0;
@@ -987,6 +1046,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
 double Solver::fp_spectral_radius(const double* t, const double* q0, double shift, int m, hipStream_t s,
                                   std::vector<double>* ritz_re, std::vector<double>* ritz_im) {
   PNK_REQUIRE(m >= 1 && m <= m_max_, "fp_spectral_radius: m exceeds the allocated basis");
+  PNK_REQUIRE(!gauge_, "fp_spectral_radius: orbital basis only");
   const int64_t n = n_;
   const int o = eng_.o(), vir = eng_.v();
   const int64_t ov = (int64_t)o * vir;
@@ -1032,38 +1092,70 @@ double Solver::fp_spectral_radius(const double* t, const double* q0, double shif
 }
 
 namespace {
-// Bordered Pulay system [B -1; -1 0][c; l] = [0; -1] by Gaussian elimination
-// with partial pivoting; returns false when it is numerically singular.
+// Bordered Pulay system [B -1; -1 0][c; l] = [0; -1] in the least-squares,
+// minimum-norm sense (the pseudo-inverse): the bordered matrix is
+// symmetric, so its singular values are the moduli of its eigenvalues,
+// found by cyclic Jacobi rotations; components along eigenvalues below
+// eps (m + 1) times the largest modulus are dropped (the usual SVD cutoff
+// of a least-squares solver). Near convergence B shrinks with the squared
+// error norms while the border stays 1, so an elimination with an
+// absolute pivot test would declare it singular long before it is.
+// Returns false only for a non-finite result.
 bool pulay_solve(const std::vector<double>& B, int m, std::vector<double>& c) {
   const int n = m + 1;
-  std::vector<double> A((size_t)n * n, 0.0), rhs(n, 0.0);
+  std::vector<double> A((size_t)n * n, 0.0), V((size_t)n * n, 0.0), rhs(n, 0.0);
   for (int i = 0; i < m; ++i)
     for (int j = 0; j < m; ++j) A[(size_t)i * n + j] = B[(size_t)i * m + j];
   for (int i = 0; i < m; ++i) { A[(size_t)i * n + m] = -1.0; A[(size_t)m * n + i] = -1.0; }
   rhs[m] = -1.0;
-  double scale = 0.0;
-  for (double a : A) scale = std::max(scale, std::fabs(a));
-  for (int col = 0; col < n; ++col) {
-    int piv = col;
-    for (int r = col + 1; r < n; ++r)
-      if (std::fabs(A[(size_t)r * n + col]) > std::fabs(A[(size_t)piv * n + col])) piv = r;
-    if (std::fabs(A[(size_t)piv * n + col]) <= 1e-14 * scale) return false;
-    if (piv != col) {
-      for (int j = 0; j < n; ++j) std::swap(A[(size_t)piv * n + j], A[(size_t)col * n + j]);
-      std::swap(rhs[piv], rhs[col]);
-    }
-    for (int r = col + 1; r < n; ++r) {
-      const double f = A[(size_t)r * n + col] / A[(size_t)col * n + col];
-      for (int j = col; j < n; ++j) A[(size_t)r * n + j] -= f * A[(size_t)col * n + j];
-      rhs[r] -= f * rhs[col];
-    }
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+  auto a = [&](int i, int j) -> double& { return A[(size_t)i * n + j]; };
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a(i, j) * a(i, j);
+        if (i != j) off += a(i, j) * a(i, j);
+      }
+    if (!(off > 1e-32 * tot)) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a(p, q);
+        if (apq == 0.0) continue;
+        // rotation that zeroes A[p][q] (Golub & Van Loan, symmetric Schur)
+        const double tau = (a(q, q) - a(p, p)) / (2.0 * apq);
+        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+        const double cs = 1.0 / std::sqrt(1.0 + tt * tt), sn = tt * cs;
+        for (int k = 0; k < n; ++k) {
+          const double akp = a(k, p), akq = a(k, q);
+          a(k, p) = cs * akp - sn * akq;
+          a(k, q) = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = a(p, k), aqk = a(q, k);
+          a(p, k) = cs * apk - sn * aqk;
+          a(q, k) = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+          V[(size_t)k * n + p] = cs * vkp - sn * vkq;
+          V[(size_t)k * n + q] = sn * vkp + cs * vkq;
+        }
+      }
   }
-  std::vector<double> sol(n);
-  for (int i = n - 1; i >= 0; --i) {
-    double acc = rhs[i];
-    for (int j = i + 1; j < n; ++j) acc -= A[(size_t)i * n + j] * sol[j];
-    sol[i] = acc / A[(size_t)i * n + i];
+  double smax = 0.0;
+  for (int i = 0; i < n; ++i) smax = std::max(smax, std::fabs(a(i, i)));
+  const double cut = 2.220446049250313e-16 * n * smax;
+  std::vector<double> sol(n, 0.0);
+  for (int e = 0; e < n; ++e) {
+    const double lam = a(e, e);
+    if (!(std::fabs(lam) > cut)) continue;
+    double proj = 0.0;
+    for (int k = 0; k < n; ++k) proj += V[(size_t)k * n + e] * rhs[k];
+    for (int k = 0; k < n; ++k) sol[k] += V[(size_t)k * n + e] * proj / lam;
   }
+  for (double x : sol)
+    if (!std::isfinite(x)) return false;
   c.assign(sol.begin(), sol.begin() + m);
   return true;
 }
@@ -1079,12 +1171,16 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
   auto mask = [&](double* y) {
     if (opt.ccd) fill(ov, 0.0, y, s);
   };
+  // Jacobi denominators from the diagonals of the Fock blocks of the
+  // gauge the iteration runs in
+  const double* fo = gauge_ ? gauge_->Fo : eng_.f_oo();
+  const double* fv = gauge_ ? gauge_->Fv : eng_.f_vv();
   if (opt.init_mp2) {
-    eng_.residual(eng_.zeros(), eng_.zeros() + ov, r_, r_ + ov, s);
+    g_residual(eng_.zeros(), r_, s);
     st->n_residual++;
     mask(r_);
     bool conv = true;
-    const int it = precond_solve(r_, x, opt.inner_rtol, 200, restart_, s, &conv, true);
+    const int it = g_precond(r_, x, opt.inner_rtol, 200, restart_, s, &conv);
     st->n_afmv += it;
     st->n_inner_iters += it;
     axpby(n, 0.0, x, -1.0, x, s);
@@ -1095,7 +1191,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
   std::vector<double> Bfull((size_t)std::max(nd, 1) * std::max(nd, 1), 0.0);
   int it = 0;
   while (true) {
-    eng_.residual(x, x + ov, r_, r_ + ov, s);
+    g_residual(x, r_, s);
     st->n_residual++;
     mask(r_);
     double rinf, rn;
@@ -1109,7 +1205,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     if (rinf < opt.tol_inf) { st->converged = 1; break; }
     if (it >= opt.max_iter || rn > 1e6) break;
     if (nd == 0) {
-      jacobi_update(eng_.o(), eng_.v(), eng_.f_oo(), eng_.f_vv(), opt.level_shift, r_, x, nullptr, s);
+      jacobi_update(eng_.o(), eng_.v(), fo, fv, opt.level_shift, r_, x, nullptr, s);
       ++it;
       continue;
     }
@@ -1125,7 +1221,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     double* xs = hx_ + (size_t)slot * n;
     double* es = he_ + (size_t)slot * n;
     copy(n, x, xs, s);
-    jacobi_update(eng_.o(), eng_.v(), eng_.f_oo(), eng_.f_vv(), opt.level_shift, r_, xs, es, s);
+    jacobi_update(eng_.o(), eng_.v(), fo, fv, opt.level_shift, r_, xs, es, s);
     // B row of the new error vector against every stored one (slot order)
     const int m = (int)slots.size();
     const int mm = std::max(nd, 1);
@@ -1154,7 +1250,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     ++it;
   }
   st->newton_iters = it;
-  eng_.energy(x, x + ov, dsc_, s);
+  g_energy(x, dsc_, s);
   read_scalars(host_, dsc_, 1, s);
   st->e_corr = host_[0];
   st->seconds = now_s() - t0;

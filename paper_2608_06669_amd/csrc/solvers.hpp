@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "ccsd.hpp"
+#include "gauge.hpp"
 
 namespace pnk {
 
@@ -84,6 +85,13 @@ class Solver {
   static constexpr int kPackedBlock = 4;   // steps per recorded block (packed layout, fused update)
   void solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s);
   void solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipStream_t s);
+  // Solve for the amplitudes of a non-orthogonal gauge (nullptr: the
+  // orbital basis, the default). solve_pnk and solve_fp_diis then iterate
+  // on gauge vectors: x, the residual, the stopping test and the FP
+  // denominators (diagonals of the gauge's Fock blocks) are the gauge's,
+  // while the engine works in the orbital basis between the transforms.
+  // The gauge's buffers must outlive the solves that use it.
+  void set_gauge(const Gauge* g) { gauge_ = g; }
 
   // Residual history (norm-2, norm-inf) per outer residual evaluation.
   const std::vector<double>& history() const { return hist_; }
@@ -131,6 +139,11 @@ class Solver {
   int lz_block_len() const;
   bool ensure_lanczos_graph(bool timed, int nb);
   std::vector<double> hist_;
+  const Gauge* gauge_ = nullptr;
+  // the maps the solvers iterate on, in the gauge when one is set
+  void g_residual(const double* x, double* r, hipStream_t s);
+  int g_precond(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s, bool* conv);
+  void g_energy(const double* x, double* e_dev, hipStream_t s);
 };
 
 }  // namespace pnk

@@ -323,6 +323,21 @@ def test_fp_diis_c1_matches_oracle(handle, lib):
     assert info6["n_residual"] == ia6.n_residual
 
 
+def test_fp_diis_in_a_rotated_gauge_matches_the_oracle(handle, lib):
+    """FP+DIIS where plain FP diverges (Haar-rotated C1): DIIS carries the
+    iteration down to 1e-9, past the point where the Pulay matrix (squared
+    error norms) is 1e-14 of its unit border, in the oracle's number of
+    steps (its Pulay system is solved in the least-squares sense)."""
+    p = make_problem(4, 16, 48, 1001, gauge="haar")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_fp_diis(P, tol_inf=1e-9, max_iter=300)
+    a1, a2, ia = solvers.solve_fp_diis(*_args(p), tol=1e-9, max_iter=300)
+    assert info["status"] == "CC_OK" and ia.converged
+    assert abs(info["newton_iters"] - ia.newton_iters) <= 2
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-8
+    assert np.abs(host(t2) - a2).max() < 1e-7
+
+
 @pytest.mark.parametrize("ccd", [False, True])
 def test_protocols_match_the_oracle(handle, lib, ccd):
     """The method table on the device: PNK, NK (no preconditioner) and INK
