@@ -406,13 +406,73 @@ def bench_levelshift(args):
     h.close()
 
 
+def bench_gauge(args):
+    """Solves in non-orthogonal gauges (gauge functions chi = phi W per
+    orbital block, cond(W) = kappa): on C1 (canonical orbitals, where FP
+    converges) PNK, FP and FP+DIIS(8) in gauges of growing kappa, all from
+    the MP2 start; on C2 (Haar-rotated) PNK in the kappa = 4 gauge beside the
+    orbital-basis PNK solve (same root, transformed). One JSON line."""
+    import torch
+
+    import paper_2608_06669_amd as pk
+    from gen import GAUGE_WORKLOAD, make_config, nonorthogonal_gauge
+
+    pk.load()
+    h = pk.Handle(0)
+    out = {"workload": "non-orthogonal gauges: c1_canonical at cond(W) 1..16, c2_haar at cond(W) 4", "runs": []}
+
+    def rec(cfg, kappa, name, info, dt):
+        r = {"config": cfg, "cond_W": kappa, "solver": name, "converged": info["status"] == "CC_OK",
+             "residual_evaluations": info["n_residual"] + info["n_jvp"], "n_jvp": info["n_jvp"],
+             "n_afmv": info["n_afmv"], "steps": info["newton_iters"], "seconds": dt, "e_corr": info["e_corr"],
+             "res_inf": info["res_inf"]}
+        out["runs"].append(r)
+        print(f"{cfg} cond {kappa} {name}: {r}", file=sys.stderr, flush=True)
+
+    def timed(fn, *a, **kw):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = fn(*a, **kw)
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    p = make_config("c1_canonical")
+    tol = p.meta["tol"]
+    P = pk.DeviceProblem.from_problem(p)
+    for kappa in (1.0, 2.0, 4.0, 8.0, 16.0):
+        G = pk.DeviceGauge(*nonorthogonal_gauge(p.nocc, p.nvir, GAUGE_WORKLOAD["gauge_seed"], kappa))
+        (_, _, info), dt = timed(h.solve_pnk_gauge, P, G, tol_inf=tol, max_newton=args.max_newton)
+        rec("c1_canonical", kappa, "PNK", info, dt)
+        (_, _, info), dt = timed(h.solve_fp_diis_gauge, P, G, tol_inf=tol, diis_size=0, max_iter=500)
+        rec("c1_canonical", kappa, "FP", info, dt)
+        (_, _, info), dt = timed(h.solve_fp_diis_gauge, P, G, tol_inf=tol, max_iter=500)
+        rec("c1_canonical", kappa, "FP+DIIS", info, dt)
+    cfg = GAUGE_WORKLOAD["config"]
+    p = make_config(cfg)
+    tol = p.meta["tol"]
+    P = pk.DeviceProblem.from_problem(p)
+    kappa = GAUGE_WORKLOAD["cond"]
+    G = pk.DeviceGauge(*nonorthogonal_gauge(p.nocc, p.nvir, GAUGE_WORKLOAD["gauge_seed"], kappa))
+    h.solve_pnk(P, tol_inf=tol, max_newton=args.max_newton)  # warm-up: graphs and integrals
+    (_, _, info), dt = timed(h.solve_pnk, P, tol_inf=tol, max_newton=args.max_newton)
+    rec(cfg, 1.0, "PNK (orbital basis)", info, dt)
+    h.solve_pnk_gauge(P, G, tol_inf=tol, max_newton=args.max_newton)
+    (_, _, info), dt = timed(h.solve_pnk_gauge, P, G, tol_inf=tol, max_newton=args.max_newton)
+    rec(cfg, kappa, "PNK", info, dt)
+    (_, _, info), dt = timed(h.solve_fp_diis_gauge, P, G, tol_inf=tol, max_iter=200)
+    rec(cfg, kappa, "FP+DIIS", info, dt)
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner", "protocols", "levelshift"],
+    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner", "protocols", "levelshift",
+                                                      "gauge"],
                     help="default: the bench line; the others print their own measurement line")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"], help="J v precision (c3/c4)")
     ap.add_argument("--max-newton", type=int, default=200)
@@ -435,6 +495,8 @@ def main():
         bench_protocols(args)
     elif args.workload == "levelshift":
         bench_levelshift(args)
+    elif args.workload == "gauge":
+        bench_gauge(args)
     else:
         bench_large(args)
 
