@@ -9,10 +9,10 @@ derived from the integrals is reused across steps. Inputs are resident in
 HBM when the timed region starts.
 
 Prints one JSON line. `roofline` is for the kernel that takes the largest
-share of the solve, the virtual-contraction A_F kernel of the inner Lanczos
-solve: its
-launches are timed with HIP event nodes inside the replayed graph, on the
-stream they run on, over the timed region.
+share of the solve, the fused first kernel of the inner Lanczos step (the
+previous step's update and the A_F virtual contractions on the packed
+pairs): its launches are timed with HIP event nodes inside the replayed
+graph, on the stream they run on, over the timed region.
 """
 
 from __future__ import annotations
@@ -29,12 +29,12 @@ sys.path.insert(0, ROOT)
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2_haar"
-# HBM bytes per launch of the occupied A_F kernel (packed pair layout) on
-# this workload, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes in
-# profiles/fock_occ_packed_kernel_c2_haar_counters.md (each scaled by the
-# same counter for a copy kernel of known size). None when the kernel has
-# changed since the counters were taken.
-FOCK_OCC_TRAFFIC_BYTES = 23901157
+# HBM bytes per launch of the fused first kernel of the inner Lanczos step
+# (packed pair layout) on this workload, from the rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes in profiles/fock_vir_lz_kernel_c2_haar_counters.md
+# (each scaled by the same counter for a copy kernel of known size). None
+# when the kernel has changed since the counters were taken.
+VIR_LZ_TRAFFIC_BYTES = 33163303
 
 
 def nominal_residual_flops(o, v, naux):
@@ -43,20 +43,23 @@ def nominal_residual_flops(o, v, naux):
             + 4 * o * o * v ** 3 + 4 * o ** 3 * v * v)
 
 
-def fock_occ_bytes(o, v):
-    """Algorithmic HBM bytes of one launch of the occupied A_F kernel in the
-    PNK solve's inner Lanczos step, on the packed pairs i <= j (o (o + 1) / 2
-    blocks of v^2): x, the virtual part y and v_{k-1} read and p written once
-    (FP64), for the doubles and the singles, plus f_vv (read by the singles)."""
+def fock_vir_lz_bytes(o, v):
+    """Algorithmic HBM bytes of one launch of the fused first kernel of the
+    inner Lanczos step on the packed pairs i <= j (n_l = o v + o (o + 1) / 2
+    v^2 FP64 elements per vector): p_{k-1}, v_{k-1}, w_{k-2}, w_{k-3} and
+    the iterate read and v_k, w_{k-1} and the iterate written once (8 vector
+    passes), the virtual part f_vv v_k + v_k f_vv of the doubles written,
+    f_vv read."""
     npair = o * (o + 1) // 2
-    return 8 * (4 * npair * v * v + 4 * o * v + v * v)
+    nl = o * v + npair * v * v
+    return 8 * (8 * nl + npair * v * v + v * v)
 
 
-def fock_occ_flops(o, v):
-    """Its flops: per packed doubles element 2o multiply-adds (the two
-    occupied contractions); per singles element v + o."""
+def fock_vir_lz_flops(o, v):
+    """Its flops: two v-deep products per packed doubles block (4 v^3) and
+    about 8 per element for the update."""
     npair = o * (o + 1) // 2
-    return 4 * o * npair * v * v + 2 * o * v * (v + o)
+    return 4 * npair * v ** 3 + 8 * (o * v + npair * v * v)
 
 
 def cpu_baseline(problem, counts, t1_gpu, t2_gpu, e_gpu):
@@ -148,16 +151,16 @@ def bench_c2(args):
     F_R = nominal_residual_flops(o, v, naux)
     res_ms = ms_res / max(n_res, 1)
     af_ms = ms_afm / n_afm if n_afm else None
-    af_bytes = fock_occ_bytes(o, v)
+    af_bytes = fock_vir_lz_bytes(o, v)
     roof = None
     if af_ms:
         gbs = af_bytes / (af_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": gbs / HBM_PEAK_GBS, "traffic": FOCK_OCC_TRAFFIC_BYTES,
-                "kernel": "fock_occ_packed_kernel (A_F occupied contractions, singles and Lanczos update on the "
-                          "packed pairs)",
+                "frac": gbs / HBM_PEAK_GBS, "traffic": VIR_LZ_TRAFFIC_BYTES,
+                "kernel": "fock_vir_lz_kernel (inner Lanczos step on the packed pairs: the previous step's "
+                          "update fused with the A_F virtual contractions)",
                 "launches": n_afm, "avg_us": af_ms * 1e3, "bytes_per_launch": af_bytes,
-                "flops_per_launch": fock_occ_flops(o, v)}
+                "flops_per_launch": fock_vir_lz_flops(o, v)}
     out = {
         "metric": "PNK CCSD solves/s + p50/p99 latency at |dE|<1e-6 Eh; residual TFLOP/s vs FP64",
         "value": args.steps / elapsed,
@@ -185,7 +188,7 @@ def bench_c2(args):
         "precond_solve_ms": ms_pre / n_pre if n_pre else None,
         "time_share": {"residual": ms_res / (1000 * elapsed), "jvp": ms_jvp / (1000 * elapsed),
                        "precond_solve": ms_pre / (1000 * elapsed),
-                       "A_F_occupied_kernel": ms_afm / (1000 * elapsed)},
+                       "A_F_fused_virtual_kernel": ms_afm / (1000 * elapsed)},
         "roofline": roof,
     }
     if not args.no_cpu_baseline:

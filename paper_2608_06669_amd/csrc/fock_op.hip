@@ -574,11 +574,17 @@ __global__ __launch_bounds__(256) void fock_occ_packed_kernel(OccPackedArgs p) {
     };
     const int first = part + ps * g0;
     if (active) fetch(first);  // in flight during the staging
-    for (int q = tid; q < npair * ns; q += 256) {
-      const int pr = q / ns, sq = q % ns;
-      const int rq = sq < tt ? sq : sq - tt;
-      const int aq = (sq < tt ? a0 : b0) + rq / t, bq = (sq < tt ? b0 : a0) + rq % t;
-      xs[q] = (aq < v && bq < v) ? p.x2[(int64_t)pr * vv + (int64_t)aq * v + bq] : 0.0;
+    {
+      // ns divides 256 (ns = t^2 or 2 t^2, t in {2, 4, 8}), so this thread
+      // stages the same tile element s of packed pairs g0, g0 + 256 / ns, ...
+      const bool inb = a < v && b < v;
+      const double* src = p.x2 + (int64_t)g0 * vv + (int64_t)a * v + b;
+      const int64_t step = (int64_t)groups * vv;
+      for (int pr = g0; pr < npair; pr += groups, src += step) {
+        double x = 0.0;
+        if (inb) x = *src;
+        xs[pr * ns + s] = x;
+      }
     }
     for (int q = tid; q < o * o; q += 256) {
       fo[q] = p.f_oo[q];
@@ -750,9 +756,17 @@ bool fock_op_plan(FockOp& op) {
   return (int64_t)op.tiles * op.o * op.o < (1ll << 31) - 8 && op.nparts() <= 0x7fffffff;
 }
 
-bool fock_op_is_occupied_lanczos_kernel(const void* func) {
-  return func == reinterpret_cast<const void*>(&fock_occ_packed_kernel) ||
-         func == reinterpret_cast<const void*>(&fock_occ_kernel<true>);
+bool fock_op_is_timed_lanczos_kernel(const void* func) {
+  const void* timed[] = {reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 16>),
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 32>),
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<48, 4, 16>),
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<48, 4, 32>),
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<64, 2, 16>),
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<64, 2, 32>),
+                         reinterpret_cast<const void*>(&fock_occ_kernel<true>)};
+  for (const void* k : timed)
+    if (func == k) return true;
+  return false;
 }
 
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s) {

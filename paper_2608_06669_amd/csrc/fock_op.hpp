@@ -93,8 +93,9 @@ void fock_op_lanczos_vir_fused(const FockOp& op, const double* P, const double* 
                                double* w2, double* x, const double* partials, int nparts, const double* st,
                                double* stn, double* fin, hipStream_t s);
 
-// True for the occupied kernel of either Lanczos form (the launch timed
-// in a recorded graph).
-bool fock_op_is_occupied_lanczos_kernel(const void* func);
+// True for the launch of a Lanczos step that is timed in a recorded graph:
+// the fused first launch (fock_op_lanczos_vir_fused) on the packed layout,
+// the occupied launch on the full one.
+bool fock_op_is_timed_lanczos_kernel(const void* func);
 
 }  // namespace pnk

@@ -498,10 +498,11 @@ void Solver::lanczos_block(hipStream_t s) {
     for (int k = 0; k < kPackedBlock; ++k) {
       double* prev = st + ((k + 1) % 2) * kStateStride;  // state after step k-1
       double* cur = st + (k % 2) * kStateStride;         // state after step k
-      fock_op_lanczos_vir_fused(op, P, V, N, Y, w1, w2, x, partials_, np, prev, cur, fin, s);
+      // the timer covers the fused launch (the larger of the two)
       if (tm) tm->begin(kTimerFock, s);
-      fock_op_lanczos_occ_packed(op, N, V, cur + kBeta, Y, partials_, kInnerSinglesScale, cur + kDone, s);
+      fock_op_lanczos_vir_fused(op, P, V, N, Y, w1, w2, x, partials_, np, prev, cur, fin, s);
       if (tm) tm->end(kTimerFock, s);
+      fock_op_lanczos_occ_packed(op, N, V, cur + kBeta, Y, partials_, kInnerSinglesScale, cur + kDone, s);
       double* oldP = P;
       P = Y;     // p_k
       Y = V;     // free
@@ -546,8 +547,8 @@ std::vector<hipGraphNode_t> chain_order(hipGraph_t g) {
   return out;
 }
 
-// Inserts event record nodes before and after each occupied A_F kernel
-// node (the Lanczos form) of a chain graph: pair k (events ev[2k],
+// Inserts event record nodes before and after each timed A_F kernel node
+// (fock_op_is_timed_lanczos_kernel) of a chain graph: pair k (events ev[2k],
 // ev[2k+1]) brackets the k-th such launch in stream order, so its duration
 // can be read after a replay. Returns the number of pairs, -1 on failure.
 int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
@@ -560,7 +561,7 @@ int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
     if (type != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams kp{};
     if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) return -1;
-    if (!fock_op_is_occupied_lanczos_kernel(kp.func)) continue;
+    if (!fock_op_is_timed_lanczos_kernel(kp.func)) continue;
     if (k >= max_pairs) return -1;
     size_t nd = 0, ns = 0;
     if (hipGraphNodeGetDependencies(node, nullptr, &nd) != hipSuccess) return -1;
@@ -695,9 +696,10 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   // (as one recorded graph), later ones a block each. The device stops the
   // recurrence at the first step that meets the test, so the batch size
   // changes the cost only, never the result. With timing on, the event
-  // pairs of the occupied launches that ran are read (in the packed form a
-  // step's update completes in the next step's first launch, so an
-  // unfinished batch has run one more occupied launch than updates).
+  // pairs of the timed launches that ran are read: the occupied launches
+  // of the full layout (one per step), the fused first launches of the
+  // packed one (one per step plus the normalising first launch; a step's
+  // update completes in the next step's first launch).
   int batch = std::min(std::max(1, (int)ceil_div(lz_steps_hint_ + (packed ? 1 : 0), len)), (int)kMaxBatchBlocks);
   int launched = 0, steps = 0;
   bool conv = false;
@@ -720,7 +722,7 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
     const double res = host_[kFinRes], bn = host_[kFinBNorm];
     const bool ok = std::isfinite(res) && (res <= rtol * bn || host_[kFinBeta] == 0.0);
     if (timed) {
-      const int ran_total = std::min(launched, (packed && !ok) ? steps + 1 : steps);
+      const int ran_total = std::min(launched, packed ? steps + 1 : steps);
       const int ran = std::min(nb * len, ran_total - before);
       for (int k = 0; k < ran; ++k) {
         float ms = 0.f;
