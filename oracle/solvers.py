@@ -411,15 +411,16 @@ def solve_fp_diis(f_oo, f_ov, f_vv, L, tol=1e-8, max_iter=500, diis_size=8,
 
 
 def solve_ink(f_oo, f_ov, f_vv, L, tol=1e-8, max_iter=200, inner_rtol=1e-12,
-              inner_maxit=200, inner_restart=30, x0=None, ccd=False, diverge=1e6):
+              inner_maxit=200, inner_restart=30, x0=None, ccd=False, diverge=1e6, gauge=None):
     """INK (method table): the Newton update with A_F in place of the
     Jacobian, A_F dt = -r(t) (equation inexact_newton_update), solved by
     GMRES; t <- t + dt until ||r||_inf < tol. Starts from the MP2 amplitudes
     -A_F^-1 r(0) unless x0 is given. In the canonical gauge A_F is the
     diagonal of orbital-energy differences and INK is the plain FP
-    iteration."""
+    iteration. gauge=(W_o, W_v) iterates on the amplitudes of that gauge
+    with its A_F."""
     t_start = time.perf_counter()
-    P = _Problem(f_oo, f_ov, f_vv, L, ccd)
+    P = _make_problem(f_oo, f_ov, f_vv, L, ccd, gauge)
     info = SolveInfo()
     N = P.o * P.v + P.o ** 2 * P.v ** 2
     if x0 is not None:

@@ -231,10 +231,11 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
   if ((int)blockIdx.x < dwg && u >= p.units) return;  // padding of the XCD grouping
 
   // The elements this workgroup updates: its own output tile, or for the
-  // trailing workgroups 1024 singles. Their loads are issued before the
-  // scalars are formed, so both latencies overlap.
-  constexpr int EPT = (BM * BN + 255) / 256;
-  static_assert(EPT >= 4, "the singles workgroups need four elements per thread");
+  // trailing workgroups 1024 singles, in batches of EB per thread. The
+  // first batch's loads are issued before the scalars are formed, so both
+  // latencies overlap; larger tiles stream their further batches after.
+  constexpr int EB = 4;
+  constexpr int NB = (BM * BN + 256 * EB - 1) / (256 * EB);
   const int v = p.v;
   const int64_t vv = (int64_t)v * v;
   const bool singles_wg = (int)blockIdx.x >= dwg;
@@ -248,28 +249,31 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
   double* __restrict__ gW2 = p.w2;
   double* __restrict__ gX = p.x;
   double* __restrict__ gVn = p.Vn;
-  int64_t idx[EPT];
-  double ep[EPT], ev[EPT], e1[EPT], e2[EPT], ex[EPT];
+  int64_t idx[EB];
+  double ep[EB], ev[EB], e1[EB], e2[EB], ex[EB];
+  auto load_batch = [&](int bt) {
 #pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    const int q = tid + 256 * j;
-    idx[j] = -1;
-    if (singles_wg) {
-      const int64_t e = (int64_t)(blockIdx.x - dwg) * 1024 + q;
-      if (q < 1024 && e < p.ov) idx[j] = e;
-    } else {
-      const int gm = m0 + q / BN, gn = n0 + q % BN;
-      if (q < BM * BN && gm < v && gn < v) idx[j] = off + (int64_t)gm * v + gn;
+    for (int j = 0; j < EB; ++j) {
+      const int q = tid + 256 * (bt * EB + j);
+      idx[j] = -1;
+      if (singles_wg) {
+        const int64_t e = (int64_t)(blockIdx.x - dwg) * 1024 + q;
+        if (q < 1024 && e < p.ov) idx[j] = e;
+      } else {
+        const int gm = m0 + q / BN, gn = n0 + q % BN;
+        if (q < BM * BN && gm < v && gn < v) idx[j] = off + (int64_t)gm * v + gn;
+      }
+      ep[j] = ev[j] = e1[j] = e2[j] = ex[j] = 0.0;
+      if (idx[j] >= 0) {
+        ep[j] = gP[idx[j]];
+        ev[j] = gV[idx[j]];
+        e1[j] = gW1[idx[j]];
+        e2[j] = gW2[idx[j]];
+        ex[j] = gX[idx[j]];
+      }
     }
-    ep[j] = ev[j] = e1[j] = e2[j] = ex[j] = 0.0;
-    if (idx[j] >= 0) {
-      ep[j] = gP[idx[j]];
-      ev[j] = gV[idx[j]];
-      e1[j] = gW1[idx[j]];
-      e2[j] = gW2[idx[j]];
-      ex[j] = gX[idx[j]];
-    }
-  }
+  };
+  load_batch(0);
 
   // scalars (every workgroup, same bits)
   double r3[3] = {0.0, 0.0, 0.0};
@@ -334,17 +338,24 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
       p.fin[kLzFinBeta] = betan;
     }
   }
+  auto apply_batch = [&]() {
 #pragma unroll
-  for (int j = 0; j < EPT; ++j) {
-    if (idx[j] < 0) continue;
-    gVn[idx[j]] = (ep[j] - alpha * ev[j]) * invb;
-    if (!first) {
-      const double w = (ev[j] - delta * e1[j] - eps * e2[j]) * ir;
-      gW2[idx[j]] = w;
-      gX[idx[j]] = ex[j] + phi * w;
+    for (int j = 0; j < EB; ++j) {
+      if (idx[j] < 0) continue;
+      gVn[idx[j]] = (ep[j] - alpha * ev[j]) * invb;
+      if (!first) {
+        const double w = (ev[j] - delta * e1[j] - eps * e2[j]) * ir;
+        gW2[idx[j]] = w;
+        gX[idx[j]] = ex[j] + phi * w;
+      }
     }
+  };
+  apply_batch();
+  if (singles_wg) return;  // 1024 singles: one batch
+  for (int bt = 1; bt < NB; ++bt) {
+    load_batch(bt);
+    apply_batch();
   }
-  if (singles_wg) return;
   if (done_now) return;  // converged: y_k is not needed
 
   const int lane = tid & 63;

@@ -135,6 +135,32 @@ def test_gauge_fp_diis_matches_the_oracle(handle, lib):
     assert info0["status"] != "CC_OK" and not ia0.converged
 
 
+@pytest.mark.parametrize("ccd", [False, True])
+def test_gauge_protocols_match_the_oracle(handle, lib, ccd):
+    """The method table in a cond-4 gauge, at the CCSD and the CCD level: PNK,
+    NK and INK on the device against the oracle's same protocols in the same
+    gauge (same steps, root and energy)."""
+    p = make_problem(3, 7, 14, 97, gauge="haar")
+    Wo, Wv = nonorthogonal_gauge(3, 7, 2006, 4.0)
+    P, G = lib.DeviceProblem.from_problem(p), lib.DeviceGauge(Wo, Wv)
+    cases = {"pnk": ({}, dict()), "nk": ({"max_newton": 200}, dict(precond=False, max_newton=200))}
+    for name, (gopt, oopt) in cases.items():
+        th1, th2, info = handle.solve_pnk_gauge(P, G, tol_inf=1e-10, protocol=name, ccd=int(ccd), **gopt)
+        a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-10, ccd=ccd, gauge=(Wo, Wv), **oopt)
+        assert info["status"] == "CC_OK" and ia.converged, name
+        assert abs(info["e_corr"] - ia.e_corr) < 1e-9, name
+        assert np.abs(host(th2) - a2).max() < 1e-8 and np.abs(host(th1) - a1).max() < 1e-8, name
+        assert info["newton_iters"] == ia.newton_iters, name
+        if ccd:
+            assert not np.any(host(th1)), name
+    th1, th2, info = handle.solve_pnk_gauge(P, G, tol_inf=1e-10, protocol="ink", ccd=int(ccd), max_newton=200)
+    a1, a2, ia = solvers.solve_ink(*_args(p), tol=1e-10, ccd=ccd, gauge=(Wo, Wv))
+    assert info["status"] == "CC_OK" and ia.converged
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-9
+    assert np.abs(host(th2) - a2).max() < 1e-8
+    assert info["newton_iters"] == ia.newton_iters and info["n_jvp"] == 0
+
+
 def test_orthogonal_gauge_solve_equals_the_rotated_problem(handle, lib):
     """With orthogonal W the gauge solve is the orbital solve of the
     Hamiltonian rotated by W^T."""

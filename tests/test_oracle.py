@@ -482,3 +482,19 @@ def test_gauge_pnk_lands_on_the_transformed_root():
     assert ia.converged and ib.converged
     assert np.abs(a1 - c1).max() < 1e-9 and np.abs(a2 - c2).max() < 1e-9
     assert abs(ia.e_corr - ib.e_corr) < 1e-10
+
+
+def test_gauge_ink_is_the_orbital_ink_transformed():
+    """INK's update t <- t - A_F^-1 r(t) is covariant: in any invertible
+    gauge its iterates are the transformed orbital-basis iterates (A_F of the
+    gauge is the similarity transform of A_F), at the CCD level too."""
+    from gen import nonorthogonal_gauge
+    from oracle import gauge
+    p = make_problem(3, 7, 20, 1105, gauge="haar")
+    Wo, Wv = nonorthogonal_gauge(3, 7, 2005, 4.0)
+    for ccd in (False, True):
+        a1, a2, ia = solvers.solve_ink(*_args(p), tol=1e-30, max_iter=3, ccd=ccd, gauge=(Wo, Wv))
+        b1, b2, ib = solvers.solve_ink(*_args(p), tol=1e-30, max_iter=3, ccd=ccd)
+        c1, c2 = gauge.forward(Wo, Wv, b1, b2)
+        assert ia.newton_iters == ib.newton_iters == 3
+        assert np.abs(a2 - c2).max() < 1e-10 and np.abs(a1 - c1).max() < 1e-10
