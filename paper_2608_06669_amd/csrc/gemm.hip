@@ -353,9 +353,13 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   int splits = 1;
   const int64_t tiles = (int64_t)p.tiles_m * p.tiles_n * nb;
   // (short contractions are not split: the extra pass over the partial sums
-  // would cost more than the product)
+  // would cost more than the product). About 900 workgroups in all (3.5 per
+  // CU): for the o v x o v products of the rotated 10/90 workload that is 4
+  // chunks, 10 % faster than 3 (a sweep over 3..12); thin products with a
+  // long contraction stay near 512 (8 chunks for the ladder, its best).
   if (d.ws && tiles < 256 && d.K >= 256) {
-    int64_t want = ceil_div(512, tiles);
+    const bool thin = d.M <= 64 && d.K >= 1024;
+    int64_t want = ceil_div(thin ? 512 : 900, tiles);
     want = std::min<int64_t>(want, d.K / (2 * BK));
     want = std::min<int64_t>(want, d.ws_elems / std::max<int64_t>(1, nb * d.M * d.N));
     want = std::min<int64_t>(want, 256);
