@@ -468,6 +468,68 @@ def bench_gauge(args):
     h.close()
 
 
+def bench_residual(args):
+    """Residual and FP64 J v evaluations alone (recorded graphs replayed) on
+    c2_haar and c4_mixed at seeded amplitudes, --steps of each, plus one
+    1024^3 FP64 product through cc_diag_gemm (2^31 flops). A torch
+    elementwise kernel runs before every evaluation and after the last, so
+    that a counter run (rocprofv3 --pmc) can attribute the dispatches
+    between two such markers to one evaluation; the 1024^3 product
+    calibrates the matrix-core operation counters. One JSON line."""
+    import torch
+
+    import paper_2608_06669_amd as pk
+    from gen import make_config, random_amplitudes
+
+    pk.load()
+    h = pk.Handle(0)
+    mark = torch.zeros(1, dtype=torch.float64, device="cuda")
+    out = {"workload": "residual and FP64 J v alone (c2_haar, c4_mixed)", "steps": args.steps, "configs": []}
+    A = torch.randn(1024, 1024, dtype=torch.float64, device="cuda")
+    B = torch.randn(1024, 1024, dtype=torch.float64, device="cuda")
+    C = torch.zeros(1024, 1024, dtype=torch.float64, device="cuda")
+    mark.add_(1.0)
+    pk.diag_gemm(A, B, C, (1024, 1), (1024, 1), (1024, 1), 1024, 1024, 1024)
+    mark.add_(1.0)
+    torch.cuda.synchronize()
+    for cfg in ("c2_haar", "c4_mixed"):
+        p = make_config(cfg)
+        o, v, naux = p.nocc, p.nvir, p.naux
+        P = pk.DeviceProblem.from_problem(p)
+        t1, t2 = (torch.as_tensor(a, device="cuda") for a in random_amplitudes(o, v, 77, scale=0.01))
+        q1, q2 = (torch.as_tensor(a, device="cuda") for a in random_amplitudes(o, v, 78, scale=1.0))
+        r1, r2 = torch.empty_like(t1), torch.empty_like(t2)
+        for _ in range(3):  # integrals, then the recorded graph
+            h.residual(P, t1, t2, r1, r2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mark.add_(1.0)
+            h.residual(P, t1, t2, r1, r2)
+        mark.add_(1.0)
+        torch.cuda.synchronize()
+        res_ms = 1000.0 * (time.perf_counter() - t0) / max(args.steps, 1)
+        y = (torch.empty_like(q1), torch.empty_like(q2))
+        for _ in range(3):
+            h.jvp(P, t1, t2, q1, q2, out=y)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mark.add_(1.0)
+            h.jvp(P, t1, t2, q1, q2, out=y)  # a residual (the linearisation point) and J v
+        mark.add_(1.0)
+        torch.cuda.synchronize()
+        rj_ms = 1000.0 * (time.perf_counter() - t0) / max(args.steps, 1)
+        F_R = nominal_residual_flops(o, v, naux)
+        rec = {"config": cfg, "nocc": o, "nvir": v, "naux": naux, "residual_ms": res_ms,
+               "residual_tflops_nominal": F_R / (res_ms * 1e-3) / 1e12, "nominal_residual_flops": F_R,
+               "residual_plus_jvp_ms": rj_ms, "jvp_ms": rj_ms - res_ms}
+        out["configs"].append(rec)
+        print(f"{cfg}: {rec}", file=sys.stderr, flush=True)
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -475,7 +537,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner", "protocols", "levelshift",
-                                                      "gauge"],
+                                                      "gauge", "residual"],
                     help="default: the bench line; the others print their own measurement line")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"], help="J v precision (c3/c4)")
     ap.add_argument("--max-newton", type=int, default=200)
@@ -500,6 +562,8 @@ def main():
         bench_levelshift(args)
     elif args.workload == "gauge":
         bench_gauge(args)
+    elif args.workload == "residual":
+        bench_residual(args)
     else:
         bench_large(args)
 
