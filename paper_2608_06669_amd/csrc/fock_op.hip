@@ -767,14 +767,18 @@ bool fock_op_plan(FockOp& op) {
   return (int64_t)op.tiles * op.o * op.o < (1ll << 31) - 8 && op.nparts() <= 0x7fffffff;
 }
 
-bool fock_op_is_timed_lanczos_kernel(const void* func) {
+bool fock_op_fused_step(const FockOp& op) { return op.pt > 0 && op.bm == 32; }
+
+bool fock_op_is_timed_lanczos_kernel(const void* func, bool fused) {
+  if (!fused)
+    return func == reinterpret_cast<const void*>(&fock_occ_kernel<true>) ||
+           func == reinterpret_cast<const void*>(&fock_occ_packed_kernel);
   const void* timed[] = {reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 16>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 32>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<48, 4, 16>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<48, 4, 32>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<64, 2, 16>),
-                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<64, 2, 32>),
-                         reinterpret_cast<const void*>(&fock_occ_kernel<true>)};
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<64, 2, 32>)};
   for (const void* k : timed)
     if (func == k) return true;
   return false;
@@ -800,6 +804,13 @@ void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev,
   PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
   const int64_t ov = (int64_t)op.o * op.v;
   launch_occ<true>(op, v, v + ov, p, p + ov, vprev, vprev + ov, beta, partials, singles_scale, done, s);
+}
+
+void fock_op_lanczos_vir_packed(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s) {
+  PNK_REQUIRE(op.bm > 0 && op.pt > 0, "fock_op: packed form not planned");
+  PNK_REQUIRE(v != p, "fock_op: output must not alias the input");
+  const int64_t ov = (int64_t)op.o * op.v;
+  launch_vir(op, op.npair, v + ov, p + ov, done, s);
 }
 
 void fock_op_lanczos_vir_fused(const FockOp& op, const double* P, const double* V, double* Vn, double* Y, double* w1,

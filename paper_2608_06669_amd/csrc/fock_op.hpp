@@ -61,7 +61,9 @@ void fock_op_lanczos_occ(const FockOp& op, const double* v, const double* vprev,
 // i o - i (i - 1) / 2 + j - i, each v*v]. The three partial sums are those
 // of the full vectors (the blocks of pairs i < j count twice); partials has
 // 3 op.nparts_packed() entries. The virtual part comes from
-// fock_op_lanczos_vir_fused below.
+// fock_op_lanczos_vir_packed (three-launch step: then a separate update) or
+// fock_op_lanczos_vir_fused below (two-launch step).
+void fock_op_lanczos_vir_packed(const FockOp& op, const double* v, double* p, const double* done, hipStream_t s);
 void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double* vprev, const double* beta, double* p,
                                 double* partials, double singles_scale, const double* done, hipStream_t s);
 
@@ -93,9 +95,16 @@ void fock_op_lanczos_vir_fused(const FockOp& op, const double* P, const double* 
                                double* w2, double* x, const double* partials, int nparts, const double* st,
                                double* stn, double* fin, hipStream_t s);
 
+// Whether the packed symmetric solve takes two launches per step (the
+// update fused into fock_op_lanczos_vir_fused): for 32-wide blocks, where
+// a workgroup's update is one batch of four elements per thread. Wider
+// blocks would stream several batches ahead of their matrix-core product,
+// so they keep the separate update launch (three launches per step).
+bool fock_op_fused_step(const FockOp& op);
+
 // True for the launch of a Lanczos step that is timed in a recorded graph:
-// the fused first launch (fock_op_lanczos_vir_fused) on the packed layout,
-// the occupied launch on the full one.
-bool fock_op_is_timed_lanczos_kernel(const void* func);
+// the fused first launch in the two-launch form (fused), else the occupied
+// launch.
+bool fock_op_is_timed_lanczos_kernel(const void* func, bool fused);
 
 }  // namespace pnk

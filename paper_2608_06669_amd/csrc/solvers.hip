@@ -407,8 +407,37 @@ __global__ __launch_bounds__(256) void lzp_unpack(int o, int v, const double* __
 // step 0 (slot 1) with the first flag; and, in place of the shares of an
 // occupied launch (occ_parts, occ_nparts each), (0, ||start||^2, 0), from
 // which the first fused step normalises the start vector.
-__global__ __launch_bounds__(256) void lzp_init(const double* __restrict__ parts, int nparts, double* st,
-                                                double* __restrict__ occ_parts, int occ_nparts, double rtol) {
+// Packed three-launch form: the state before the first step (slot 0) from
+// the packing's partial sums of ||b||^2 and ||D^1/2 b||^2; the start vector
+// is then normalised by ||D^1/2 b|| (fin's kFinBHat).
+__global__ __launch_bounds__(256) void lzp_init_normalised(const double* __restrict__ parts, int nparts, double* st,
+                                                           double rtol) {
+  __shared__ double sm[2][4];
+  double r[2] = {0.0, 0.0};
+  for (int k = threadIdx.x; k < nparts; k += 256) {
+    r[0] += parts[k];
+    r[1] += parts[nparts + k];
+  }
+  block_sum256<2>(r, sm);
+  if (threadIdx.x != 0) return;
+  const double bn = sqrt(r[0]), bhat = sqrt(r[1]);
+  for (int k = 0; k < kNState; ++k) st[k] = 0.0;
+  st[kC2] = 1.0;
+  st[kC1] = 1.0;
+  st[kPhiBar] = bhat;
+  st[kRes] = bhat;
+  st[kStateStride + kDone] = 0.0;
+  double* fin = st + 2 * kStateStride;
+  fin[kFinSteps] = 0.0;
+  fin[kFinRes] = bhat;
+  fin[kFinBeta] = 1.0;
+  fin[kFinTol] = rtol * bn;
+  fin[kFinBNorm] = bn;
+  fin[kFinBHat] = bhat;
+}
+
+__global__ __launch_bounds__(256) void lzp_init_fused(const double* __restrict__ parts, int nparts, double* st,
+                                                      double* __restrict__ occ_parts, int occ_nparts, double rtol) {
   __shared__ double sm[2][4];
   double r[2] = {0.0, 0.0};
   for (int k = threadIdx.x; k < nparts; k += 256) {
@@ -459,7 +488,16 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
   double* part1 = partials_;
   const FockOp* op = eng_.fock_op();
   int nparts1 = kLzBlocks;
-  if (op && op->nparts() <= kMaxFusedParts) {
+  if (lz_mode_ == kLzPacked3) {
+    // packed pair layout (see precond_solve_sym): the same three launches
+    n = ov + (int64_t)op->npair * eng_.v() * eng_.v();
+    Timers* tm = eng_.timers();
+    fock_op_lanczos_vir_packed(*op, v, p, st + kDone, s);
+    if (tm) tm->begin(kTimerFock, s);
+    fock_op_lanczos_occ_packed(*op, v, vprev, st + kBeta, p, part1, kInnerSinglesScale, st + kDone, s);
+    if (tm) tm->end(kTimerFock, s);
+    nparts1 = (int)op->nparts_packed();
+  } else if (op && op->nparts() <= kMaxFusedParts) {
     // p = A_F v_k - beta_k v_{k-1} and the partials of <v_k, p>; the timer
     // covers the occupied launch
     Timers* tm = eng_.timers();
@@ -480,12 +518,12 @@ void Solver::lanczos_step(double* vprev, double* v, double* p, double* w1, doubl
 // Six steps: the buffer rotation (v: period 3, w: period 2, state slot:
 // period 2) returns to its start, so the block can be recorded once as a
 // HIP graph and replayed.
-int Solver::lz_block_len() const { return lz_packed_ ? kPackedBlock : kLanczosBlock; }
+int Solver::lz_block_len() const { return lz_mode_ == kLzFused ? kPackedBlock : kLanczosBlock; }
 
 void Solver::lanczos_block(hipStream_t s) {
   const int64_t n = n_;
   double* st = lanczos_state();
-  if (lz_packed_) {
+  if (lz_mode_ == kLzFused) {
     // packed: two launches per step, the update fused into the next step's
     // virtual launch; four vectors rotate (P = p_{k-1}, V = v_{k-1}, N = v_k,
     // Y = y_k -> p_k), period 4; w rotates with period 2
@@ -551,7 +589,7 @@ std::vector<hipGraphNode_t> chain_order(hipGraph_t g) {
 // (fock_op_is_timed_lanczos_kernel) of a chain graph: pair k (events ev[2k],
 // ev[2k+1]) brackets the k-th such launch in stream order, so its duration
 // can be read after a replay. Returns the number of pairs, -1 on failure.
-int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
+int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs, bool fused) {
   const std::vector<hipGraphNode_t> nodes = chain_order(g);
   if (nodes.empty()) return -1;
   int k = 0;
@@ -561,7 +599,7 @@ int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
     if (type != hipGraphNodeTypeKernel) continue;
     hipKernelNodeParams kp{};
     if (hipGraphKernelNodeGetParams(node, &kp) != hipSuccess) return -1;
-    if (!fock_op_is_timed_lanczos_kernel(kp.func)) continue;
+    if (!fock_op_is_timed_lanczos_kernel(kp.func, fused)) continue;
     if (k >= max_pairs) return -1;
     size_t nd = 0, ns = 0;
     if (hipGraphNodeGetDependencies(node, nullptr, &nd) != hipSuccess) return -1;
@@ -592,8 +630,8 @@ int bracket_fock_nodes(hipGraph_t g, const hipEvent_t* ev, int max_pairs) {
 // engine's timers are on).
 bool Solver::ensure_lanczos_graph(bool timed, int nb) {
   if (nb < 1 || nb > kMaxBatchBlocks) return false;
-  hipGraphExec_t& exec = lz_graphs_[lz_packed_ ? 1 : 0][timed ? 1 : 0][nb];
-  bool& failed = lz_graph_failed_[lz_packed_ ? 1 : 0][timed ? 1 : 0][nb];
+  hipGraphExec_t& exec = lz_graphs_[lz_mode_][timed ? 1 : 0][nb];
+  bool& failed = lz_graph_failed_[lz_mode_][timed ? 1 : 0][nb];
   if (exec) return true;
   if (failed) return false;
   const int pairs = nb * lz_block_len();
@@ -620,7 +658,7 @@ bool Solver::ensure_lanczos_graph(bool timed, int nb) {
       if (std::getenv("PNK_DEBUG")) std::fprintf(stderr, "pnk: graph capture failed: %s\n", e.what());
     }
     if (hipStreamEndCapture(cs, &g) == hipSuccess && g && !threw &&
-        (!timed || bracket_fock_nodes(g, lz_ev_.data(), pairs) == pairs) &&
+        (!timed || bracket_fock_nodes(g, lz_ev_.data(), pairs, lz_mode_ == kLzFused) == pairs) &&
         hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess)
       ok = true;
   }
@@ -653,23 +691,38 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   double* st = lanczos_state();
   const double* fin = st + 2 * kStateStride;
   const FockOp* op = eng_.fock_op();
-  lz_packed_ = packed;
+  const int mode = !packed ? kLzFull : (fock_op_fused_step(*op) ? kLzFused : kLzPacked3);
+  lz_mode_ = mode;
   // scaled system D^1/2 A_F D^1/2 z = D^1/2 b, x = D^1/2 z, D = diag(s I, I).
   // ||b|| stays on the device (b = 0 gives a zero start and a stop at the
   // first step).
   double* xi;  // the iterate z
-  if (packed) {
+  if (mode == kLzPacked3) {
     // pair-symmetric b: the recurrence runs on pairs i <= j, with inner
     // products that count the blocks of pairs i < j twice (those of the full
-    // vectors), so its steps are those of the full-layout recurrence. The
-    // first fused step normalises the start vector P = D^1/2 b (V = 0).
+    // vectors), so its steps are those of the full-layout recurrence; the
+    // buffers are those of the full layout, n_l of each used
+    const int64_t nl = ov + (int64_t)op->npair * vir * vir;
+    double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n;
+    xi = Qi_ + 5 * n;
+    double* parts = partials_ + 3 * kMaxFusedParts;
+    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, xi, parts);
+    lzp_init_normalised<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, rtol);
+    scale_by_inverse(nl, xi, fin + kFinBHat, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
+    fill(nl, 0.0, vprev, s);
+    fill(nl, 0.0, w1, s);
+    fill(nl, 0.0, w2, s);
+    fill(nl, 0.0, xi, s);
+  } else if (mode == kLzFused) {
+    // the same on the two-launch form: the first fused step normalises the
+    // start vector P = D^1/2 b (V = 0)
     const int64_t nl = ov + (int64_t)op->npair * vir * vir;
     double *P0 = Qi_, *V0 = Qi_ + n, *w1 = Qi_ + 4 * n, *w2 = Qi_ + 5 * n;
     xi = Qi_ + 6 * n;
     double* parts = partials_ + 3 * kMaxFusedParts;
     lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, P0, parts);
-    lzp_init<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, partials_, (int)op->nparts_packed(),
-                                rtol);
+    lzp_init_fused<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, partials_,
+                                      (int)op->nparts_packed(), rtol);
     fill(nl, 0.0, V0, s);
     fill(nl, 0.0, w1, s);
     fill(nl, 0.0, w2, s);
@@ -690,27 +743,28 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   }
   PNK_CHECK_LAUNCH();
   Timers* tm = eng_.timers();
-  const bool fused = packed || (op && op->nparts() <= kMaxFusedParts);
+  const bool timeable = packed || (op && op->nparts() <= kMaxFusedParts);
   const int len = lz_block_len();
   // The first batch queues as many blocks as the last solve needed steps
   // (as one recorded graph), later ones a block each. The device stops the
   // recurrence at the first step that meets the test, so the batch size
   // changes the cost only, never the result. With timing on, the event
   // pairs of the timed launches that ran are read: the occupied launches
-  // of the full layout (one per step), the fused first launches of the
-  // packed one (one per step plus the normalising first launch; a step's
-  // update completes in the next step's first launch).
-  int batch = std::min(std::max(1, (int)ceil_div(lz_steps_hint_ + (packed ? 1 : 0), len)), (int)kMaxBatchBlocks);
+  // of the three-launch forms (one per step), the fused first launches of
+  // the two-launch form (one per step plus the normalising first launch; a
+  // step's update completes in the next step's first launch).
+  const bool two = mode == kLzFused;
+  int batch = std::min(std::max(1, (int)ceil_div(lz_steps_hint_ + (two ? 1 : 0), len)), (int)kMaxBatchBlocks);
   int launched = 0, steps = 0;
   bool conv = false;
   while (launched < maxit) {
     const int nb = (int)std::min<int64_t>(batch, ceil_div(maxit - launched, len));
     bool timed = false, graph = false;
     if (use_graphs_) {
-      timed = tm && fused && ensure_lanczos_graph(true, nb);
+      timed = tm && timeable && ensure_lanczos_graph(true, nb);
       graph = timed || ensure_lanczos_graph(false, nb);
     }
-    if (graph) PNK_HIP(hipGraphLaunch(lz_graphs_[lz_packed_ ? 1 : 0][timed ? 1 : 0][nb], s));
+    if (graph) PNK_HIP(hipGraphLaunch(lz_graphs_[mode][timed ? 1 : 0][nb], s));
     else
       for (int q = 0; q < nb; ++q) lanczos_block(s);
     const int before = launched;
@@ -722,7 +776,7 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
     const double res = host_[kFinRes], bn = host_[kFinBNorm];
     const bool ok = std::isfinite(res) && (res <= rtol * bn || host_[kFinBeta] == 0.0);
     if (timed) {
-      const int ran_total = std::min(launched, packed ? steps + 1 : steps);
+      const int ran_total = std::min(launched, two ? steps + 1 : steps);
       const int ran = std::min(nb * len, ran_total - before);
       for (int k = 0; k < ran; ++k) {
         float ms = 0.f;

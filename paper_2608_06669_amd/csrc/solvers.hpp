@@ -83,6 +83,7 @@ class Solver {
   void set_graphs(bool on) { use_graphs_ = on; }
   static constexpr int kLanczosBlock = 6;  // steps per recorded block (full layout)
   static constexpr int kPackedBlock = 4;   // steps per recorded block (packed layout, fused update)
+  // (the packed three-launch form uses kLanczosBlock)
   void solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s);
   void solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipStream_t s);
   // Solve for the amplitudes of a non-orthogonal gauge (nullptr: the
@@ -126,9 +127,12 @@ class Solver {
   bool use_graphs_ = true;
   // recorded runs of nb blocks, nb = 1 .. kMaxBatchBlocks
   static constexpr int kMaxBatchBlocks = 16;
-  hipGraphExec_t lz_graphs_[2][2][kMaxBatchBlocks + 1] = {};  // [packed][timed][nb]
-  bool lz_graph_failed_[2][2][kMaxBatchBlocks + 1] = {};
-  bool lz_packed_ = false;  // layout of the current symmetric solve
+  // form of the current symmetric solve: full layout; packed pairs, three
+  // launches per step; packed pairs, two launches (fused update)
+  enum { kLzFull = 0, kLzPacked3 = 1, kLzFused = 2, kLzModes = 3 };
+  hipGraphExec_t lz_graphs_[kLzModes][2][kMaxBatchBlocks + 1] = {};  // [mode][timed][nb]
+  bool lz_graph_failed_[kLzModes][2][kMaxBatchBlocks + 1] = {};
+  int lz_mode_ = kLzFull;
   std::vector<hipEvent_t> lz_ev_;  // event pairs around the A_F launches of a timed run
   int lz_steps_hint_ = 0;          // steps the last symmetric solve ran
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
