@@ -313,9 +313,14 @@ constexpr int kPackBlocksX = 16;  // workgroups per pair block (grid-stride over
 // (b_ij + b_ji^T) / 2 (the pair-symmetric part; b_ji^T staged through LDS).
 // Each workgroup writes its shares of ||sym(b)||^2 and ||D^1/2 sym(b)||^2
 // (blocks of pairs i < j counted twice) to parts[g], parts[G + g], g the
-// workgroup's linear index, G the number of workgroups.
+// workgroup's linear index, G the number of workgroups. The packed vectors
+// of z (null entries skipped) are set to zero in the same pass.
+struct ZeroList {
+  double* p[4];
+};
+
 __global__ __launch_bounds__(256) void lzp_pack(int o, int v, const double* __restrict__ b, double rs,
-                                                double* __restrict__ xp, double* __restrict__ parts) {
+                                                double* __restrict__ xp, double* __restrict__ parts, ZeroList z) {
   __shared__ double tile[kPackTile][kPackTile + 1];
   __shared__ double sm[2][4];
   const int npair = o * (o + 1) / 2;
@@ -326,6 +331,9 @@ __global__ __launch_bounds__(256) void lzp_pack(int o, int v, const double* __re
     for (int64_t e = blockIdx.x * (int64_t)256 + tid; e < ov; e += (int64_t)gridDim.x * 256) {
       const double x = b[e];
       xp[e] = rs * x;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (z.p[q]) z.p[q][e] = 0.0;
       s_plain += x * x;
       s_scaled += (rs * x) * (rs * x);
     }
@@ -351,6 +359,10 @@ __global__ __launch_bounds__(256) void lzp_pack(int o, int v, const double* __re
         if (a < v && bb < v) {
           const double x = 0.5 * (bij[(int64_t)a * v + bb] + tile[tx][r]);
           out[(int64_t)a * v + bb] = x;
+          const int64_t idx = ov + (int64_t)blockIdx.y * vv + (int64_t)a * v + bb;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            if (z.p[q]) z.p[q][idx] = 0.0;
           s_plain += w * x * x;
           s_scaled += w * x * x;
         }
@@ -706,27 +718,21 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
     double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n;
     xi = Qi_ + 5 * n;
     double* parts = partials_ + 3 * kMaxFusedParts;
-    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, xi, parts);
+    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, xi, parts,
+                                                                 ZeroList{{vprev, w1, w2, nullptr}});
     lzp_init_normalised<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, rtol);
     scale_by_inverse(nl, xi, fin + kFinBHat, v, s);  // v_1 = D^1/2 b / ||D^1/2 b||
-    fill(nl, 0.0, vprev, s);
-    fill(nl, 0.0, w1, s);
-    fill(nl, 0.0, w2, s);
     fill(nl, 0.0, xi, s);
   } else if (mode == kLzFused) {
     // the same on the two-launch form: the first fused step normalises the
     // start vector P = D^1/2 b (V = 0)
-    const int64_t nl = ov + (int64_t)op->npair * vir * vir;
     double *P0 = Qi_, *V0 = Qi_ + n, *w1 = Qi_ + 4 * n, *w2 = Qi_ + 5 * n;
     xi = Qi_ + 6 * n;
     double* parts = partials_ + 3 * kMaxFusedParts;
-    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, P0, parts);
+    lzp_pack<<<dim3(kPackBlocksX, op->npair + 1), 256, 0, s>>>(o, vir, b, rs, P0, parts,
+                                                                 ZeroList{{V0, w1, w2, xi}});
     lzp_init_fused<<<1, 256, 0, s>>>(parts, kPackBlocksX * (op->npair + 1), st, partials_,
                                       (int)op->nparts_packed(), rtol);
-    fill(nl, 0.0, V0, s);
-    fill(nl, 0.0, w1, s);
-    fill(nl, 0.0, w2, s);
-    fill(nl, 0.0, xi, s);
   } else {
     double *vprev = Qi_, *v = Qi_ + n, *w1 = Qi_ + 3 * n, *w2 = Qi_ + 4 * n;
     xi = Qi_ + 5 * n;

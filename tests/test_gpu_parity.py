@@ -380,10 +380,14 @@ def test_sfp_diis_ccd_matches_the_oracle(handle, lib):
     assert info["n_residual"] == ia.n_residual
 
 
-def test_timed_solve_matches_untimed(handle, lib):
-    """Timing instrumentation (events around the fused A_F launches inside
-    the replayed inner-solve graph) changes nothing in the solve."""
-    p = make_problem(4, 18, 40, 53, gauge="haar")
+@pytest.mark.parametrize("o,v,naux", [(4, 18, 40), (5, 40, 40)])
+def test_timed_solve_matches_untimed(handle, lib, o, v, naux):
+    """Timing instrumentation (events around the timed A_F launch of each
+    step inside the replayed inner-solve graph) changes nothing in the
+    solve: v = 18 plans 32-wide blocks (the two-launch step, the fused
+    launch timed), v = 40 48-wide ones (three launches, the occupied launch
+    timed)."""
+    p = make_problem(o, v, naux, 53, gauge="haar")
     P = lib.DeviceProblem.from_problem(p)
     _, _, ref = handle.solve_pnk(P, tol_inf=1e-10)
     handle.timing(True)
