@@ -217,8 +217,12 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
   constexpr int TMI = WTM / Mma::TM, TNI = WTN / Mma::TN;
   constexpr int ALDS = lds_elems<Mma, BM, BK>();
   constexpr int BLDS = lds_elems<Mma, BN, BK>();
-  __shared__ __attribute__((aligned(16))) double As[2][ALDS];
-  __shared__ __attribute__((aligned(16))) double Bs[2][BLDS];
+  // ONE: the whole contraction (v <= BK) in one panel per phase, one LDS
+  // buffer; the phase-0 panels are read before the scalars are formed
+  constexpr bool ONE = BK >= 64;
+  constexpr int NBUF = ONE ? 1 : 2;
+  __shared__ __attribute__((aligned(16))) double As[NBUF][ALDS];
+  __shared__ __attribute__((aligned(16))) double Bs[NBUF][BLDS];
   __shared__ double red[3][4];
 
   const int tid = threadIdx.x;
@@ -274,6 +278,21 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
     }
   };
   load_batch(0);
+  const double* __restrict__ Xp = p.P + off;
+  const double* __restrict__ Xv = p.V + off;
+  const double* __restrict__ F = p.f_vv;
+  const bool vec = p.vec != 0;
+  // phase 0 of ONE: F rows m0.. and the p, v columns n0.. (v_k is formed
+  // from them once alpha and beta are known)
+  Panel<Mma, double, BM, BK, true> fa;
+  Panel<Mma, double, BN, BK, false> pbp, pbv;
+  if constexpr (ONE) {
+    if (!singles_wg) {
+      fa.load(F, v, 1, m0, v, 0, v, vec, tid);
+      pbp.load(Xp, 1, v, n0, v, 0, v, vec, tid);
+      pbv.load(Xv, 1, v, n0, v, 0, v, vec, tid);
+    }
+  }
 
   // scalars (every workgroup, same bits)
   double r3[3] = {0.0, 0.0, 0.0};
@@ -361,41 +380,12 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave / WGN, wn = wave % WGN;
-  const double* __restrict__ Xp = p.P + off;
-  const double* __restrict__ Xv = p.V + off;
-  const double* __restrict__ F = p.f_vv;
-  const bool vec = p.vec != 0;
-  const int nkp = (v + BK - 1) / BK;
-  const int nk = 2 * nkp;
   double acc[TMI][TNI];
 #pragma unroll
   for (int a = 0; a < TMI; ++a)
 #pragma unroll
     for (int b = 0; b < TNI; ++b) acc[a][b] = 0.0;
-  // phase 0: F[a][c] x v_k[c][b]; phase 1: v_k[a][c] x F[c][b]; the v_k
-  // panel is (p - alpha v) / beta of the two loaded panels
-  Panel<Mma, double, BM, BK, true> pa;
-  Panel<Mma, double, BN, BK, false> pb;
-  auto load = [&](int t) {
-    if (t >= nkp) {
-      const int k0 = (t - nkp) * BK;
-      pa.load_diff(Xp, Xv, alpha, invb, v, 1, m0, v, k0, v, vec, tid);
-      pb.load(F, 1, v, n0, v, k0, v, vec, tid);
-    } else {
-      const int k0 = t * BK;
-      pa.load(F, v, 1, m0, v, k0, v, vec, tid);
-      pb.load_diff(Xp, Xv, alpha, invb, 1, v, n0, v, k0, v, vec, tid);
-    }
-  };
-  load(0);
-  pa.store(As[0], tid);
-  pb.store(Bs[0], tid);
-  __syncthreads();
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = kt & 1;
-    if (kt + 1 < nk) load(kt + 1);
-    const double* Ac = As[cur];
-    const double* Bc = Bs[cur];
+  auto mma = [&](const double* Ac, const double* Bc) {
 #pragma unroll
     for (int ks = 0; ks < BK; ks += Mma::KSTEP) {
       const int kk = ks + (lane >> 4);
@@ -409,11 +399,59 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
 #pragma unroll
         for (int b = 0; b < TNI; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
     }
-    if (kt + 1 < nk) {
-      pa.store(As[cur ^ 1], tid);
-      pb.store(Bs[cur ^ 1], tid);
-    }
+  };
+  if constexpr (ONE) {
+    // phase 0: F[m0.., :] x v_k[:, n0..]; phase 1: v_k[m0.., :] x F[:, n0..]
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(pbp.r) / sizeof(double)); ++i) pbp.r[i] = (pbp.r[i] - alpha * pbv.r[i]) * invb;
+    fa.store(As[0], tid);
+    pbp.store(Bs[0], tid);
+    Panel<Mma, double, BM, BK, true> pap, pav;
+    Panel<Mma, double, BN, BK, false> fb;
+    pap.load(Xp, v, 1, m0, v, 0, v, vec, tid);
+    pav.load(Xv, v, 1, m0, v, 0, v, vec, tid);
+    fb.load(F, 1, v, n0, v, 0, v, vec, tid);
     __syncthreads();
+    mma(As[0], Bs[0]);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(pap.r) / sizeof(double)); ++i) pap.r[i] = (pap.r[i] - alpha * pav.r[i]) * invb;
+    __syncthreads();
+    pap.store(As[0], tid);
+    fb.store(Bs[0], tid);
+    __syncthreads();
+    mma(As[0], Bs[0]);
+  } else {
+    const int nkp = (v + BK - 1) / BK;
+    const int nk = 2 * nkp;
+    // phase 0: F[a][c] x v_k[c][b]; phase 1: v_k[a][c] x F[c][b]; the v_k
+    // panel is (p - alpha v) / beta of the two loaded panels
+    Panel<Mma, double, BM, BK, true> pa;
+    Panel<Mma, double, BN, BK, false> pb;
+    auto load = [&](int t) {
+      if (t >= nkp) {
+        const int k0 = (t - nkp) * BK;
+        pa.load_diff(Xp, Xv, alpha, invb, v, 1, m0, v, k0, v, vec, tid);
+        pb.load(F, 1, v, n0, v, k0, v, vec, tid);
+      } else {
+        const int k0 = t * BK;
+        pa.load(F, v, 1, m0, v, k0, v, vec, tid);
+        pb.load_diff(Xp, Xv, alpha, invb, 1, v, n0, v, k0, v, vec, tid);
+      }
+    };
+    load(0);
+    pa.store(As[0], tid);
+    pb.store(Bs[0], tid);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+      const int cur = kt & 1;
+      if (kt + 1 < nk) load(kt + 1);
+      mma(As[cur], Bs[cur]);
+      if (kt + 1 < nk) {
+        pa.store(As[cur ^ 1], tid);
+        pb.store(Bs[cur ^ 1], tid);
+      }
+      __syncthreads();
+    }
   }
   double* __restrict__ Yo = p.Y + off;
 #pragma unroll
@@ -775,6 +813,8 @@ bool fock_op_is_timed_lanczos_kernel(const void* func, bool fused) {
            func == reinterpret_cast<const void*>(&fock_occ_packed_kernel);
   const void* timed[] = {reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 16>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 32>),
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 64>),
+                         reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 96>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<48, 4, 16>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<48, 4, 32>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<64, 2, 16>),
@@ -842,6 +882,14 @@ void fock_op_lanczos_vir_fused(const FockOp& op, const double* P, const double* 
   a.stn = stn;
   a.fin = fin;
   dim3 grid((unsigned)(8 * a.per_xcd + a.nsw));
+  // 32 < v <= 96 on 32-wide blocks: the whole contraction in one panel per
+  // phase (two dependent panel reads per workgroup instead of up to six)
+  if (op.bm == 32 && op.v > 32 && op.v <= 96) {
+    if (op.v <= 64) fock_vir_lz_kernel<32, 2, 64><<<grid, 256, 0, s>>>(a);
+    else fock_vir_lz_kernel<32, 2, 96><<<grid, 256, 0, s>>>(a);
+    PNK_CHECK_LAUNCH();
+    return;
+  }
   const bool bk32 = op.bm == 32 && ceil_div(op.v, 32) * 32 <= ceil_div(op.v, 16) * 16;
   switch (op.bm * 2 + (bk32 ? 1 : 0)) {
     case 64: fock_vir_lz_kernel<32, 2, 16><<<grid, 256, 0, s>>>(a); break;

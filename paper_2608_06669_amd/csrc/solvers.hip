@@ -749,7 +749,9 @@ int Solver::precond_solve_sym(const double* b, double* x, double rtol, int maxit
   }
   PNK_CHECK_LAUNCH();
   Timers* tm = eng_.timers();
-  const bool timeable = packed || (op && op->nparts() <= kMaxFusedParts);
+  // the event pairs are read for a sample of the solves: each bracketed
+  // launch pays for its two event nodes, which would slow every solve
+  const bool timeable = (packed || (op && op->nparts() <= kMaxFusedParts)) && lz_solves_++ % kTimedEvery == 0;
   const int len = lz_block_len();
   // The first batch queues as many blocks as the last solve needed steps
   // (as one recorded graph), later ones a block each. The device stops the

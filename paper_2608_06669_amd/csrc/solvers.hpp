@@ -135,6 +135,10 @@ class Solver {
   int lz_mode_ = kLzFull;
   std::vector<hipEvent_t> lz_ev_;  // event pairs around the A_F launches of a timed run
   int lz_steps_hint_ = 0;          // steps the last symmetric solve ran
+  // With timing on, one symmetric solve in kTimedEvery replays the graphs
+  // with event nodes (they cost several microseconds per bracketed launch)
+  static constexpr int kTimedEvery = 8;
+  int64_t lz_solves_ = 0;
   void lanczos_step(double* vprev, double* v, double* p, double* w1, double* w2, double* x, double* st,
                     double* stn, hipStream_t s);
   // state slots of the Lanczos recurrence (device scalars)

@@ -198,11 +198,14 @@ def test_precond_solve_symmetric_fock_operator(handle, lib):
         assert np.abs(host(s2) - e2).max() <= 1e-10 * np.abs(e2).max()
 
 
-@pytest.mark.parametrize("o,v,seed", [(5, 23, 47), (1, 9, 48), (10, 90, 49), (7, 40, 50)])
+@pytest.mark.parametrize("o,v,seed", [(5, 23, 47), (1, 9, 48), (10, 90, 49), (7, 40, 50), (12, 60, 51)])
 def test_precond_solve_pair_symmetric_packed_layout(handle, lib, o, v, seed):
     """cc_precond_solve_pairsym: the Lanczos vectors hold pairs i <= j only
     (tile edge 8 at o=5/v=23, 4 at o=10/v=90, both with a ragged last
-    tile). Several calls in a row replay the recorded graphs; each result
+    tile). The virtual contraction of the fused step runs in panels of 32
+    at v=23, in one panel of 96 at v=90 and of 64 at v=60 (o=12: 32-wide
+    blocks); v=40 takes 48-wide blocks and the three-launch step. Several
+    calls in a row replay the recorded graphs; each result
     equals the eigendecomposition inverse, and agrees with the full-layout
     solve."""
     p = make_problem(o, v, 3 * (o + v), seed, gauge="haar")
@@ -383,8 +386,8 @@ def test_sfp_diis_ccd_matches_the_oracle(handle, lib):
 @pytest.mark.parametrize("o,v,naux", [(4, 18, 40), (5, 40, 40)])
 def test_timed_solve_matches_untimed(handle, lib, o, v, naux):
     """Timing instrumentation (events around the timed A_F launch of each
-    step inside the replayed inner-solve graph) changes nothing in the
-    solve: v = 18 plans 32-wide blocks (the two-launch step, the fused
+    step inside the replayed inner-solve graph, for one inner solve in
+    eight) changes nothing in the solve: v = 18 plans 32-wide blocks (the two-launch step, the fused
     launch timed), v = 40 48-wide ones (three launches, the occupied launch
     timed)."""
     p = make_problem(o, v, naux, 53, gauge="haar")
