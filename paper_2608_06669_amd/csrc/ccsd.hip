@@ -141,12 +141,13 @@ struct Sizes {
 };
 
 // Split-K scratch. Products are split only when they have fewer than 256
-// output tiles of at least 64 x 64, into at most ceil(512 / tiles) chunks,
-// so splits * M * N * batch stays below 512 * 4096 + 64 * 64 * 256 doubles;
-// small problems need far less.
+// output tiles; the chunk count is also capped by this size (splits * M * N
+// * batch must fit). 16 times the largest o^2 v^2-class tensor, at most 8 M
+// elements (64 MB): room for the four chunks of the o v x o v products at
+// o = 10, v = 90 and the twelve of their 300 x 900 x 900 ones.
 int64_t splitk_elems(const Sizes& z) {
   const int64_t big = std::max<int64_t>({z.o * z.o * z.v * z.v, z.ov * z.ov, (int64_t)z.o * z.o * z.o * z.o});
-  return std::min<int64_t>(std::max<int64_t>(16 * big, 1 << 16), 3 * 1024 * 1024);
+  return std::min<int64_t>(std::max<int64_t>(16 * big, 1 << 16), 8 * 1024 * 1024);
 }
 
 // Rounded copies of FP64 operands for the FP32/BF16 products of J v: room
