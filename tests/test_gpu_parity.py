@@ -198,13 +198,15 @@ def test_precond_solve_symmetric_fock_operator(handle, lib):
         assert np.abs(host(s2) - e2).max() <= 1e-10 * np.abs(e2).max()
 
 
-@pytest.mark.parametrize("o,v,seed", [(5, 23, 47), (1, 9, 48), (10, 90, 49), (7, 40, 50), (12, 60, 51)])
+@pytest.mark.parametrize("o,v,seed", [(5, 23, 47), (1, 9, 48), (10, 90, 49), (7, 40, 50), (12, 60, 51), (5, 64, 52),
+                                      (6, 96, 53)])
 def test_precond_solve_pair_symmetric_packed_layout(handle, lib, o, v, seed):
     """cc_precond_solve_pairsym: the Lanczos vectors hold pairs i <= j only
     (tile edge 8 at o=5/v=23, 4 at o=10/v=90, both with a ragged last
     tile). The virtual contraction of the fused step runs in panels of 32
     at v=23, in one panel of 96 at v=90 and of 64 at v=60 (o=12: 32-wide
-    blocks); v=40 takes 48-wide blocks and the three-launch step. Several
+    blocks), and exactly fills its one panel at v=64 and v=96; v=40 takes
+    48-wide blocks and the three-launch step. Several
     calls in a row replay the recorded graphs; each result
     equals the eigendecomposition inverse, and agrees with the full-layout
     solve."""
