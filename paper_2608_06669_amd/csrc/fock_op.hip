@@ -208,6 +208,8 @@ struct VirLzArgs {
 // panels load. The first step of a solve (flag in the state) only
 // normalises: p is the start vector, v_{-1} is zero and the shares are
 // (0, ||p||^2, 0). A step whose test holds skips the matrix product.
+// BK >= 64 is launched only for v <= BK: each phase's contraction is then
+// one panel, and the first phase's panels are read with the element batch.
 template <int BM, int WGM, int BK>
 __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
   using Mma = MmaF64;
@@ -217,8 +219,9 @@ __global__ __launch_bounds__(256) void fock_vir_lz_kernel(VirLzArgs p) {
   constexpr int TMI = WTM / Mma::TM, TNI = WTN / Mma::TN;
   constexpr int ALDS = lds_elems<Mma, BM, BK>();
   constexpr int BLDS = lds_elems<Mma, BN, BK>();
-  // ONE: the whole contraction (v <= BK) in one panel per phase, one LDS
-  // buffer; the phase-0 panels are read before the scalars are formed
+  // ONE: the whole contraction (v <= BK, checked by the launcher) in one
+  // panel per phase, one LDS buffer; the phase-0 panels are read before the
+  // scalars are formed
   constexpr bool ONE = BK >= 64;
   constexpr int NBUF = ONE ? 1 : 2;
   __shared__ __attribute__((aligned(16))) double As[NBUF][ALDS];
@@ -884,7 +887,7 @@ void fock_op_lanczos_vir_fused(const FockOp& op, const double* P, const double* 
   dim3 grid((unsigned)(8 * a.per_xcd + a.nsw));
   // 32 < v <= 96 on 32-wide blocks: the whole contraction in one panel per
   // phase (two dependent panel reads per workgroup instead of up to six)
-  if (op.bm == 32 && op.v > 32 && op.v <= 96) {
+  if (op.bm == 32 && op.v > 32 && op.v <= 96) {  // v <= BK, as the one-panel form needs
     if (op.v <= 64) fock_vir_lz_kernel<32, 2, 64><<<grid, 256, 0, s>>>(a);
     else fock_vir_lz_kernel<32, 2, 96><<<grid, 256, 0, s>>>(a);
     PNK_CHECK_LAUNCH();
