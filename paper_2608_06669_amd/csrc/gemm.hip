@@ -277,18 +277,35 @@ __global__ __launch_bounds__(256) void gemm_smallk(KArgs p) {
   double* __restrict__ C = (double*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
   const int L = LONG_N ? p.N : p.M;
   const int S = LONG_N ? p.M : p.N;
+  // the short side is split over p.splits groups of workgroups. With at
+  // least 8 blocks of 256 along the long side, the groups of one block share
+  // an XCD (block ids go round-robin over the 8 XCDs), so its operand is
+  // read from HBM once; fewer blocks (batched products) map in order
+  const int sgn = p.splits;
+  const int nlb = (L + 255) / 256;
+  int lblock, sg;
+  if (nlb >= 8) {
+    const int xcd = (int)(blockIdx.x % 8), q8 = (int)(blockIdx.x / 8);
+    lblock = xcd + 8 * (q8 / sgn);
+    sg = q8 % sgn;
+  } else {
+    lblock = (int)blockIdx.x / sgn;
+    sg = (int)blockIdx.x % sgn;
+  }
+  const int sper = (S + sgn - 1) / sgn;
+  const int s0 = sg * sper, s1 = min(S, s0 + sper);
   for (int q = threadIdx.x; q < S * p.K; q += 256) {
     const int s = q / p.K, k = q % p.K;
     sh[s * kSmallK + k] = LONG_N ? A[s * p.a_m + k * p.a_k] : B[k * p.b_k + s * p.b_n];
   }
   __syncthreads();
-  const int l = blockIdx.x * 256 + threadIdx.x;
-  if (l >= L) return;
+  const int l = lblock * 256 + threadIdx.x;
+  if (l >= L || s0 >= s1) return;
   double r[kSmallK];
 #pragma unroll
   for (int k = 0; k < kSmallK; ++k)
     r[k] = k < p.K ? (LONG_N ? B[k * p.b_k + l * p.b_n] : A[l * p.a_m + k * p.a_k]) : 0.0;
-  for (int s = 0; s < S; ++s) {
+  for (int s = s0; s < s1; ++s) {
     double acc = 0.0;
 #pragma unroll
     for (int k = 0; k < kSmallK; ++k)
@@ -311,10 +328,17 @@ void launch_smallk(const GemmDesc& d, const void* A, const void* B, void* C, hip
   // contiguous index of C)
   const bool long_n = d.N >= d.M;
   const int L = long_n ? d.N : d.M;
+  const int S = long_n ? d.M : d.N;
   int64_t gy = d.nb0, gz = d.nb1;
   while (gy * 2 <= 65535 && gz % 2 == 0) { gy *= 2; gz /= 2; }
   PNK_REQUIRE(gy <= 65535 && gz <= 65535, "gemm: batch too large");
-  dim3 grid((unsigned)ceil_div(L, 256), (unsigned)gy, (unsigned)gz);
+  // one lane per index of the long side leaves a few waves per SIMD when
+  // the long side is short of a million: split the short side into groups
+  // (at most four) until about 4096 waves run
+  const int64_t nlb = ceil_div(L, 256);
+  const int64_t waves = nlb * 4 * (int64_t)d.nb0 * d.nb1;
+  p.splits = (int)std::max<int64_t>(1, std::min<int64_t>({4, S, ceil_div(4096, std::max<int64_t>(waves, 1))}));
+  dim3 grid((unsigned)((nlb >= 8 ? 8 * ceil_div(nlb, 8) : nlb) * p.splits), (unsigned)gy, (unsigned)gz);
   if (long_n) gemm_smallk<true><<<grid, 256, 0, s>>>(p);
   else gemm_smallk<false><<<grid, 256, 0, s>>>(p);
   PNK_CHECK_LAUNCH();
