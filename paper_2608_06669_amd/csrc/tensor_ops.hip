@@ -159,11 +159,13 @@ __global__ __launch_bounds__(256) void reduce_stage1(int64_t n, const double* __
   if (threadIdx.x == 0) partials[blockIdx.x] = sm[0];
 }
 
+// One workgroup per vector (a grid-stride loop over the vectors); each
+// vector's sum runs in the same fixed order whatever the grid.
 template <int OP>  // 0: sum, 1: sqrt(sum), 2: max
 __global__ __launch_bounds__(256) void reduce_stage2(int nparts, const double* partials, int stride, int nvec,
                                                      double* out) {
   __shared__ double sm[256];
-  for (int vct = 0; vct < nvec; ++vct) {
+  for (int vct = blockIdx.x; vct < nvec; vct += gridDim.x) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < nparts; i += 256) {
       const double p = partials[(int64_t)i * stride + vct];
@@ -365,7 +367,7 @@ void multi_dot(int64_t n, int m, const double* Q, int64_t ldq, const double* w, 
                hipStream_t s) {
   if (m <= 0) return;
   multi_dot_stage1<<<kReduceBlocks, 256, 0, s>>>(n, m, Q, ldq, w, partials);
-  reduce_stage2<0><<<1, 256, 0, s>>>(kReduceBlocks, partials, m, m, out);
+  reduce_stage2<0><<<m, 256, 0, s>>>(kReduceBlocks, partials, m, m, out);
   PNK_CHECK_LAUNCH();
 }
 void multi_axpy(int64_t n, int m, const double* Q, int64_t ldq, const double* h, double* w, hipStream_t s) {
