@@ -667,11 +667,20 @@ void Engine::jvp(const double* x1, const double* x2, double* y1, double* y2, Pre
   GraphSlot* slot = &jvp_slot_[(int)prec];
   if (graph_ready(slot, T1.v, T2.v, nullptr, nullptr, Mode::Tangent)) {
     jprec_ = prec;
-    PNK_HIP(hipMemcpyAsync(tin_, x1, ov_ * sizeof(double), hipMemcpyDeviceToDevice, s));
-    PNK_HIP(hipMemcpyAsync(tin_ + ov_, x2, n2_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    // (one copy each way when the caller's singles and doubles are adjacent)
+    if (x2 == x1 + ov_) {
+      PNK_HIP(hipMemcpyAsync(tin_, x1, (ov_ + n2_) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      PNK_HIP(hipMemcpyAsync(tin_, x1, ov_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PNK_HIP(hipMemcpyAsync(tin_ + ov_, x2, n2_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
     PNK_HIP(hipGraphLaunch(slot->exec, s));
-    PNK_HIP(hipMemcpyAsync(y1, tout_, ov_ * sizeof(double), hipMemcpyDeviceToDevice, s));
-    PNK_HIP(hipMemcpyAsync(y2, tout_ + ov_, n2_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (y2 == y1 + ov_) {
+      PNK_HIP(hipMemcpyAsync(y1, tout_, (ov_ + n2_) * sizeof(double), hipMemcpyDeviceToDevice, s));
+    } else {
+      PNK_HIP(hipMemcpyAsync(y1, tout_, ov_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+      PNK_HIP(hipMemcpyAsync(y2, tout_ + ov_, n2_ * sizeof(double), hipMemcpyDeviceToDevice, s));
+    }
   } else {
     T1.d = const_cast<double*>(x1);
     T2.d = const_cast<double*>(x2);
