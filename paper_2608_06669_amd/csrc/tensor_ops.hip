@@ -193,11 +193,26 @@ __global__ __launch_bounds__(256) void multi_dot_stage1(int64_t n, int m, const 
     double acc[kMD];
 #pragma unroll
     for (int q = 0; q < kMD; ++q) acc[q] = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-      const double wi = w[i];
+    // four grid-stride iterations' loads are issued before their products
+    // are added, in the same order as one iteration at a time
+    const int64_t st = (int64_t)gridDim.x * 256;
+    constexpr int U = 4;
+    for (int64_t i0 = blockIdx.x * (int64_t)256 + threadIdx.x; i0 < n; i0 += U * st) {
+      double wi[U], qv[U][kMD];
 #pragma unroll
-      for (int q = 0; q < kMD; ++q)
-        if (q < mc) acc[q] += Q[(int64_t)(c0 + q) * ldq + i] * wi;
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + u * st;
+        wi[u] = i < n ? w[i] : 0.0;
+#pragma unroll
+        for (int q = 0; q < kMD; ++q) qv[u][q] = (q < mc && i < n) ? Q[(int64_t)(c0 + q) * ldq + i] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (i0 + u * st >= n) break;
+#pragma unroll
+        for (int q = 0; q < kMD; ++q)
+          if (q < mc) acc[q] += qv[u][q] * wi[u];
+      }
     }
 #pragma unroll
     for (int q = 0; q < kMD; ++q) sm[q][threadIdx.x] = acc[q];
