@@ -215,13 +215,30 @@ template <typename TC>
 __global__ __launch_bounds__(256) void splitk_reduce(KArgs p) {
   const int64_t MN = (int64_t)p.M * p.N;
   const int64_t total = MN * p.nbtot;
+  // one row-major output: its address is the element index
+  const bool flat = p.nbtot == 1 && p.c_n == 1 && p.c_m == p.N;
   for (int64_t e = blockIdx.x * (int64_t)256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
     double acc = 0.0;
-    for (int s = 0; s < p.splits; ++s) acc += p.ws[(int64_t)s * total + e];
-    const int64_t b = e / MN;
-    const int m = (int)((e % MN) / p.N), n = (int)(e % p.N);
-    const int b0 = (int)(b % p.nb0), b1 = (int)(b / p.nb0);
-    TC* c = (TC*)p.C + b0 * p.c_b0 + b1 * p.c_b1 + m * p.c_m + n * p.c_n;
+    // four chunks' loads in flight before they are added, in chunk order
+    int s = 0;
+    for (; s + 4 <= p.splits; s += 4) {
+      const double x0 = p.ws[(int64_t)s * total + e], x1 = p.ws[(int64_t)(s + 1) * total + e];
+      const double x2 = p.ws[(int64_t)(s + 2) * total + e], x3 = p.ws[(int64_t)(s + 3) * total + e];
+      acc += x0;
+      acc += x1;
+      acc += x2;
+      acc += x3;
+    }
+    for (; s < p.splits; ++s) acc += p.ws[(int64_t)s * total + e];
+    TC* c;
+    if (flat) {
+      c = (TC*)p.C + e;
+    } else {
+      const int64_t b = e / MN;
+      const int m = (int)((e % MN) / p.N), n = (int)(e % p.N);
+      const int b0 = (int)(b % p.nb0), b1 = (int)(b / p.nb0);
+      c = (TC*)p.C + b0 * p.c_b0 + b1 * p.c_b1 + m * p.c_m + n * p.c_n;
+    }
     double v = p.alpha * acc;
     if (p.beta != 0.0) v += p.beta * load_c<TC>(c);
     *c = from_acc<TC>(v);
