@@ -63,6 +63,21 @@ struct PermFlatArgs {
 };
 
 __global__ __launch_bounds__(256) void permute_flat_kernel(PermFlatArgs p) {
+  if (p.total < (1ll << 31)) {
+    // the same indices in 32-bit arithmetic (64-bit division is a long
+    // instruction sequence); e + stride stays below 2^32
+    const uint32_t od1 = (uint32_t)p.od[1], od2 = (uint32_t)p.od[2], od3 = (uint32_t)p.od[3];
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < (uint32_t)p.total; e += gridDim.x * blockDim.x) {
+      uint32_t r = e;
+      const uint32_t i3 = r % od3; r /= od3;
+      const uint32_t i2 = r % od2; r /= od2;
+      const uint32_t i1 = r % od1; r /= od1;
+      const uint32_t i0 = r;
+      const double v = p.alpha * p.in[i0 * p.is[0] + i1 * p.is[1] + i2 * p.is[2] + i3 * p.is[3]];
+      p.out[e] = (p.beta == 0.0) ? v : v + p.beta * p.out[e];
+    }
+    return;
+  }
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < p.total;
        e += (int64_t)gridDim.x * blockDim.x) {
     int64_t r = e;
