@@ -199,17 +199,17 @@ def test_precond_solve_symmetric_fock_operator(handle, lib):
 
 
 @pytest.mark.parametrize("o,v,seed", [(5, 23, 47), (1, 9, 48), (10, 90, 49), (7, 40, 50), (12, 60, 51), (5, 64, 52),
-                                      (6, 96, 53)])
+                                      (6, 96, 53), (4, 91, 54)])
 def test_precond_solve_pair_symmetric_packed_layout(handle, lib, o, v, seed):
     """cc_precond_solve_pairsym: the Lanczos vectors hold pairs i <= j only
-    (tile edge 8 at o=5/v=23, 4 at o=10/v=90, both with a ragged last
-    tile). The virtual contraction of the fused step runs in panels of 32
-    at v=23, in one panel of 96 at v=90 and of 64 at v=60 (o=12: 32-wide
+    (the occupied kernel's tile edge is 8 at o=5/v=23, with a ragged last
+    tile, and 2 with the pairs unsplit at v=90, 91 and 96, ragged at 91).
+    The virtual contraction of the fused step runs in panels of 32 at v=23,
+    in one panel of 96 at v=90 and 91 and of 64 at v=60 (o=12: 32-wide
     blocks), and exactly fills its one panel at v=64 and v=96; v=40 takes
-    48-wide blocks and the three-launch step. Several
-    calls in a row replay the recorded graphs; each result
-    equals the eigendecomposition inverse, and agrees with the full-layout
-    solve."""
+    48-wide blocks and the three-launch step. Several calls in a row replay
+    the recorded graphs; each result equals the eigendecomposition inverse,
+    and agrees with the full-layout solve."""
     p = make_problem(o, v, 3 * (o + v), seed, gauge="haar")
     P = lib.DeviceProblem.from_problem(p)
     for k in range(3):
