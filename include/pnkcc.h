@@ -160,7 +160,12 @@ cc_status cc_precond_solve_pairsym(cc_handle* h, const cc_problem* p, const doub
  *            and one inner solve per step, max_newton of them; m_max and
  *            the forcing terms are unused)
  * ccd:       1 = the paper's CCD level: t1 is held at zero and the singles
- *            equations are dropped (t1 in and out is zero) */
+ *            equations are dropped (t1 in and out is zero)
+ * stall_window, stall_factor: stagnation stop (not in the paper; 0 = off):
+ *            the solve ends as CC_NOT_CONVERGED, with info->stalled = 1,
+ *            once stall_window Newton steps have passed without ||r||_inf
+ *            falling below stall_factor times its value at the last step
+ *            where it did (the first step counts as such) */
 typedef enum { CC_PNK = 0, CC_NK = 1, CC_INK = 2 } cc_protocol;
 
 typedef struct {
@@ -176,6 +181,8 @@ typedef struct {
   int init_mp2;
   cc_protocol protocol;
   int ccd;
+  int stall_window;
+  double stall_factor;
 } cc_pnk_opts;
 
 /* FP (+ level shift, + DIIS) options: t <- t - r/(D + level_shift) with D
@@ -194,16 +201,19 @@ typedef struct {
 
 /* Solve statistics (host). n_residual and n_jvp count residual evaluations
  * and Jacobian products (the paper's cost measure); n_afmv counts A_F
- * products of the inner solves. */
+ * products of the inner solves; stalled = 1 when the stagnation stop of
+ * cc_pnk_opts ended the solve. */
 typedef struct {
   double e_corr, res_inf, res_2;
   int converged, newton_iters, n_residual, n_jvp, n_afmv, n_inner_iters;
   double seconds;
+  int stalled;
 } cc_info;
 
 /* Defaults: tol 1e-8, 100 Newton steps, m_max 20, gamma 0.9, alpha 1.5,
  * eta0 0.5, eta_max 0.9, inner rtol 1e-12, inner maxit 200, restart 30,
- * FP64 products, analytic J v, MP2 start, PNK, CCSD. */
+ * FP64 products, analytic J v, MP2 start, PNK, CCSD, no stagnation stop
+ * (stall_window 0, stall_factor 0.5). */
 void cc_pnk_opts_default(cc_pnk_opts* o);
 /* Defaults: tol 1e-8, 500 iterations, DIIS 8 from iteration 2, no shift,
  * MP2 start, CCSD. */
@@ -296,16 +306,22 @@ int cc_last_history(const cc_handle* h, double* pairs, int max_pairs);
 /* ---------------------------------------------------------------------
  * Serving: continuous batching of PNK solves on one GPU.
  *
- * Requests carry HOST problem arrays that are copied at submission. A
- * scheduler admits queued requests in arrival order while a slot is free and
- * the request's device footprint (cc_workspace_bytes of its shape and
- * options plus its problem arrays) fits in the unused part of mem_budget;
- * admitted requests run concurrently, each on its own stream, so their
- * kernels overlap on the device. A finished request frees its memory and
- * slot, and the next queued request is admitted at once. A request whose
- * footprint exceeds the whole budget is rejected at submission
- * (CC_ERR_REJECTED). Each result depends only on its own request: the same
- * kernels and launch shapes run whatever else is in flight.
+ * Requests carry HOST problem arrays that are copied at submission and
+ * dropped once the solve has consumed them. A scheduler admits queued
+ * requests while a slot is free and the request's device footprint
+ * (cc_workspace_bytes of its shape and options plus its problem arrays)
+ * fits in the unused part of mem_budget: the first one in arrival order
+ * that fits, except that a request passed over 2 * max_slots times by later
+ * ones blocks those behind it until it runs. Admitted requests run
+ * concurrently, each on its own stream, so their kernels overlap on the
+ * device. A finished request frees its problem arrays and slot and leaves
+ * its handle (integral workspace, recorded graphs, Krylov bases) in a cache
+ * keyed by (nocc, nvir, naux, precision) for a later request of the same
+ * key; cached handles count against mem_budget and the least recently used
+ * are freed when a queued request needs the room. A request whose footprint
+ * exceeds the whole budget is rejected at submission (CC_ERR_REJECTED).
+ * Each result depends only on its own request: the same kernels and launch
+ * shapes run whatever else is in flight, on a fresh or a cached handle.
  * --------------------------------------------------------------------- */
 typedef struct cc_server cc_server;
 
@@ -317,18 +333,24 @@ cc_status cc_server_create(cc_server** s, int device, size_t mem_budget, int max
 cc_status cc_server_submit(cc_server* s, const cc_problem* p_host, const cc_pnk_opts* opts, uint64_t* req_id);
 /* Non-blocking: *done = 1 when finished, then info (may be NULL) and the
  * solution (t1_host [o][v], t2_host [o][o][v][v], may be NULL) are copied
- * out and the request is released. Returns the solve's own status once
- * done. */
+ * out and the request is released (only its times are kept; a later poll of
+ * the same id is CC_ERR_ARG). Returns the solve's own status once done. */
 cc_status cc_server_poll(cc_server* s, uint64_t req_id, int* done, cc_info* info, double* t1_host, double* t2_host);
 /* Wait until every submitted request has finished. */
 cc_status cc_server_drain(cc_server* s);
 /* Admission/latency figures (host): queued, running, finished counts, peak
- * bytes admitted at once, and the per-request submit/admit/finish times in
- * seconds since server creation (arrays of length max_reqs, may be NULL). */
+ * bytes admitted at once (cached handles included), the host memory still
+ * held for requests, and the handle cache; cc_server_request_times gives
+ * one request's submit/admit/finish times in seconds since server creation
+ * (also after it was collected). */
 typedef struct {
   uint64_t queued, running, finished, rejected;
   size_t bytes_in_use, peak_bytes, budget;
   int max_slots, peak_running;
+  size_t host_bytes_held;   /* host copies of inputs and results not yet collected */
+  uint64_t requests_held;   /* requests submitted and not yet collected by a done poll */
+  size_t cached_bytes;      /* device bytes of cached idle handles (part of bytes_in_use) */
+  uint64_t cached_handles, handle_reuses;
 } cc_server_stats;
 cc_status cc_server_get_stats(cc_server* s, cc_server_stats* st);
 cc_status cc_server_request_times(cc_server* s, uint64_t req_id, double* t_submit, double* t_admit,
@@ -338,10 +360,6 @@ void cc_server_destroy(cc_server* s);
 /* ---------------------------------------------------------------------
  * Diagnostics (for kernel tests; not part of the solver path)
  * --------------------------------------------------------------------- */
-/* C = alpha * A * B + beta * C with element strides (A[m*a_m + k*a_k],
- * B[k*b_k + n*b_n], C[m*c_m + n*c_n]), all float64 device arrays, computed
- * on the matrix cores in precision `prec` (FP32/BF16: float accumulation).
- * This is the contraction kernel every residual term runs on. */
 /* Device timing of tagged work on the handle, with HIP events recorded on
  * the stream each launch runs on. Slots: 0 the particle-particle ladder
  * contraction (one launch per residual or J v), 1 whole residual
@@ -358,9 +376,26 @@ cc_status cc_diag_timing_read(cc_handle* h, int slot, int* count, double* total_
  * CC_NOT_CONVERGED if the iteration stalls. */
 cc_status cc_diag_hessenberg_eigenvalues(int m, const double* H, double* re, double* im);
 
+/* C = alpha * A * B + beta * C with element strides (A[m*a_m + k*a_k],
+ * B[k*b_k + n*b_n], C[m*c_m + n*c_n]), all float64 device arrays, computed
+ * on the matrix cores in precision `prec` (FP32/BF16: float accumulation).
+ * This is the contraction kernel every residual term runs on. */
 cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_t a_k, const double* B,
                        int64_t b_k, int64_t b_n, double* C, int64_t c_m, int64_t c_n, double alpha, double beta,
                        cc_precision prec, void* stream);
+
+/* Batched cc_diag_gemm: C[b] = alpha A[b] B[b] + beta C[b] for b < nbatch,
+ * with batch strides a_b, b_b, c_b (elements) added to the three base
+ * pointers. flags bit 0: round FP64 operands of an FP32/BF16 product once
+ * into a scratch copy (rows contiguous along k) before the product, as the
+ * residual and J v do for their large products; bit 1: allow split-K (the
+ * contraction cut into chunks whose partial sums are added in a fixed
+ * order) when the output tiles cannot fill the GPU. The scratch memory is
+ * allocated and freed inside the call (diagnostics only). Synchronises. */
+cc_status cc_diag_gemm_batched(int M, int N, int K, int nbatch, const double* A, int64_t a_m, int64_t a_k,
+                               int64_t a_b, const double* B, int64_t b_k, int64_t b_n, int64_t b_b, double* C,
+                               int64_t c_m, int64_t c_n, int64_t c_b, double alpha, double beta, cc_precision prec,
+                               int flags, void* stream);
 
 #ifdef __cplusplus
 }

@@ -41,7 +41,8 @@ class cc_pnk_opts(ctypes.Structure):
                 ("gamma", ctypes.c_double), ("alpha", ctypes.c_double), ("eta0", ctypes.c_double),
                 ("eta_max", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("inner_restart", ctypes.c_int), ("jvp_prec", ctypes.c_int), ("use_fd_jvp", ctypes.c_int),
-                ("init_mp2", ctypes.c_int), ("protocol", ctypes.c_int), ("ccd", ctypes.c_int)]
+                ("init_mp2", ctypes.c_int), ("protocol", ctypes.c_int), ("ccd", ctypes.c_int),
+                ("stall_window", ctypes.c_int), ("stall_factor", ctypes.c_double)]
 
 
 class cc_fp_opts(ctypes.Structure):
@@ -58,7 +59,7 @@ class cc_info(ctypes.Structure):
     _fields_ = [("e_corr", ctypes.c_double), ("res_inf", ctypes.c_double), ("res_2", ctypes.c_double),
                 ("converged", ctypes.c_int), ("newton_iters", ctypes.c_int), ("n_residual", ctypes.c_int),
                 ("n_jvp", ctypes.c_int), ("n_afmv", ctypes.c_int), ("n_inner_iters", ctypes.c_int),
-                ("seconds", ctypes.c_double)]
+                ("seconds", ctypes.c_double), ("stalled", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -67,7 +68,10 @@ class cc_info(ctypes.Structure):
 class cc_server_stats(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_uint64), ("running", ctypes.c_uint64), ("finished", ctypes.c_uint64),
                 ("rejected", ctypes.c_uint64), ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
-                ("budget", ctypes.c_size_t), ("max_slots", ctypes.c_int), ("peak_running", ctypes.c_int)]
+                ("budget", ctypes.c_size_t), ("max_slots", ctypes.c_int), ("peak_running", ctypes.c_int),
+                ("host_bytes_held", ctypes.c_size_t), ("requests_held", ctypes.c_uint64),
+                ("cached_bytes", ctypes.c_size_t), ("cached_handles", ctypes.c_uint64),
+                ("handle_reuses", ctypes.c_uint64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -121,6 +125,9 @@ SIGNATURES = {
     "cc_diag_timing_read": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
     "cc_diag_gemm": (I, [I, I, I, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64, P,
                          ctypes.c_int64, ctypes.c_int64, D, D, I, P]),
+    "cc_diag_gemm_batched": (I, [I, I, I, I, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
+                                 ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                 D, D, I, I, P]),
 }
 
 _lib = None

@@ -182,6 +182,8 @@ PnkOptions to_internal(const cc_pnk_opts& o) {
   r.init_mp2 = o.init_mp2 != 0;
   r.protocol = (int)o.protocol;
   r.ccd = o.ccd != 0;
+  r.stall_window = o.stall_window;
+  r.stall_factor = o.stall_factor;
   return r;
 }
 
@@ -196,6 +198,8 @@ void check_pnk_opts(const cc_pnk_opts& o) {
   PNK_REQUIRE(!(o.use_fd_jvp && o.jvp_prec != CC_FP64), "the finite-difference product is FP64 only");
   PNK_REQUIRE(o.eta_max > 0 && o.eta_max < 1 && o.eta0 > 0 && o.eta0 < 1, "forcing terms must be in (0, 1)");
   PNK_REQUIRE(o.protocol == CC_PNK || o.protocol == CC_NK || o.protocol == CC_INK, "unknown protocol");
+  PNK_REQUIRE(o.stall_window >= 0, "stall_window must be >= 0");
+  PNK_REQUIRE(o.stall_window == 0 || (o.stall_factor > 0 && o.stall_factor < 1), "stall_factor must be in (0, 1)");
 }
 
 int lowp_for(cc_precision p) { return p == CC_FP32 ? 1 : (p == CC_BF16 ? 2 : 0); }
@@ -267,6 +271,8 @@ void cc_pnk_opts_default(cc_pnk_opts* o) {
   o->init_mp2 = 1;
   o->protocol = CC_PNK;
   o->ccd = 0;
+  o->stall_window = 0;
+  o->stall_factor = 0.5;
 }
 
 void cc_fp_opts_default(cc_fp_opts* o) {
@@ -399,6 +405,7 @@ static void fill_info(const SolveStats& st, cc_info* info) {
   info->n_afmv = st.n_afmv;
   info->n_inner_iters = st.n_inner_iters;
   info->seconds = st.seconds;
+  info->stalled = st.stalled;
 }
 
 cc_status cc_solve_pnk(cc_handle* h, const cc_problem* p, const cc_pnk_opts* opts, double* t1, double* t2,
@@ -652,6 +659,51 @@ cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_
     return CC_ERR_HIP;
   }
   return CC_OK;
+}
+
+cc_status cc_diag_gemm_batched(int M, int N, int K, int nbatch, const double* A, int64_t a_m, int64_t a_k,
+                               int64_t a_b, const double* B, int64_t b_k, int64_t b_n, int64_t b_b, double* C,
+                               int64_t c_m, int64_t c_n, int64_t c_b, double alpha, double beta, cc_precision prec,
+                               int flags, void* stream) {
+  if (M < 1 || N < 1 || K < 1 || nbatch < 1 || !A || !B || !C) return CC_ERR_ARG;
+  if (prec != CC_FP64 && prec != CC_FP32 && prec != CC_BF16) return CC_ERR_ARG;
+  if (flags & ~3) return CC_ERR_ARG;
+  hipStream_t s = (hipStream_t)stream;
+  void* cast = nullptr;
+  double* ws = nullptr;
+  cc_status st = CC_OK;
+  try {
+    GemmDesc d;
+    d.M = M; d.N = N; d.K = K;
+    d.nb0 = nbatch;
+    d.a_m = a_m; d.a_k = a_k; d.a_b0 = a_b;
+    d.b_k = b_k; d.b_n = b_n; d.b_b0 = b_b;
+    d.c_m = c_m; d.c_n = c_n; d.c_b0 = c_b;
+    d.alpha = alpha; d.beta = beta;
+    if (flags & 1) {
+      const int64_t es = prec == CC_BF16 ? 2 : 4;
+      d.cast_ws_bytes = es * (int64_t)nbatch * ((int64_t)M + N) * K + 512;
+      if (hipMalloc(&cast, d.cast_ws_bytes) != hipSuccess) throw OomError("diag_gemm: cast scratch");
+      d.cast_ws = cast;
+    }
+    if (flags & 2) {
+      d.ws_elems = std::min<int64_t>((int64_t)64 * nbatch * M * N, (int64_t)8 << 20);
+      if (hipMalloc((void**)&ws, d.ws_elems * sizeof(double)) != hipSuccess) throw OomError("diag_gemm: split-K scratch");
+      d.ws = ws;
+    }
+    gemm(d, A, Prec::F64, B, Prec::F64, C, Prec::F64, (Prec)prec, s);
+    PNK_HIP(hipStreamSynchronize(s));
+  } catch (const ArgError&) {
+    st = CC_ERR_ARG;
+  } catch (const OomError&) {
+    (void)hipGetLastError();
+    st = CC_ERR_OOM;
+  } catch (const std::exception&) {
+    st = CC_ERR_HIP;
+  }
+  if (cast) (void)hipFree(cast);
+  if (ws) (void)hipFree(ws);
+  return st;
 }
 
 }  // extern "C"

@@ -986,6 +986,8 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   }
   mask(x);
   double rn_prev = 0.0, eta = opt.eta0;
+  double stall_ref = 0.0;
+  int stall_k = 0;
   int k = 0;
   std::vector<double> H, cs, sn, g, h;
   while (true) {
@@ -1003,6 +1005,15 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
                    st->n_jvp, st->n_afmv);
     if (!std::isfinite(rn)) { st->diverged = 1; break; }
     if (rinf < opt.tol_inf) { st->converged = 1; break; }
+    if (opt.stall_window > 0) {
+      if (k == 0 || rinf < opt.stall_factor * stall_ref) {
+        stall_ref = rinf;
+        stall_k = k;
+      } else if (k - stall_k >= opt.stall_window) {
+        st->stalled = 1;
+        break;
+      }
+    }
     if (k >= opt.max_newton) break;
     if (opt.protocol == PnkOptions::kINK) {
       // A_F dt = -r(t): one inner solve per step, no Jacobian products

@@ -27,6 +27,11 @@ struct PnkOptions {
   enum Protocol { kPNK = 0, kNK = 1, kINK = 2 };
   int protocol = kPNK;
   bool ccd = false;  // CCD level: t1 held at zero, singles equations dropped
+  // stagnation stop (0: off): end once stall_window Newton steps pass
+  // without ||r||_inf falling below stall_factor times its value at the
+  // last step where it did
+  int stall_window = 0;
+  double stall_factor = 0.5;
 };
 
 struct FpOptions {
@@ -45,6 +50,7 @@ struct SolveStats {
   int converged = 0, newton_iters = 0, n_residual = 0, n_jvp = 0, n_afmv = 0, n_inner_iters = 0;
   double seconds = 0.0;
   int diverged = 0;  // nonfinite residual norm
+  int stalled = 0;   // ended by the stagnation stop
 };
 
 // Krylov and history buffers for one problem size (device), plus pinned

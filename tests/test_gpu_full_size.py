@@ -1,0 +1,345 @@
+"""GPU parity at the full workload sizes, and on kernel configurations that
+only large shapes reach.
+
+* Matrix-core products in FP32/BF16 with 128 x 128 output tiles (taken when
+  a product has at least 256 of them, as the o v x o v ring products and
+  the ladder of the o=20/v=180 workload do), plain, transposed, batched and
+  with the operands rounded once into a scratch copy: elementwise against
+  float64 with the bound of the rounding model.
+* The residual (equation CC_ampl), the energy (equation CC_energy) and J v
+  at the o=16/v=144 and o=20/v=180 workloads: sampled elements and whole-
+  vector norms against values the oracle wrote (tests/golden/
+  make_residual_samples.py; the complex-step oracle product at these sizes
+  takes minutes, so it is not rerun here).
+* PNK solves of the o=20/v=180 workload in FP64, FP32 and BF16 J v: every
+  root is checked with the oracle's residual and energy, evaluated here.
+* The inner A_F solve on the packed pair layout with 64-wide virtual blocks.
+* The o=10/v=90 workload solved to 1e-10 against the oracle's converged
+  energy and amplitudes (tests/golden/make_energies.py).
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gen import make_config, make_problem, make_near_degenerate, random_amplitudes
+from oracle import ccsd, solvers
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2608_06669_amd as pk
+    pk.load()
+    assert torch.cuda.is_available(), "a GPU is required"
+    return pk
+
+
+@pytest.fixture(scope="module")
+def handle(lib):
+    h = lib.Handle(0)
+    yield h
+    h.close()
+
+
+def dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _args(p):
+    return p.f_oo, p.f_ov, p.f_vv, p.L
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# ----------------------------------------------- 128 x 128 FP32 / BF16 --
+# Rounding model: each FP64 operand is rounded once to the compute type
+# (unit roundoff u_in: 2^-24 for FP32, 2^-8 for BF16), products of two
+# rounded values are exact in float, and the K-term sum is accumulated in
+# float (2^-24 per addition). So |C - AB|_ij <= (2 u_in + u_in^2 + K 2^-24)
+# (|A| |B|)_ij, evaluated here with |A| |B| in float64.
+U_IN = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
+
+LAYOUTS = {
+    # name: (M, N, K, nbatch, transpose A, transpose B, precast)
+    "nn": (2100, 2100, 512, 1, False, False, False),
+    "tn": (2100, 2100, 512, 1, True, False, False),
+    "nt": (2100, 2100, 300, 1, False, True, False),
+    "nn_precast": (2100, 2100, 512, 1, False, False, True),
+    "tt_precast": (2100, 2050, 300, 1, True, True, True),
+    "batched": (1024, 1030, 300, 4, False, False, False),
+    "batched_precast_t": (1024, 1030, 300, 4, True, False, True),
+}
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("layout", sorted(LAYOUTS))
+def test_gemm_128_tiles_low_precision_elementwise(lib, prec, layout):
+    M, N, K, nb, ta, tb, pre = LAYOUTS[layout]
+    assert -(-M // 128) * -(-N // 128) * nb >= 256  # the 128 x 128 tile path
+    g = torch.Generator(device="cpu").manual_seed(M + 7 * N + 13 * K + nb)
+    A = torch.randn(nb, K, M, generator=g, dtype=torch.float64) if ta else \
+        torch.randn(nb, M, K, generator=g, dtype=torch.float64)
+    B = torch.randn(nb, N, K, generator=g, dtype=torch.float64) if tb else \
+        torch.randn(nb, K, N, generator=g, dtype=torch.float64)
+    Am = A.transpose(1, 2) if ta else A
+    Bm = B.transpose(1, 2) if tb else B
+    C0 = torch.randn(nb, M, N, generator=g, dtype=torch.float64)
+    ref = 0.5 * torch.bmm(Am.contiguous(), Bm.contiguous()) + 0.25 * C0
+    absprod = torch.bmm(Am.abs().contiguous(), Bm.abs().contiguous())
+    a_str = (1, M, M * K) if ta else (K, 1, M * K)
+    b_str = (1, K, N * K) if tb else (N, 1, N * K)
+    Cd = C0.cuda()
+    lib.diag_gemm_batched(A.cuda(), B.cuda(), Cd, a_str, b_str, (N, 1, M * N), M, N, K, nb, alpha=0.5, beta=0.25,
+                          prec=prec, precast=pre)
+    u = U_IN[prec]
+    bound = 0.5 * (2 * u + u * u + K * 2.0 ** -24) * absprod + 1e-15 * ref.abs()
+    err = (Cd.cpu() - ref).abs()
+    assert bool((err <= bound).all()), float((err / bound).max())
+    # the product did run in the low precision (an FP64 product would agree
+    # to about 1e-15 relative)
+    assert float(err.max()) > 1e-11 * float(ref.abs().max())
+
+
+# ------------------------------------- residual, energy, J v at C3 / C4 --
+def _sampled(x1, x2, g):
+    return np.ravel(x1)[g["index1"]], np.ravel(x2)[g["index2"]]
+
+
+@pytest.fixture(scope="module")
+def samples():
+    return _load("oracle_residual_samples.json")
+
+
+def _full_size_inputs(lib, name, g):
+    p = make_config(name)
+    a = g["amplitudes"]
+    t1, t2 = random_amplitudes(p.nocc, p.nvir, a["seed_t"], scale=a["scale_t"])
+    v1, v2 = random_amplitudes(p.nocc, p.nvir, a["seed_v"], scale=a["scale_v"])
+    return p, lib.DeviceProblem.from_problem(p), dev(t1), dev(t2), dev(v1), dev(v2)
+
+
+def _compare_sampled(y1, y2, ref, g, rel):
+    """Sampled elements within rel * max|ref| (both blocks), and the
+    whole-vector 2-norms and max-norms within rel of the oracle's."""
+    s1, s2 = _sampled(host(y1), host(y2), g)
+    scale = max(ref["max1"], ref["max2"])
+    e1 = np.abs(s1 - np.array(ref["s1"])).max()
+    e2 = np.abs(s2 - np.array(ref["s2"])).max()
+    assert e1 <= rel * scale and e2 <= rel * scale, (e1 / scale, e2 / scale)
+    n1 = float(torch.linalg.vector_norm(y1))
+    n2 = float(torch.linalg.vector_norm(y2))
+    assert abs(n1 - ref["norm1"]) <= rel * ref["norm1"] and abs(n2 - ref["norm2"]) <= rel * ref["norm2"]
+    m2 = float(y2.abs().max())
+    assert abs(m2 - ref["max2"]) <= rel * scale
+    return max(e1, e2) / scale
+
+
+@pytest.mark.parametrize("name", ["c3_neardeg", "c4_mixed"])
+def test_residual_energy_full_size_against_oracle(handle, lib, samples, name):
+    """FP64 residual and energy at seeded amplitudes of the o=16/v=144 and
+    o=20/v=180 workloads: sampled elements at 1e-10 of the largest component,
+    norms at 1e-10 relative, energy at 1e-12 relative."""
+    g = samples[name]
+    p, P, t1, t2, _, _ = _full_size_inputs(lib, name, g)
+    r1, r2, e = handle.residual(P, t1, t2, energy=True)
+    _compare_sampled(r1, r2, g["residual"], g, 1e-10)
+    assert abs(e - g["e_corr"]) <= 1e-12 * max(1.0, abs(g["e_corr"]))
+
+
+# Low-precision J v: every contraction rounds its FP64 operands once to the
+# compute type (unit roundoff u_in: 2^-24 FP32, 2^-8 BF16) and accumulates in
+# float (2^-24 per addition). The rounding errors of different terms are
+# independent, so an output element of a K-term sum is off by about
+# (u_in + sqrt(K) 2^-24) times the root-mean-square size of its terms times
+# sqrt(K), against a size of the same order for a sum of random-sign terms:
+# the error is O(u_in + sqrt(K) 2^-24) of the output's scale. The longest
+# contraction is the ladder's, K = v(v+1)/2 = 16290 pair indices at v = 180;
+# the bound allows 8 times that, relative to the largest component of J v.
+K_LADDER = 180 * 181 // 2
+JVP_REL = {"fp64": 1e-10,
+           "fp32": 8 * (2.0 ** -24 + K_LADDER ** 0.5 * 2.0 ** -24),
+           "bf16": 8 * (2.0 ** -8 + K_LADDER ** 0.5 * 2.0 ** -24)}
+
+
+@pytest.mark.parametrize("name", ["c3_neardeg", "c4_mixed"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_jvp_full_size_against_oracle(handle, lib, samples, name, prec):
+    """J v at the same amplitudes along a seeded direction, against the
+    oracle's complex-step product (exact to rounding): FP64 at 1e-10 of the
+    largest component; FP32 and BF16 within their rounding bounds."""
+    g = samples[name]
+    p, P, t1, t2, v1, v2 = _full_size_inputs(lib, name, g)
+    y1, y2 = handle.jvp(P, t1, t2, v1, v2, prec=prec)
+    torch.cuda.synchronize()
+    worst = _compare_sampled(y1, y2, g["jvp"], g, JVP_REL[prec])
+    print(f"{name} {prec}: largest sampled error {worst:.2e} of max|J v| (bound {JVP_REL[prec]:.1e})")
+
+
+# ----------------------------------------- C4 solves, roots checked -----
+@pytest.fixture(scope="module")
+def c4_fp64_root(handle, lib):
+    p = make_config("c4_mixed")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=200, jvp_prec="fp64")
+    return p, host(t1), host(t2), info
+
+
+def _oracle_root_check(p, t1, t2, info):
+    o1, o2 = ccsd.residual(*_args(p), t1, t2)
+    res = max(np.abs(o1).max(), np.abs(o2).max())
+    e_or = float(ccsd.energy(*_args(p), t1, t2))
+    return res, e_or
+
+
+def test_pnk_c4_fp64_root_is_an_oracle_root(c4_fp64_root):
+    """FP64 PNK on the o=20/v=180/naux=600 Haar-rotated workload to
+    max |R| < 1e-8: the amplitudes are a root of the oracle's residual at ten
+    times the stopping level, and the oracle's energy there equals the
+    device's to 1e-9 Eh."""
+    p, t1, t2, info = c4_fp64_root
+    assert info["status"] == "CC_OK", info
+    res, e_or = _oracle_root_check(p, t1, t2, info)
+    print(f"c4 fp64: E {info['e_corr']:.10f}, oracle max|R| {res:.2e}, |E_oracle - E| {abs(e_or - info['e_corr']):.2e}")
+    assert res < 1e-7
+    assert abs(e_or - info["e_corr"]) < 1e-9
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_pnk_c4_mixed_precision_root_and_energy(handle, lib, c4_fp64_root, prec):
+    """Mixed-precision PNK (J v in FP32 or BF16 with float accumulation;
+    residual, energy and Arnoldi in FP64) on the same workload: an oracle
+    root (max |R_oracle| < 1e-7) whose oracle energy equals the device's to
+    1e-9 Eh, and |E - E_FP64| <= 1e-6 Eh against the FP64 root above."""
+    p, f1, f2, ref = c4_fp64_root
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=200, jvp_prec=prec)
+    assert info["status"] == "CC_OK", info
+    res, e_or = _oracle_root_check(p, host(t1), host(t2), info)
+    dE = abs(info["e_corr"] - ref["e_corr"])
+    print(f"c4 {prec}: E {info['e_corr']:.10f}, |dE vs FP64| {dE:.2e}, oracle max|R| {res:.2e}, "
+          f"|E_oracle - E| {abs(e_or - info['e_corr']):.2e}, newton {info['newton_iters']}")
+    assert res < 1e-7
+    assert abs(e_or - info["e_corr"]) < 1e-9
+    assert dE <= 1e-6
+
+
+# ------------------------------------ inner solve with 64-wide blocks --
+@pytest.mark.parametrize("o,v,seed", [(12, 128, 61), (13, 129, 62)])
+def test_precond_solve_packed_64_wide_blocks(handle, lib, o, v, seed):
+    """The packed inner solve when the plan takes 64-wide virtual blocks
+    and the three-launch step (as the o=20/v=180 workload does): exact at
+    v = 128, ragged at v = 129 with an odd o. A_F products and the inverse
+    against the oracle."""
+    p = make_problem(o, v, 3 * (o + v), seed, gauge="haar")
+    P = lib.DeviceProblem.from_problem(p)
+    x1, x2 = random_amplitudes(o, v, seed + 100, scale=1.0)
+    y1, y2 = handle.fock_apply(P, dev(x1), dev(x2))
+    a1, a2 = solvers.fock_apply(p.f_oo, p.f_ov, p.f_vv, x1, x2)
+    assert np.abs(host(y1) - a1).max() <= 1e-13 * np.abs(a1).max()
+    assert np.abs(host(y2) - a2).max() <= 1e-13 * np.abs(a2).max()
+    e1, e2 = solvers.fock_solve_exact(p.f_oo, p.f_ov, p.f_vv, x1, x2)
+    for k in range(2):  # the second call replays the recorded graphs
+        s1, s2, iters, ok = handle.precond_solve(P, dev(x1), dev(x2), rtol=1e-12, maxit=300, pair_symmetric=True)
+        assert ok and 0 < iters < 300
+        assert np.abs(host(s1) - e1).max() <= 1e-10 * np.abs(e1).max()
+        assert np.abs(host(s2) - e2).max() <= 1e-10 * np.abs(e2).max()
+
+
+# ------------------------------------------- C2 against the oracle root --
+@pytest.fixture(scope="module")
+def c2_golden():
+    return _load("oracle_energies.json")["c2_haar"]
+
+
+def test_pnk_c2_matches_the_oracle_converged_solution(handle, lib, c2_golden):
+    """FP64 PNK on the Haar-rotated o=10/v=90 workload to max |R| < 1e-10
+    against the oracle's own PNK root (converged to 1e-11): energy to
+    1e-9 Eh, sampled amplitudes to 1e-8."""
+    g = c2_golden
+    assert g["converged"]
+    p = make_config("c2_haar")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-10, max_newton=200)
+    assert info["status"] == "CC_OK", info
+    print(f"c2: E {info['e_corr']:.12f} oracle {g['e_corr']:.12f}, newton {info['newton_iters']} "
+          f"(oracle {g['newton_iters']})")
+    assert abs(info["e_corr"] - g["e_corr"]) < 1e-9
+    s = g["sample"]
+    d1 = np.abs(host(t1).ravel()[s["t1_index"]] - np.array(s["t1"])).max()
+    d2 = np.abs(host(t2).ravel()[s["t2_index"]] - np.array(s["t2"])).max()
+    assert d1 < 1e-8 and d2 < 1e-8, (d1, d2)
+    assert abs(float(t2.abs().max()) - s["t2_max_abs"]) < 1e-8
+    assert abs(float(torch.linalg.vector_norm(t2)) - s["t2_norm"]) < 1e-8 * max(1.0, s["t2_norm"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_pnk_c2_mixed_precision_energy_against_the_oracle(handle, lib, c2_golden, prec):
+    """Mixed-precision PNK on the same workload to max |R| < 1e-8: the
+    energy within 1e-6 Eh of the oracle's converged energy."""
+    p = make_config("c2_haar")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=200, jvp_prec=prec)
+    assert info["status"] == "CC_OK", info
+    dE = abs(info["e_corr"] - c2_golden["e_corr"])
+    print(f"c2 {prec}: |E - E_oracle| {dE:.2e}, newton {info['newton_iters']}")
+    assert dE <= 1e-6
+
+
+# ----------------------------------- non-converging runs, step by step --
+@pytest.fixture(scope="module")
+def histories():
+    return _load("oracle_histories.json")
+
+
+def test_near_degenerate_pnk_stalls_like_the_oracle(handle, lib, histories):
+    """The near-degenerate recipe scaled down to o=4, v=36: the oracle's PNK
+    does not reach 1e-8 in 40 Newton steps (its tail is linear); the device
+    takes the same path: the same residual norms while they fall fast (to
+    1e-6 relative), the same step count and a final max |R| within a factor
+    of two of the oracle's."""
+    h = histories["neardeg_o4_v36"]
+    p = make_near_degenerate(4, 36, 120, 1003, sigma=0.08)
+    P = lib.DeviceProblem.from_problem(p)
+    _, _, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=40)
+    gh = handle.history()
+    oh = np.array([[r2, ri] for _, r2, ri in h["history"]])
+    print("device ||r||_inf:", " ".join(f"{x:.2e}" for x in gh[::4, 1]))
+    print("oracle ||r||_inf:", " ".join(f"{x:.2e}" for x in oh[::4, 1]))
+    assert info["status"] == "CC_NOT_CONVERGED" and not h["converged"]
+    assert info["newton_iters"] == h["newton_iters"] == 40
+    assert len(gh) == len(oh)
+    k = 6
+    assert np.allclose(gh[:k], oh[:k], rtol=1e-6, atol=0.0)
+    assert 0.5 <= info["res_inf"] / h["res_inf"] <= 2.0
+
+
+def test_fp_diis_c2_diverges_like_the_oracle(handle, lib, histories):
+    """FP+DIIS(8) on the Haar-rotated o=10/v=90 workload from the MP2 start:
+    the oracle diverges (||r||_2 above 1e6) and so does the device, at the
+    same iteration and through the same residual norms (1e-8 relative)."""
+    h = histories["c2_haar_fp_diis"]
+    p = make_config("c2_haar")
+    P = lib.DeviceProblem.from_problem(p)
+    _, _, info = handle.solve_fp_diis(P, tol_inf=1e-8, max_iter=10)
+    gh = handle.history()
+    oh = np.array([[r2, ri] for _, r2, ri in h["history"]])
+    assert info["status"] == "CC_NOT_CONVERGED" and not h["converged"]
+    assert info["n_residual"] == h["n_residual"]
+    assert len(gh) == len(oh)
+    assert np.allclose(gh, oh, rtol=1e-8, atol=0.0)
+    assert gh[-1, 0] > 1e6

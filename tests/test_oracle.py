@@ -316,6 +316,35 @@ def test_protocols_reach_one_root_in_a_rotated_gauge(ccd):
     assert abs(inkc.e_corr - ref.e_corr) < 1e-9
 
 
+# ------------------------------------------------------ forcing term -----
+# Eisenstat & Walker (SIAM J. Sci. Comput. 17 (1996) 16), choice 2, with the
+# paper's gamma = 0.9, alpha = 1.5 (Section "Adaptive Forcing"), eta_0 = 0.5,
+# eta_max = 0.9, the safeguard max(eta, gamma eta_prev^alpha) when
+# gamma eta_prev^alpha > 0.1, and the floor 0.5 tol / ||r_k||. Expected values
+# are decimal evaluations of those definitions:
+#   0.9 * 0.5**1.5  = 0.31819805153394637   (ratio ||r_k|| / ||r_{k-1}|| = 0.5)
+#   0.9 * 0.8**1.5  = 0.64398757751993940   (safeguard from eta_prev = 0.8)
+#   0.9 * 0.4**1.5  = 0.22768399153212330   (safeguard from eta_prev = 0.4)
+#   0.9 * 0.2**1.5  = 0.08049844718999243   (below 0.1: safeguard off)
+#   0.9 * 0.01**1.5 = 0.0009                (ratio 0.01)
+#   0.9 * 2**1.5    = 2.545584412271571     (ratio 2: above the cap)
+@pytest.mark.parametrize("k,rn,rn_prev,eta_prev,tol,expected", [
+    (0, 3.0, None, 0.5, 1e-8, 0.5),                       # first step: eta_0
+    (1, 0.5, 1.0, 0.8, 1e-12, 0.6439875775199394),        # safeguard above the plain term
+    (1, 0.5, 1.0, 0.2, 1e-12, 0.31819805153394637),       # safeguard off (0.0805 <= 0.1)
+    (1, 0.5, 1.0, 0.4, 1e-12, 0.31819805153394637),       # safeguard on but smaller
+    (1, 0.01, 1.0, 0.4, 1e-12, 0.2276839915321233),       # safeguard lifts 0.0009
+    (1, 0.01, 1.0, 0.2, 1e-12, 0.0009),                   # plain term, small
+    (1, 2.0, 1.0, 0.2, 1e-12, 0.9),                       # cap eta_max
+    (1, 0.01, 1.0, 1.0, 1e-12, 0.9),                      # safeguard 0.9 itself, at the cap
+    (1, 2e-8, 2e-6, 0.05, 1e-8, 0.25),                    # floor 0.5 * 1e-8 / 2e-8
+    (1, 4e-9, 4e-7, 0.05, 1e-8, 0.9),                     # floor 1.25 capped at eta_max
+])
+def test_forcing_term_branches(k, rn, rn_prev, eta_prev, tol, expected):
+    eta = solvers.forcing_term(k, rn, rn_prev, eta_prev, tol)
+    assert eta == pytest.approx(expected, rel=1e-13, abs=0.0)
+
+
 # ---------------------------------------------------------- constants ----
 def test_paper_constants():
     with open(os.path.join(GOLDEN, "paper_constants.json")) as fh:
