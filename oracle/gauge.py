@@ -188,4 +188,6 @@ class GaugeProblem(_Problem):
                     b, rtol=rtol, maxit=maxit, restart=restart)
         info.n_afmv += res.iters
         info.n_inner_iters += res.iters
-        return self.mask(res.x)
+        # gauge amplitudes keep the pair symmetry: the same W maps i and j,
+        # and a and b
+        return self.amplitude_space(res.x)

@@ -23,7 +23,10 @@ path).
   accelerated by DIIS (Pulay, Chem. Phys. Lett. 73 (1980) 393).
 
 Readings where the paper is silent (each is listed with its reason in the
-design notes): the stopping test uses ||r||_inf; the forcing test uses the
+design notes): the unknowns are the closed-shell amplitudes, doubles with
+t_ij^ab = t_ji^ba, so every preconditioned vector is projected onto that
+space (the identity on it in exact arithmetic); the stopping test uses
+||r||_inf; the forcing test uses the
 preconditioned GMRES residual estimate |g_{m+1}| <= eta_k beta; eta_0 = 0.5
 and the Eisenstat-Walker safeguards (choice 2 of Eisenstat & Walker, SIAM J.
 Sci. Comput. 17 (1996) 16) with eta_max = 0.9; the update sums the basis
@@ -181,6 +184,16 @@ class _Problem:
             x[: self.o * self.v] = 0.0
         return x
 
+    def amplitude_space(self, x):
+        """Orthogonal projection onto the space the unknowns live in: doubles
+        with t_ij^ab = t_ji^ba (closed-shell amplitudes; the residual has the
+        same symmetry), and zero singles at the CCD level. Every vector the
+        solvers build from such amplitudes lies in it in exact arithmetic;
+        the projection removes what rounding leaves outside it, where the
+        Jacobian of the equations as written is not that of any amplitude
+        (left in, it makes the Newton tail linear on hard problems)."""
+        return self.mask(pair_symmetrize(x, self.o, self.v))
+
     def residual(self, x):
         return self.mask(pack(*ccsd.residual(self.f_oo, self.f_ov, self.f_vv, self.L, *unpack(x, self.o, self.v))))
 
@@ -204,7 +217,7 @@ class _Problem:
                     b, rtol=rtol, maxit=maxit, restart=restart)
         info.n_afmv += res.iters
         info.n_inner_iters += res.iters
-        return self.mask(res.x)
+        return self.amplitude_space(res.x)
 
 
 def _make_problem(f_oo, f_ov, f_vv, L, ccd, gauge):
@@ -253,7 +266,8 @@ def solve_pnk(f_oo, f_ov, f_vv, L, tol=1e-8, max_newton=100, m_max=20,
 
     def Ainv(b):
         if not precond:
-            return b.copy()
+            # NK: no preconditioner, the identity on the amplitude space
+            return P.amplitude_space(b)
         return P.precond(b, inner_rtol, inner_maxit, inner_restart, info)
 
     if x0 is None:
