@@ -1,20 +1,23 @@
 """Benchmark: PNK CCSD solves/s on one MI355X.
 
-One step = one complete FP64 PNK solve of the Haar-rotated (non-canonical
-gauge) workload nocc=10, nvir=90, naux=300 to ||r||_inf < 1e-8: integral
-preparation (the symmetry-adapted (ac|bd) tensor from the DF factors), MP2
-start, residuals, J v products, inner A_F solves, outer Arnoldi and the final
-energy. Every step solves a fresh device copy of the problem, so nothing
-derived from the integrals is reused across steps. Inputs are resident in
-HBM when the timed region starts.
+One step = one complete mixed-precision PNK solve of the o=20/v=180/naux=600
+Haar-rotated workload to ||r||_inf < 1e-8: integral preparation (the
+symmetry-adapted (ac|bd) tensor from the DF factors), MP2 start, FP64
+residuals, J v products in BF16 on the matrix cores with float
+accumulation, inner A_F solves, FP64 Arnoldi, Givens and updates, and the
+FP64 energy. Every step solves a fresh device copy of the problem, so
+nothing derived from the integrals is reused across steps. Inputs are
+resident in HBM when the timed region starts.
 
-Prints one JSON line. `roofline` is for the kernel that takes the largest
-share of the solve, the fused first kernel of the inner Lanczos step (the
-previous step's update and the A_F virtual contractions on the packed
-pairs): its launches are timed with HIP event nodes inside the replayed
-graph, on the stream they run on, over the timed region, in one inner solve
-of eight (each bracketed launch pays for its two event nodes; bracketing
-every launch would slow the solve by about a tenth).
+Prints one JSON line: solves/s, p50/p99 latency of the solves, the energy
+difference against an FP64 solve of the same problem (untimed, when the
+run's time allows it) and the oracle's residual and energy at the
+mixed-precision root. `roofline` is for the residual evaluation (its
+matrix-core contractions, FP64): algorithmic flops per residual over its
+duration measured with HIP events on its stream during the timed region.
+`roofline_inner` is the same for the occupied A_F launch of the inner solve
+(HBM bound). Other workloads: --workload c2_haar | c3_neardeg | c4_single |
+serving | inner | protocols | levelshift | gauge | residual.
 """
 
 from __future__ import annotations
@@ -30,13 +33,23 @@ sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
 HBM_PEAK_GBS = 8000.0
-WORKLOAD = "c2_haar"
+WORKLOAD = "c2_haar"      # the FP64 solve line (--workload c2_haar)
+HEADLINE = "c4_mixed"     # the default line
+# The driver's window for the whole default run; the untimed FP64 reference
+# solve is skipped when it would not fit.
+RUN_BUDGET_S = 540.0
 # HBM bytes per launch of the fused first kernel of the inner Lanczos step
 # (packed pair layout) on this workload, from the rocprofv3 FETCH_SIZE /
 # WRITE_SIZE passes in profiles/fock_vir_lz_kernel_c2_haar_counters.md
 # (each scaled by the same counter for a copy kernel of known size). None
 # when the kernel has changed since the counters were taken.
 VIR_LZ_TRAFFIC_BYTES = 33288550
+# HBM bytes of one residual evaluation and of one occupied A_F launch on the
+# default workload, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (each
+# scaled by the same counter for a copy kernel of known size); None until
+# counters of the current kernels are taken.
+RESIDUAL_TRAFFIC_BYTES = None
+OCC_PACKED_TRAFFIC_BYTES = None
 
 
 def nominal_residual_flops(o, v, naux):
@@ -204,6 +217,187 @@ def bench_c2(args):
     h.close()
 
 
+def residual_algorithmic_flops(o, v, naux):
+    """Flops of one residual as evaluated here: the nominal count with the
+    particle-particle ladder at o^2 v^4 (its symmetric / antisymmetric pair
+    form contracts v(v+1)/2 and v(v-1)/2 pair indices instead of v^2)."""
+    return nominal_residual_flops(o, v, naux) - o * o * v ** 4
+
+
+def occ_packed_bytes(o, v):
+    """Algorithmic HBM bytes of one occupied A_F launch of the packed inner
+    step (three-launch form): v_k, the virtual part of p and v_{k-1} read,
+    p written, n_l = o v + o (o + 1) / 2 v^2 elements each."""
+    nl = o * v + o * (o + 1) // 2 * v * v
+    return 8 * 4 * nl
+
+
+def cpu_baseline_sample(problem, counts, t1_gpu, t2_gpu, e_gpu):
+    """The oracle on the host, on a bounded sample of the same workload: one
+    residual evaluation (at the device's root, which also checks it) and a
+    few A_F products of its GMRES. A complex-step J v costs at least one
+    residual (it evaluates the residual once in complex arithmetic), so each
+    is counted as one residual: the rate is an upper bound of the oracle's."""
+    import numpy as np
+
+    from oracle import ccsd, solvers
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    p = problem
+    o, v = p.nocc, p.nvir
+    t0 = time.perf_counter()
+    r1, r2 = ccsd.residual(p.f_oo, p.f_ov, p.f_vv, p.L, t1_gpu, t2_gpu)
+    t_res = time.perf_counter() - t0
+    e_or = float(ccsd.energy(p.f_oo, p.f_ov, p.f_vv, p.L, t1_gpu, t2_gpu))
+    t0 = time.perf_counter()
+    _, _, res = solvers.fock_solve_gmres(p.f_oo, p.f_ov, p.f_vv, r1, r2, rtol=1e-12, maxit=4)
+    t_af = (time.perf_counter() - t0) / max(res.iters, 1)
+    per_solve = (counts["n_residual"] + counts["n_jvp"]) * t_res + counts["n_afmv"] * t_af
+    out = {"value": 1.0 / per_solve, "unit": "solves/s", "cores": int(threads), "kind": "oracle",
+           "sample": (f"oracle (numpy FP64) on {o}/{v}/{p.naux}: 1 residual {t_res:.1f} s, {res.iters} A_F "
+                      f"products {t_af * res.iters:.2f} s; scaled by the device solve's {counts['n_residual']} "
+                      f"residuals, {counts['n_jvp']} J v (each counted as one residual, a lower bound of the "
+                      f"complex-step product) and {counts['n_afmv']} A_F products -> {per_solve:.0f} s per solve "
+                      f"(an upper bound of the oracle's rate)")}
+    check = {"oracle_res_inf_at_root": float(max(np.abs(r1).max(), np.abs(r2).max())),
+             "abs_dE_oracle_energy_at_root": float(abs(e_or - e_gpu))}
+    return out, check
+
+
+def bench_headline(args):
+    """The default line: mixed-precision PNK solves of c4_mixed."""
+    import torch
+
+    import paper_2608_06669_amd as pk
+    from gen import make_config
+
+    t_begin = time.perf_counter()
+    pk.load()
+    p = make_config(HEADLINE)
+    o, v, naux = p.nocc, p.nvir, p.naux
+    tol = p.meta["tol"]
+    prec = args.prec or "bf16"
+    h = pk.Handle(0)
+    nsteps = args.warmup + args.steps
+    probs = [pk.DeviceProblem.from_problem(p) for _ in range(nsteps)]
+    torch.cuda.synchronize()
+
+    def step(P, jprec):
+        return h.solve_pnk(P, tol_inf=tol, max_newton=200, jvp_prec=jprec, inner_rtol=args.inner_rtol)
+
+    for i in range(args.warmup):
+        step(probs[i], prec)
+        print(f"warm-up solve {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    h.timing(True)
+    lat, infos = [], []
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.warmup, nsteps):
+        s0 = time.perf_counter()
+        t1, t2, info = step(probs[i], prec)
+        lat.append(time.perf_counter() - s0)  # solve_pnk returns after its final sync
+        infos.append(info)
+        print(f"solve {i + 1 - args.warmup}/{args.steps}: {lat[-1]:.2f} s, {info['status']}", file=sys.stderr,
+              flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    n_res, ms_res = h.timing_read(1)
+    n_jvp, ms_jvp = h.timing_read(2)
+    n_afm, ms_afm = h.timing_read(3)
+    n_pre, ms_pre = h.timing_read(4)
+    h.timing(False)
+    ok = all(x["status"] == "CC_OK" for x in infos)
+    e = infos[-1]["e_corr"]
+    lat_ms = sorted(1000.0 * x for x in lat)
+
+    def pct(q):
+        k = min(len(lat_ms) - 1, max(0, int(round(q / 100.0 * (len(lat_ms) - 1)))))
+        return lat_ms[k]
+
+    # FP64 reference solve of the same problem (untimed), when it fits the
+    # run's window: about 1.7 mixed-precision solves, plus the oracle leg
+    ref = None
+    spent = time.perf_counter() - t_begin
+    est = 1.9 * (elapsed / max(args.steps, 1)) + 60.0
+    if prec != "fp64" and spent + est < RUN_BUDGET_S:
+        s0 = time.perf_counter()
+        _, _, ri = step(probs[0], "fp64")
+        ref = {"status": ri["status"], "e_corr": ri["e_corr"], "newton_iters": ri["newton_iters"],
+               "seconds": time.perf_counter() - s0}
+        print(f"FP64 reference solve: {ref['seconds']:.1f} s", file=sys.stderr, flush=True)
+
+    F_R = nominal_residual_flops(o, v, naux)
+    F_alg = residual_algorithmic_flops(o, v, naux)
+    res_ms = ms_res / max(n_res, 1)
+    roof = None
+    if n_res:
+        tf = F_alg / (res_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": tf, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": tf / FP64_PEAK_TFLOPS, "traffic": RESIDUAL_TRAFFIC_BYTES,
+                "kernel": "FP64 residual evaluation (recorded graph of matrix-core products: ladder in the "
+                          "symmetric/antisymmetric pair basis, ring, hole-hole, Fock and dressing terms)",
+                "launches_timed": n_res, "avg_ms": res_ms, "flops_per_launch": F_alg}
+    roof_inner = None
+    if n_afm:
+        af_ms = ms_afm / n_afm
+        b = occ_packed_bytes(o, v)
+        gbs = b / (af_ms * 1e-3) / 1e9
+        roof_inner = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                      "frac": gbs / HBM_PEAK_GBS, "traffic": OCC_PACKED_TRAFFIC_BYTES,
+                      "kernel": "fock_occ_packed_kernel (occupied A_F contractions of the inner Lanczos step on "
+                                "the packed pairs)", "launches_timed": n_afm, "avg_us": af_ms * 1e3,
+                      "bytes_per_launch": b}
+    out = {
+        "metric": "PNK CCSD solves/s + p50/p99 latency at |dE|<1e-6 Eh; residual TFLOP/s vs FP64",
+        "value": args.steps / elapsed,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+bf16" if prec == "bf16" else ("f64+f32" if prec == "fp32" else "f64"),
+        "data": "synthetic",
+        "config": {"workload": f"{HEADLINE}: RCCSD Haar-rotated gauge, nocc={o} nvir={v} naux={naux}, "
+                               f"mixed-precision PNK (J v in {prec.upper()} on the matrix cores with float "
+                               f"accumulation; residual, energy, Arnoldi, least squares and update in FP64; "
+                               f"m_max 20, A_F^-1 by inner Lanczos/GMRES rtol {args.inner_rtol:g}) to "
+                               f"||r||_inf<{tol:g}, one solve per step",
+                   "nocc": o, "nvir": v, "naux": naux, "tol_inf": tol, "jvp_prec": prec,
+                   "inner_rtol": args.inner_rtol,
+                   "latency": "per-solve latency of back-to-back solves (the serving stream is "
+                              "--workload serving)"},
+        "latency_ms": {"p50": pct(50), "p99": pct(99)},
+        "converged": ok,
+        "e_corr": e,
+        "fp64_reference": ref,
+        "abs_dE_vs_fp64_root": abs(e - ref["e_corr"]) if ref else None,
+        "counts_per_solve": {k: infos[-1][k] for k in ("newton_iters", "n_residual", "n_jvp", "n_afmv")},
+        "residual_tflops_fp64_nominal": F_R / (res_ms * 1e-3) / 1e12 if n_res else None,
+        "residual_tflops_fp64_algorithmic": F_alg / (res_ms * 1e-3) / 1e12 if n_res else None,
+        "residual_ms": res_ms if n_res else None,
+        "jvp_ms": ms_jvp / n_jvp if n_jvp else None,
+        "precond_solve_ms": ms_pre / n_pre if n_pre else None,
+        "time_share": {"residual": ms_res / (1000 * elapsed), "jvp": ms_jvp / (1000 * elapsed),
+                       "precond_solve": ms_pre / (1000 * elapsed)},
+        "roofline": roof,
+        "roofline_inner": roof_inner,
+    }
+    if not args.no_cpu_baseline:
+        cb, check = cpu_baseline_sample(p, infos[-1], t1.cpu().numpy(), t2.cpu().numpy(), e)
+        out["cpu_baseline"] = cb
+        out.update(check)
+    out["run_seconds"] = time.perf_counter() - t_begin
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
 def bench_large(args):
     """One PNK solve of a larger workload (near-degenerate o=16/v=144 or the
     mixed-precision o=20/v=180), J v in the requested precision; prints one
@@ -214,15 +408,17 @@ def bench_large(args):
     from gen import make_config
 
     pk.load()
-    p = make_config(args.workload)
+    p = make_config("c4_mixed" if args.workload == "c4_single" else args.workload)
     o, v, naux = p.nocc, p.nvir, p.naux
     tol = p.meta["tol"]
+    args.prec = args.prec or "fp64"
     h = pk.Handle(0)
     P = pk.DeviceProblem.from_problem(p)
     torch.cuda.synchronize()
     h.timing(True)
     t0 = time.perf_counter()
-    t1, t2, info = h.solve_pnk(P, tol_inf=tol, max_newton=args.max_newton, jvp_prec=args.prec)
+    t1, t2, info = h.solve_pnk(P, tol_inf=tol, max_newton=args.max_newton, jvp_prec=args.prec,
+                               inner_rtol=args.inner_rtol)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n_res, ms_res = h.timing_read(1)
@@ -232,6 +428,7 @@ def bench_large(args):
     hist = h.history()
     F_R = nominal_residual_flops(o, v, naux)
     out = {"workload": args.workload, "nocc": o, "nvir": v, "naux": naux, "tol_inf": tol, "jvp_prec": args.prec,
+           "inner_rtol": args.inner_rtol,
            "status": info["status"], "seconds": dt, "e_corr": info["e_corr"], "res_inf": info["res_inf"],
            "counts": {k: info[k] for k in ("newton_iters", "n_residual", "n_jvp", "n_afmv")},
            "residual_ms": ms_res / max(n_res, 1), "residual_tflops_fp64_nominal": F_R / (ms_res / max(n_res, 1) * 1e-3) / 1e12,
@@ -541,11 +738,14 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default=WORKLOAD, choices=[WORKLOAD, "c3_neardeg", "c4_mixed", "serving", "inner", "protocols", "levelshift",
-                                                      "gauge", "residual"],
+    ap.add_argument("--workload", default=HEADLINE,
+                    choices=[HEADLINE, WORKLOAD, "c3_neardeg", "c4_single", "serving", "inner", "protocols",
+                             "levelshift", "gauge", "residual"],
                     help="default: the bench line; the others print their own measurement line")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16"], help="J v precision (c3/c4)")
+    ap.add_argument("--prec", default=None, choices=["fp64", "fp32", "bf16"],
+                    help="J v precision (default line: bf16; c3_neardeg / c4_single: fp64)")
     ap.add_argument("--max-newton", type=int, default=200)
+    ap.add_argument("--inner-rtol", type=float, default=1e-12, help="A_F^-1 inner solve tolerance (c3/c4)")
     ap.add_argument("--layout", default="both", choices=["both", "full", "pairsym"],
                     help="inner: which inner-solve layout to time")
     ap.add_argument("--requests", type=int, default=40)
@@ -555,7 +755,9 @@ def main():
         print(f"bench.py runs on one GPU (asked for {args.gpus}): one solve is not sharded across GPUs here; "
               "see the design notes for how it would shard", file=sys.stderr)
         sys.exit(2)
-    if args.workload == WORKLOAD:
+    if args.workload == HEADLINE:
+        bench_headline(args)
+    elif args.workload == WORKLOAD:
         bench_c2(args)
     elif args.workload == "serving":
         bench_serving(args)

@@ -329,6 +329,8 @@ class Server:
         st = _lib().cc_server_poll(self._s, rid, ctypes.byref(done), ctypes.byref(info),
                                    t1.ctypes.data_as(ctypes.c_void_p) if t1 is not None else None,
                                    t2.ctypes.data_as(ctypes.c_void_p) if t2 is not None else None)
+        if st == L.CC_ERR_ARG:
+            raise CCError(st, f"unknown or already collected request {rid}")
         if not done.value:
             return None
         return dict(info.as_dict(), status=L.STATUS_NAMES.get(st, st), t1=t1, t2=t2)

@@ -1,6 +1,7 @@
 // C boundary of the library (include/pnkcc.h): argument checks, workspace
 // management, problem caching and status codes.
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -661,6 +662,20 @@ cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_
   return CC_OK;
 }
 
+}  // extern "C"
+
+namespace pnk {
+int64_t diag_splitk_elems(int64_t nbatch, int M, int N) {
+  return std::min<int64_t>(64 * nbatch * (int64_t)M * N, kDiagSplitElems);
+}
+int64_t diag_cast_bytes(int64_t nbatch, int M, int N, int K, cc_precision prec) {
+  const int64_t es = prec == CC_BF16 ? 2 : 4;
+  return es * nbatch * ((int64_t)M + N) * K + 512;
+}
+}  // namespace pnk
+
+extern "C" {
+
 cc_status cc_diag_gemm_batched(int M, int N, int K, int nbatch, const double* A, int64_t a_m, int64_t a_k,
                                int64_t a_b, const double* B, int64_t b_k, int64_t b_n, int64_t b_b, double* C,
                                int64_t c_m, int64_t c_n, int64_t c_b, double alpha, double beta, cc_precision prec,
@@ -680,14 +695,13 @@ cc_status cc_diag_gemm_batched(int M, int N, int K, int nbatch, const double* A,
     d.b_k = b_k; d.b_n = b_n; d.b_b0 = b_b;
     d.c_m = c_m; d.c_n = c_n; d.c_b0 = c_b;
     d.alpha = alpha; d.beta = beta;
-    if (flags & 1) {
-      const int64_t es = prec == CC_BF16 ? 2 : 4;
-      d.cast_ws_bytes = es * (int64_t)nbatch * ((int64_t)M + N) * K + 512;
+    if ((flags & 1) && prec != CC_FP64) {
+      d.cast_ws_bytes = diag_cast_bytes(nbatch, M, N, K, prec);
       if (hipMalloc(&cast, d.cast_ws_bytes) != hipSuccess) throw OomError("diag_gemm: cast scratch");
       d.cast_ws = cast;
     }
     if (flags & 2) {
-      d.ws_elems = std::min<int64_t>((int64_t)64 * nbatch * M * N, (int64_t)8 << 20);
+      d.ws_elems = diag_splitk_elems(nbatch, M, N);
       if (hipMalloc((void**)&ws, d.ws_elems * sizeof(double)) != hipSuccess) throw OomError("diag_gemm: split-K scratch");
       d.ws = ws;
     }

@@ -52,6 +52,11 @@ struct Handle {
 };
 
 size_t workspace_bytes(int o, int v, int naux, int lowp, int m_max, int restart, int diis);
+// Scratch sizes of the batched diagnostic product: split-K partial sums
+// (elements, at most kDiagSplitElems) and rounded operand copies (bytes).
+constexpr int64_t kDiagSplitElems = int64_t(4) << 20;
+int64_t diag_splitk_elems(int64_t nbatch, int M, int N);
+int64_t diag_cast_bytes(int64_t nbatch, int M, int N, int K, cc_precision prec);
 void check_problem(const cc_problem* p);
 void check_pnk_opts(const cc_pnk_opts& o);
 PnkOptions to_internal(const cc_pnk_opts& o);

@@ -306,26 +306,26 @@ def histories():
     return _load("oracle_histories.json")
 
 
-def test_near_degenerate_pnk_stalls_like_the_oracle(handle, lib, histories):
-    """The near-degenerate recipe scaled down to o=4, v=36: the oracle's PNK
-    does not reach 1e-8 in 40 Newton steps (its tail is linear); the device
-    takes the same path: the same residual norms while they fall fast (to
-    1e-6 relative), the same step count and a final max |R| within a factor
-    of two of the oracle's."""
+def test_near_degenerate_small_pnk_matches_the_oracle(handle, lib, histories):
+    """The near-degenerate recipe scaled down to o=4, v=36 (HOMO-LUMO gap
+    0.05 Eh, two levels on each side within 0.1 Eh of the Fermi level, DF
+    entries N(0, 0.08^2)): the oracle's PNK, iterating on the pair-symmetric
+    amplitude space, converges to 1e-8 in some twenty Newton steps; the
+    device takes the same path: the same residual norms (1e-6 relative)
+    while they fall fast, the same number of Newton steps within one, and
+    the same energy to 1e-9 Eh."""
     h = histories["neardeg_o4_v36"]
     p = make_near_degenerate(4, 36, 120, 1003, sigma=0.08)
     P = lib.DeviceProblem.from_problem(p)
     _, _, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=40)
     gh = handle.history()
     oh = np.array([[r2, ri] for _, r2, ri in h["history"]])
-    print("device ||r||_inf:", " ".join(f"{x:.2e}" for x in gh[::4, 1]))
-    print("oracle ||r||_inf:", " ".join(f"{x:.2e}" for x in oh[::4, 1]))
-    assert info["status"] == "CC_NOT_CONVERGED" and not h["converged"]
-    assert info["newton_iters"] == h["newton_iters"] == 40
-    assert len(gh) == len(oh)
-    k = 6
-    assert np.allclose(gh[:k], oh[:k], rtol=1e-6, atol=0.0)
-    assert 0.5 <= info["res_inf"] / h["res_inf"] <= 2.0
+    print("device ||r||_inf:", " ".join(f"{x:.2e}" for x in gh[::3, 1]))
+    print("oracle ||r||_inf:", " ".join(f"{x:.2e}" for x in oh[::3, 1]))
+    assert info["status"] == "CC_OK" and h["converged"], info
+    assert abs(info["newton_iters"] - h["newton_iters"]) <= 1
+    assert abs(info["e_corr"] - h["e_corr"]) < 1e-9
+    assert np.allclose(gh[:10], oh[:10], rtol=1e-6, atol=0.0)
 
 
 def test_fp_diis_c2_diverges_like_the_oracle(handle, lib, histories):

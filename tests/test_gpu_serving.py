@@ -96,3 +96,77 @@ def test_serving_results_match_the_oracle(lib):
         tol = 1e-9 if STREAM[k][3] == "fp64" else 1e-6
         assert res[k]["status"] == "CC_OK"
         assert abs(res[k]["e_corr"] - ref.e_corr) < tol, (k, res[k]["e_corr"], ref.e_corr)
+
+
+def test_serving_reuses_cached_handles_with_identical_results(lib):
+    """Requests of one shape and precision take over the handle a finished
+    one left (integral workspace, recorded graphs): the results are still
+    bit for bit those of solo solves, and the cache's memory stays inside
+    the budget."""
+    shapes = [(4, 20, "haar", "fp64"), (4, 20, "canonical", "fp64"), (4, 20, "haar", "bf16"),
+              (4, 20, "haar", "fp64"), (4, 20, "haar", "bf16"), (5, 25, "haar", "fp64")]
+    probs = [make_problem(o, v, 3 * (o + v), 7100 + k, gauge=g) for k, (o, v, g, _) in enumerate(shapes)]
+    h = lib.Handle(0)
+    solo = []
+    for p, (_, _, _, prec) in zip(probs, shapes):
+        t1, t2, info = h.solve_pnk(lib.DeviceProblem.from_problem(p), tol_inf=TOL, jvp_prec=prec)
+        solo.append((t1.cpu().numpy(), t2.cpu().numpy(), info))
+    h.close()
+    foot = max(_footprint(lib, p.nocc, p.nvir, p.naux, prec) for p, (_, _, _, prec) in zip(probs, shapes))
+    srv = lib.Server(0, mem_budget=3 * foot, max_slots=1)  # one slot: each request follows the previous one
+    try:
+        res = []
+        for p, (_, _, _, prec) in zip(probs, shapes):
+            rid = srv.submit(p, tol_inf=TOL, jvp_prec=prec)
+            srv.drain()
+            res.append(srv.poll(rid))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert stats["handle_reuses"] >= 3, stats
+    assert stats["peak_bytes"] <= 3 * foot
+    assert stats["cached_bytes"] <= stats["bytes_in_use"] <= 3 * foot
+    for r, (s1, s2, sinfo) in zip(res, solo):
+        assert r["status"] == "CC_OK"
+        assert r["e_corr"] == sinfo["e_corr"]
+        assert np.array_equal(r["t1"], s1) and np.array_equal(r["t2"], s2)
+
+
+def test_serving_host_memory_is_released(lib):
+    """Once a request has finished only its results are held on the host
+    (its input copies are dropped), and once collected nothing is held; a
+    collected request cannot be polled again but its times remain."""
+    probs = _problems()[:4]
+    srv = lib.Server(0, max_slots=2)
+    try:
+        ids = [srv.submit(p, tol_inf=1e-8) for p in probs]
+        srv.drain()
+        st = srv.stats()
+        results = sum(8 * (p.nocc * p.nvir + (p.nocc * p.nvir) ** 2) for p in probs)
+        assert st["requests_held"] == len(probs)
+        assert st["host_bytes_held"] == results, (st["host_bytes_held"], results)
+        for i in ids:
+            assert srv.poll(i, want_amplitudes=False)["status"] == "CC_OK"
+        st = srv.stats()
+        assert st["requests_held"] == 0 and st["host_bytes_held"] == 0
+        with pytest.raises(lib.CCError):
+            srv.poll(ids[0])
+        t_sub, t_adm, t_fin = srv.times(ids[0])
+        assert 0.0 <= t_sub <= t_adm <= t_fin
+    finally:
+        srv.close()
+
+
+def test_server_rejects_a_request_larger_than_the_budget(lib):
+    """A request whose footprint exceeds the whole budget can never run: it
+    is refused at submission with CC_ERR_REJECTED (nothing is queued)."""
+    p = make_problem(4, 20, 72, 7200, gauge="haar")
+    srv = lib.Server(0, mem_budget=1 << 20, max_slots=2)
+    try:
+        with pytest.raises(lib.CCError) as err:
+            srv.submit(p)
+        assert err.value.status == -5  # CC_ERR_REJECTED
+        st = srv.stats()
+        assert st["rejected"] == 1 and st["queued"] == 0 and st["finished"] == 0
+    finally:
+        srv.close()
