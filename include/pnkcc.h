@@ -397,6 +397,30 @@ cc_status cc_diag_gemm_batched(int M, int N, int K, int nbatch, const double* A,
                                int64_t c_m, int64_t c_n, int64_t c_b, double alpha, double beta, cc_precision prec,
                                int flags, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Allocation-free product (for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).
+ *
+ * cc_gemm_noalloc takes the arguments of cc_diag_gemm_batched and computes
+ * the same product with the same kernels and the same split-K chunks (its
+ * results are bitwise those of cc_diag_gemm_batched), but allocates
+ * nothing: its scratch (split-K partial sums, at most 4 Mi doubles, and the
+ * operand copies of flags bit 0, at most 32 MiB) is a fixed 64 MiB array
+ * that the library holds on each device it runs on until the process ends.
+ * A product whose rounded operand copies (2 bytes per element for BF16, 4
+ * for FP32, nbatch * (M + N) * K elements) exceed 32 MiB is refused with
+ * CC_ERR_OOM before any work is queued; split-K uses at most the 4 Mi
+ * doubles (fewer chunks when a product would need more). All calls on one
+ * device share its array: calls that overlap in time on one device race
+ * and must be ordered by the caller (one stream, or events). Does not
+ * synchronise; device pointers as for cc_diag_gemm_batched.
+ * --------------------------------------------------------------------- */
+cc_status cc_gemm_noalloc(int M, int N, int K, int nbatch, const double* A, int64_t a_m, int64_t a_k, int64_t a_b,
+                          const double* B, int64_t b_k, int64_t b_n, int64_t b_b, double* C, int64_t c_m,
+                          int64_t c_n, int64_t c_b, double alpha, double beta, cc_precision prec, int flags,
+                          void* stream);
+
 #ifdef __cplusplus
 }
 #endif

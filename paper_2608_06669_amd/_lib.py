@@ -128,6 +128,9 @@ SIGNATURES = {
     "cc_diag_gemm_batched": (I, [I, I, I, I, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
                                  ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                  D, D, I, I, P]),
+    "cc_gemm_noalloc": (I, [I, I, I, I, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,
+                            ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                            D, D, I, I, P]),
 }
 
 _lib = None

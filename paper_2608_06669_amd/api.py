@@ -279,6 +279,19 @@ def diag_gemm_batched(A, B, C, a_strides, b_strides, c_strides, M, N, K, nbatch,
     return C
 
 
+def gemm_noalloc(A, B, C, a_strides, b_strides, c_strides, M, N, K, nbatch, alpha=1.0, beta=0.0, prec="fp64",
+                 precast=False, splitk=False, stream=None):
+    """cc_gemm_noalloc: diag_gemm_batched's product with its scratch in the
+    library's fixed device array (no allocation; does not synchronise)."""
+    st = _lib().cc_gemm_noalloc(M, N, K, nbatch, _ptr(A), a_strides[0], a_strides[1], a_strides[2], _ptr(B),
+                                b_strides[0], b_strides[1], b_strides[2], _ptr(C), c_strides[0], c_strides[1],
+                                c_strides[2], alpha, beta, L.PRECISIONS[prec] if isinstance(prec, str) else int(prec),
+                                (1 if precast else 0) | (2 if splitk else 0), _stream(stream))
+    if st != L.CC_OK:
+        raise CCError(st, "cc_gemm_noalloc failed")
+    return C
+
+
 def hessenberg_eigenvalues(H) -> np.ndarray:
     """Eigenvalues of a real upper Hessenberg matrix by the library's host
     QR iteration (cc_diag_hessenberg_eigenvalues; no GPU needed)."""

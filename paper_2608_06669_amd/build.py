@@ -13,7 +13,7 @@ OUT = os.path.join(HERE, "libpnkcc.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["gemm.hip", "fock_op.hip", "tensor_ops.hip", "cc_kernels.hip", "ccsd.hip", "solvers.hip", "eig.hip", "gauge.hip", "api.hip",
-           "server.hip"]
+           "server.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
