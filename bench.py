@@ -370,7 +370,7 @@ def bench_headline(args):
                                f"m_max 20, A_F^-1 by inner Lanczos/GMRES rtol {args.inner_rtol:g}) to "
                                f"||r||_inf<{tol:g}, one solve per step",
                    "nocc": o, "nvir": v, "naux": naux, "tol_inf": tol, "jvp_prec": prec,
-                   "inner_rtol": args.inner_rtol,
+                   "inner_rtol": args.inner_rtol, "inner_rtol_jv": args.inner_rtol_jv or 0.0,
                    "latency": "per-solve latency of back-to-back solves (the serving stream is "
                               "--workload serving)"},
         "latency_ms": {"p50": pct(50), "p99": pct(99)},
@@ -418,7 +418,7 @@ def bench_large(args):
     h.timing(True)
     t0 = time.perf_counter()
     t1, t2, info = h.solve_pnk(P, tol_inf=tol, max_newton=args.max_newton, jvp_prec=args.prec,
-                               inner_rtol=args.inner_rtol)
+                               inner_rtol=args.inner_rtol, inner_rtol_jv=args.inner_rtol_jv or 0.0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     n_res, ms_res = h.timing_read(1)
@@ -746,6 +746,8 @@ def main():
                     help="J v precision (default line: bf16; c3_neardeg / c4_single: fp64)")
     ap.add_argument("--max-newton", type=int, default=200)
     ap.add_argument("--inner-rtol", type=float, default=1e-12, help="A_F^-1 inner solve tolerance (c3/c4)")
+    ap.add_argument("--inner-rtol-jv", type=float, default=None,
+                    help="tolerance of the inner solves of A_F^-1 J q in the Krylov loop (0: --inner-rtol)")
     ap.add_argument("--layout", default="both", choices=["both", "full", "pairsym"],
                     help="inner: which inner-solve layout to time")
     ap.add_argument("--requests", type=int, default=40)

@@ -165,7 +165,12 @@ cc_status cc_precond_solve_pairsym(cc_handle* h, const cc_problem* p, const doub
  *            the solve ends as CC_NOT_CONVERGED, with info->stalled = 1,
  *            once stall_window Newton steps have passed without ||r||_inf
  *            falling below stall_factor times its value at the last step
- *            where it did (the first step counts as such) */
+ *            where it did (the first step counts as such)
+ * inner_rtol_jv: tolerance of the inner solves of A_F^-1 (J q) inside the
+ *            Krylov loop (0: inner_rtol). The right-hand side solve
+ *            A_F^-1 r of each Newton step keeps inner_rtol. With J v in FP32
+ *            or BF16 the products carry relative errors of about 1e-6 or
+ *            1e-3, which bounds what a tighter inner solve can add */
 typedef enum { CC_PNK = 0, CC_NK = 1, CC_INK = 2 } cc_protocol;
 
 typedef struct {
@@ -183,6 +188,7 @@ typedef struct {
   int ccd;
   int stall_window;
   double stall_factor;
+  double inner_rtol_jv;
 } cc_pnk_opts;
 
 /* FP (+ level shift, + DIIS) options: t <- t - r/(D + level_shift) with D
@@ -213,7 +219,7 @@ typedef struct {
 /* Defaults: tol 1e-8, 100 Newton steps, m_max 20, gamma 0.9, alpha 1.5,
  * eta0 0.5, eta_max 0.9, inner rtol 1e-12, inner maxit 200, restart 30,
  * FP64 products, analytic J v, MP2 start, PNK, CCSD, no stagnation stop
- * (stall_window 0, stall_factor 0.5). */
+ * (stall_window 0, stall_factor 0.5), inner_rtol_jv 0 (= inner_rtol). */
 void cc_pnk_opts_default(cc_pnk_opts* o);
 /* Defaults: tol 1e-8, 500 iterations, DIIS 8 from iteration 2, no shift,
  * MP2 start, CCSD. */
@@ -409,7 +415,8 @@ cc_status cc_diag_gemm_batched(int M, int N, int K, int nbatch, const double* A,
  * operand copies of flags bit 0, at most 32 MiB) is a fixed 64 MiB array
  * that the library holds on each device it runs on until the process ends.
  * A product whose rounded operand copies (2 bytes per element for BF16, 4
- * for FP32, nbatch * (M + N) * K elements) exceed 32 MiB is refused with
+ * for FP32, nbatch * (M + N) * K' elements, K' = K rounded up to a multiple
+ * of 8 for BF16 and of 4 for FP32) exceed 32 MiB is refused with
  * CC_ERR_OOM before any work is queued; split-K uses at most the 4 Mi
  * doubles (fewer chunks when a product would need more). All calls on one
  * device share its array: calls that overlap in time on one device race

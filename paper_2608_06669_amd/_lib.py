@@ -42,7 +42,8 @@ class cc_pnk_opts(ctypes.Structure):
                 ("eta_max", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("inner_maxit", ctypes.c_int),
                 ("inner_restart", ctypes.c_int), ("jvp_prec", ctypes.c_int), ("use_fd_jvp", ctypes.c_int),
                 ("init_mp2", ctypes.c_int), ("protocol", ctypes.c_int), ("ccd", ctypes.c_int),
-                ("stall_window", ctypes.c_int), ("stall_factor", ctypes.c_double)]
+                ("stall_window", ctypes.c_int), ("stall_factor", ctypes.c_double),
+                ("inner_rtol_jv", ctypes.c_double)]
 
 
 class cc_fp_opts(ctypes.Structure):

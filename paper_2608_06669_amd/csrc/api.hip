@@ -185,6 +185,7 @@ PnkOptions to_internal(const cc_pnk_opts& o) {
   r.ccd = o.ccd != 0;
   r.stall_window = o.stall_window;
   r.stall_factor = o.stall_factor;
+  r.inner_rtol_jv = o.inner_rtol_jv;
   return r;
 }
 
@@ -201,6 +202,7 @@ void check_pnk_opts(const cc_pnk_opts& o) {
   PNK_REQUIRE(o.protocol == CC_PNK || o.protocol == CC_NK || o.protocol == CC_INK, "unknown protocol");
   PNK_REQUIRE(o.stall_window >= 0, "stall_window must be >= 0");
   PNK_REQUIRE(o.stall_window == 0 || (o.stall_factor > 0 && o.stall_factor < 1), "stall_factor must be in (0, 1)");
+  PNK_REQUIRE(o.inner_rtol_jv == 0 || (o.inner_rtol_jv > 0 && o.inner_rtol_jv < 1), "inner_rtol_jv must be 0 or in (0, 1)");
 }
 
 int lowp_for(cc_precision p) { return p == CC_FP32 ? 1 : (p == CC_BF16 ? 2 : 0); }
@@ -274,6 +276,7 @@ void cc_pnk_opts_default(cc_pnk_opts* o) {
   o->ccd = 0;
   o->stall_window = 0;
   o->stall_factor = 0.5;
+  o->inner_rtol_jv = 0.0;
 }
 
 void cc_fp_opts_default(cc_fp_opts* o) {
@@ -669,8 +672,9 @@ int64_t diag_splitk_elems(int64_t nbatch, int M, int N) {
   return std::min<int64_t>(64 * nbatch * (int64_t)M * N, kDiagSplitElems);
 }
 int64_t diag_cast_bytes(int64_t nbatch, int M, int N, int K, cc_precision prec) {
-  const int64_t es = prec == CC_BF16 ? 2 : 4;
-  return es * nbatch * ((int64_t)M + N) * K + 512;
+  // rows of the copies padded to 16 bytes
+  const int64_t es = prec == CC_BF16 ? 2 : 4, per = 16 / es;
+  return es * nbatch * ((int64_t)M + N) * ((K + per - 1) / per * per) + 512;
 }
 }  // namespace pnk
 

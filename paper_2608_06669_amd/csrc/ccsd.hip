@@ -129,6 +129,9 @@ void Timers::reset() {
 
 namespace {
 
+// n rounded up to a multiple of m
+int64_t pad_to(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
+
 struct Sizes {
   int64_t o, v, naux, np, n, ov, n2, p2, p2m, o2, wna;
   explicit Sizes(int o_, int v_, int naux_)
@@ -151,10 +154,11 @@ int64_t splitk_elems(const Sizes& z) {
 }
 
 // Rounded copies of FP64 operands for the FP32/BF16 products of J v: room
-// for both operands of the largest dual product (the ring term, 2ov x 2ov).
+// for both operands of the largest dual product (the ring term, 2ov x 2ov),
+// with rows padded to 16 bytes.
 int64_t cast_bytes(const Sizes& z, const EngineOptions& opt) {
   if (!opt.lowp_f32 && !opt.lowp_bf16) return 0;
-  return (opt.lowp_f32 ? 4 : 2) * 4 * z.n2 + 1024;
+  return (opt.lowp_f32 ? 4 : 2) * (4 * z.n2 + 32 * z.ov) + (1 << 20);
 }
 
 // Calls `f(count_doubles)` for every FP64 buffer in allocation order, and
@@ -168,8 +172,14 @@ void for_each_buffer(const Sizes& z, const EngineOptions& opt, F f, G g) {
   const int64_t p2 = z.p2, p2m = z.p2m, o2 = z.o2;
   f(p2 * p2); f(p2m * p2m); f(z.wna * v * v * v); g(4 * (2 * p2 + 2 * p2m));
   f(o * v * v * v); f(n2); f(n2); f(n2); f(n2); f(n2);
-  if (opt.lowp_f32) { g(4 * p2 * p2); g(4 * p2m * p2m); g(4 * o * v * v * v); g(4 * n2); g(4 * n2); g(4 * n2); g(4 * n2); }
-  if (opt.lowp_bf16) { g(2 * p2 * p2); g(2 * p2m * p2m); g(2 * o * v * v * v); g(2 * n2); g(2 * n2); g(2 * n2); g(2 * n2); }
+  if (opt.lowp_f32) {
+    g(4 * p2 * pad_to(p2, 4)); g(4 * p2m * pad_to(p2m, 4));
+    g(4 * o * v * v * v); g(4 * n2); g(4 * n2); g(4 * n2); g(4 * n2);
+  }
+  if (opt.lowp_bf16) {
+    g(2 * p2 * pad_to(p2, 8)); g(2 * p2m * pad_to(p2m, 8));
+    g(2 * o * v * v * v); g(2 * n2); g(2 * n2); g(2 * n2); g(2 * n2);
+  }
   g(cast_bytes(z, opt));
   // intermediates, value and tangent
   for (int rep = 0; rep < 2; ++rep) {
@@ -216,13 +226,19 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
   mpair_a_ = arena_.take<int>(z.p2m); mpair_b_ = arena_.take<int>(z.p2m);
   Wov.v = take(O * V * V * V);
   Ioovv.v = take(N2); Iovov.v = take(N2); Ix.v = take(N2); Ikldc.v = take(N2); Itil.v = take(N2);
+  // the low-precision ladder tensors keep rows of a 16-byte multiple (the
+  // pair counts v(v+1)/2, v(v-1)/2 need not be), for vector loads
+  ld32_ = pad_to(z.p2, 4); ld32m_ = pad_to(z.p2m, 4);
+  ld16_ = pad_to(z.p2, 8); ld16m_ = pad_to(z.p2m, 8);
   if (opt.lowp_f32) {
-    S.lp32 = arena_.take<float>(z.p2 * z.p2); Am.lp32 = arena_.take<float>(z.p2m * z.p2m); Wov.lp32 = arena_.take<float>(O * V * V * V);
+    S.lp32 = arena_.take<float>(z.p2 * ld32_); Am.lp32 = arena_.take<float>(z.p2m * ld32m_);
+    Wov.lp32 = arena_.take<float>(O * V * V * V);
     Ioovv.lp32 = arena_.take<float>(N2); Iovov.lp32 = arena_.take<float>(N2);
     Ix.lp32 = arena_.take<float>(N2); Ikldc.lp32 = arena_.take<float>(N2);
   }
   if (opt.lowp_bf16) {
-    S.lp16 = arena_.take<uint16_t>(z.p2 * z.p2); Am.lp16 = arena_.take<uint16_t>(z.p2m * z.p2m); Wov.lp16 = arena_.take<uint16_t>(O * V * V * V);
+    S.lp16 = arena_.take<uint16_t>(z.p2 * ld16_); Am.lp16 = arena_.take<uint16_t>(z.p2m * ld16m_);
+    Wov.lp16 = arena_.take<uint16_t>(O * V * V * V);
     Ioovv.lp16 = arena_.take<uint16_t>(N2); Iovov.lp16 = arena_.take<uint16_t>(N2);
     Ix.lp16 = arena_.take<uint16_t>(N2); Ikldc.lp16 = arena_.take<uint16_t>(N2);
   }
@@ -518,9 +534,14 @@ void Engine::prepare(const ProblemView& p, hipStream_t s) {
     permute4(Ioovv.v, Itil.v, dims2, pm2, -1.0, 0.0, s);
     axpby(n2_, 2.0, Ioovv.v, 1.0, Itil.v, s);
   }
-  Ten* lows[] = {&S, &Am, &Wov, &Ioovv, &Iovov, &Ix, &Ikldc};
-  const int64_t lsz[] = {p2_ * p2_, p2m_ * p2m_, (int64_t)o * v * vv, n2_, n2_, n2_, n2_};
-  for (int k = 0; k < 7; ++k) {
+  // the ladder tensors with padded rows, the others flat
+  if (S.lp32) cast_f64_to_f32_rows(p2_, p2_, ld32_, S.v, (float*)S.lp32, s);
+  if (S.lp16) cast_f64_to_bf16_rows(p2_, p2_, ld16_, S.v, (uint16_t*)S.lp16, s);
+  if (Am.lp32) cast_f64_to_f32_rows(p2m_, p2m_, ld32m_, Am.v, (float*)Am.lp32, s);
+  if (Am.lp16) cast_f64_to_bf16_rows(p2m_, p2m_, ld16m_, Am.v, (uint16_t*)Am.lp16, s);
+  Ten* lows[] = {&Wov, &Ioovv, &Iovov, &Ix, &Ikldc};
+  const int64_t lsz[] = {(int64_t)o * v * vv, n2_, n2_, n2_, n2_};
+  for (int k = 0; k < 5; ++k) {
     if (lows[k]->lp32) cast_f64_to_f32(lsz[k], lows[k]->v, (float*)lows[k]->lp32, s);
     if (lows[k]->lp16) cast_f64_to_bf16(lsz[k], lows[k]->v, (uint16_t*)lows[k]->lp16, s);
   }
@@ -588,9 +609,13 @@ void Engine::run(Mode m) {
     // the compute type stages best (n for FP64/FP32, k for BF16)
     const bool kc = mode_ == Mode::Tangent && jprec_ == Prec::BF16;
     const int P2 = (int)p2_, P2m = (int)p2m_, O2 = (int)o2_;
+    // row length of the copy the product reads (padded in FP32 / BF16)
+    const bool t32 = mode_ == Mode::Tangent && jprec_ == Prec::F32;
+    const int64_t ls = kc && S.lp16 ? ld16_ : (t32 && S.lp32 ? ld32_ : p2_);
+    const int64_t lm = kc && Am.lp16 ? ld16m_ : (t32 && Am.lp32 ? ld32m_ : p2m_);
     if (timers_) timers_->begin(kTimerPPL, s_);
-    mm(gd(O2, P2, P2, p2_, 1, kc ? 1 : p2_, kc ? p2_ : 1, p2_, 1), Tp, S, Rp);
-    if (P2m > 0) mm(gd(O2, P2m, P2m, p2m_, 1, kc ? 1 : p2m_, kc ? p2m_ : 1, p2m_, 1), Tm, Am, Rm);
+    mm(gd(O2, P2, P2, p2_, 1, kc ? 1 : ls, kc ? ls : 1, p2_, 1), Tp, S, Rp);
+    if (P2m > 0) mm(gd(O2, P2m, P2m, p2m_, 1, kc ? 1 : lm, kc ? lm : 1, p2m_, 1), Tm, Am, Rm);
     if (timers_) timers_->end(kTimerPPL, s_);
   }
   lin_ppl_unpack(Rp, Rm, R2);

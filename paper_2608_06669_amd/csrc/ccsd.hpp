@@ -164,6 +164,7 @@ class Engine {
   double* wblk_;
   int wblk_na_;
   int64_t p2_, p2m_, o2_;
+  int64_t ld32_ = 0, ld32m_ = 0, ld16_ = 0, ld16m_ = 0;  // row lengths of the low-precision ladder copies
   // amplitudes and outputs
   Ten T1, T2, R1, R2;
   // intermediates

@@ -520,11 +520,13 @@ bool gemm_precast(const GemmDesc& d, const void* A, const void* B, const void* A
   if (dual && pa != pb) return false;
   const int64_t es = compute == Prec::BF16 ? 2 : 4;
   const int kt = dual ? 2 * d.K : d.K;
-  const int64_t need = es * nb * ((pa ? (int64_t)d.M * kt : 0) + (pb ? (int64_t)d.N * kt : 0)) + 256;
+  // rows of the copies start on 16-byte boundaries (vector loads)
+  const int ld = (int)((kt + 16 / es - 1) / (16 / es) * (16 / es));
+  const int64_t need = es * nb * ((pa ? (int64_t)d.M * ld : 0) + (pb ? (int64_t)d.N * ld : 0)) + 256;
   if (need > d.cast_ws_bytes) return false;
   char* base = (char*)d.cast_ws;
   char* abuf = base;
-  char* bbuf = base + (((pa ? es * nb * (int64_t)d.M * kt : 0) + 255) & ~int64_t(255));
+  char* bbuf = base + (((pa ? es * nb * (int64_t)d.M * ld : 0) + 255) & ~int64_t(255));
   GemmDesc e = d;
   e.cast_ws = nullptr;
   const void *An = A, *Bn = B;
@@ -534,22 +536,22 @@ bool gemm_precast(const GemmDesc& d, const void* A, const void* B, const void* A
     const int rows = is_a ? d.M : d.N;
     const int64_t sr = is_a ? d.a_m : d.b_n, sk = is_a ? d.a_k : d.b_k;
     const int64_t sb0 = is_a ? d.a_b0 : d.b_b0, sb1 = is_a ? d.a_b1 : d.b_b1;
-    if (es == 2) pack<uint16_t>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, kt, koff, dst, s);
-    else pack<float>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, kt, koff, dst, s);
+    if (es == 2) pack<uint16_t>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, ld, koff, dst, s);
+    else pack<float>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, ld, koff, dst, s);
   };
   if (pa) {
     run_pack(A, true, 0, abuf);
     if (dual) run_pack(A2, true, d.K, abuf);
     An = abuf;
     apn = compute;
-    e.a_m = kt; e.a_k = 1; e.a_b0 = (int64_t)d.M * kt; e.a_b1 = (int64_t)d.nb0 * d.M * kt;
+    e.a_m = ld; e.a_k = 1; e.a_b0 = (int64_t)d.M * ld; e.a_b1 = (int64_t)d.nb0 * d.M * ld;
   }
   if (pb) {
     run_pack(B, false, 0, bbuf);
     if (dual) run_pack(B2, false, d.K, bbuf);
     Bn = bbuf;
     bpn = compute;
-    e.b_n = kt; e.b_k = 1; e.b_b0 = (int64_t)d.N * kt; e.b_b1 = (int64_t)d.nb0 * d.N * kt;
+    e.b_n = ld; e.b_k = 1; e.b_b0 = (int64_t)d.N * ld; e.b_b1 = (int64_t)d.nb0 * d.N * ld;
   }
   if (dual) {
     // both products packed along k: one product of depth 2K

@@ -957,7 +957,9 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   auto mask = [&](double* y) {
     if (opt.ccd) fill(ov, 0.0, y, s);
   };
-  auto Ainv = [&](const double* b, double* out) {
+  // tolerance of the inner solves of A_F^-1 J q inside the Krylov loop
+  const double krylov_rtol = opt.inner_rtol_jv > 0.0 ? opt.inner_rtol_jv : opt.inner_rtol;
+  auto Ainv = [&](const double* b, double* out, double rtol) {
     if (opt.protocol == PnkOptions::kNK) {
       // no preconditioner: the identity on pair-symmetric vectors, applied
       // as the projection (b2 + b2^T over pairs) / 2 so that rounding-level
@@ -967,7 +969,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
       pair_symmetrize_add(o, vir, b + ov, 0.5, out + ov, s);
     } else {
       bool conv = true;
-      const int it = g_precond(b, out, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv);
+      const int it = g_precond(b, out, rtol, opt.inner_maxit, opt.inner_restart, s, &conv);
       st->n_afmv += it;
       st->n_inner_iters += it;
     }
@@ -1018,7 +1020,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     if (opt.protocol == PnkOptions::kINK) {
       // A_F dt = -r(t): one inner solve per step, no Jacobian products
       if (rn > 1e6) break;  // diverging, as FP ends it
-      Ainv(r_, w_);
+      Ainv(r_, w_, opt.inner_rtol);
       axpby(n, -1.0, w_, 1.0, x, s);
       rn_prev = rn;
       ++k;
@@ -1026,7 +1028,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     }
     eta = forcing(k, rn, rn_prev, eta, opt.tol_inf, opt);
     // z = A_F^{-1} r, q_1 = z / beta
-    Ainv(r_, w_);
+    Ainv(r_, w_, opt.inner_rtol);
     double zinf, beta;
     norms(w_, &zinf, &beta, s);
     if (!(beta > 0.0) || !std::isfinite(beta)) { st->diverged = !std::isfinite(beta); break; }
@@ -1056,7 +1058,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
         st->n_jvp++;
         mask(g.w2);
         bool conv = true;
-        const int it = precond_solve(g.w2, g.w1, opt.inner_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
+        const int it = precond_solve(g.w2, g.w1, krylov_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
         st->n_afmv += it;
         st->n_inner_iters += it;
         mask(g.w1);
@@ -1078,7 +1080,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
         }
         st->n_jvp++;
         mask(w_);
-        Ainv(w_, wv);
+        Ainv(w_, wv, krylov_rtol);
       }
       const double hn = orthogonalise(Qo_, n, m + 1, wv, h, s);
       for (int i = 0; i <= m; ++i) H[i + (size_t)m * (M + 1)] = h[i];

@@ -32,6 +32,9 @@ struct PnkOptions {
   // last step where it did
   int stall_window = 0;
   double stall_factor = 0.5;
+  // tolerance of the inner solves applied to J q inside the Krylov loop
+  // (0: inner_rtol); the solve of the Newton right-hand side keeps inner_rtol
+  double inner_rtol_jv = 0.0;
 };
 
 struct FpOptions {

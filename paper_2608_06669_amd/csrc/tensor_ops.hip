@@ -116,6 +116,18 @@ __global__ void cast_bf16_kernel(int64_t n, const double* __restrict__ x, uint16
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = f32_to_bf16_rne((float)x[i]);
 }
+// rows x cols row-major (row length cols) to rows of length ld >= cols; the
+// ld - cols padding elements of each row are zero
+template <typename T>
+__global__ void cast_rows_kernel(int64_t rows, int64_t cols, int64_t ld, const double* __restrict__ x, T* __restrict__ y) {
+  const int64_t n = rows * ld;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / ld, c = i - r * ld;
+    const double v = c < cols ? x[r * cols + c] : 0.0;
+    if constexpr (sizeof(T) == 2) y[i] = f32_to_bf16_rne((float)v);
+    else y[i] = (float)v;
+  }
+}
 
 // R[i][j][a][b] += alpha * (X[i][j][a][b] + X[j][i][b][a]); one (i,j) pair and
 // one 32 x 32 (a,b) tile per block
@@ -365,6 +377,16 @@ void cast_f64_to_f32(int64_t n, const double* x, float* y, hipStream_t s) {
 void cast_f64_to_bf16(int64_t n, const double* x, uint16_t* y, hipStream_t s) {
   if (n <= 0) return;
   cast_bf16_kernel<<<grid_for(n, 16384), 256, 0, s>>>(n, x, y);
+  PNK_CHECK_LAUNCH();
+}
+void cast_f64_to_f32_rows(int64_t rows, int64_t cols, int64_t ld, const double* x, float* y, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  cast_rows_kernel<float><<<grid_for(rows * ld, 16384), 256, 0, s>>>(rows, cols, ld, x, y);
+  PNK_CHECK_LAUNCH();
+}
+void cast_f64_to_bf16_rows(int64_t rows, int64_t cols, int64_t ld, const double* x, uint16_t* y, hipStream_t s) {
+  if (rows <= 0 || cols <= 0) return;
+  cast_rows_kernel<uint16_t><<<grid_for(rows * ld, 16384), 256, 0, s>>>(rows, cols, ld, x, y);
   PNK_CHECK_LAUNCH();
 }
 

@@ -20,6 +20,10 @@ void copy(int64_t n, const double* x, double* y, hipStream_t s);
 // y[i] = (float or bf16 bits) x[i]
 void cast_f64_to_f32(int64_t n, const double* x, float* y, hipStream_t s);
 void cast_f64_to_bf16(int64_t n, const double* x, uint16_t* y, hipStream_t s);
+// x [rows][cols] to y [rows][ld] (ld >= cols, padding zeroed), so that rows
+// start on 16-byte boundaries for the matrix-core products' vector loads
+void cast_f64_to_f32_rows(int64_t rows, int64_t cols, int64_t ld, const double* x, float* y, hipStream_t s);
+void cast_f64_to_bf16_rows(int64_t rows, int64_t cols, int64_t ld, const double* x, uint16_t* y, hipStream_t s);
 
 // R[i][j][a][b] += alpha * (X[i][j][a][b] + X[j][i][b][a])
 void pair_symmetrize_add(int o, int v, const double* X, double alpha, double* R, hipStream_t s);

@@ -328,6 +328,28 @@ def test_near_degenerate_small_pnk_matches_the_oracle(handle, lib, histories):
     assert np.allclose(gh[:10], oh[:10], rtol=1e-6, atol=0.0)
 
 
+def test_near_degenerate_o6_stalls_like_the_oracle(handle, lib, histories):
+    """The near-degenerate recipe at o=6, v=54 (the recipe of the o=16/v=144
+    workload, scaled down): the oracle's PNK stalls near max |R| = 3e-2 and
+    is still there after 20 Newton steps; the device stalls the same way,
+    through the same residual norms at every step (1e-3 relative). The
+    stall of the o=16/v=144 workload is the method's behaviour on this
+    Hamiltonian, not the device's."""
+    h = histories["neardeg_o6_v54"]
+    p = make_near_degenerate(6, 54, 180, 1003, sigma=0.08)
+    P = lib.DeviceProblem.from_problem(p)
+    _, _, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=20)
+    gh = handle.history()
+    oh = np.array([[r2, ri] for _, r2, ri in h["history"]])
+    print("device ||r||_inf:", " ".join(f"{x:.3e}" for x in gh[:, 1]))
+    print("oracle ||r||_inf:", " ".join(f"{x:.3e}" for x in oh[:, 1]))
+    assert info["status"] == "CC_NOT_CONVERGED" and not h["converged"]
+    assert info["newton_iters"] == h["newton_iters"] == 20
+    assert len(gh) == len(oh)
+    assert np.allclose(gh, oh, rtol=1e-3, atol=0.0)
+    assert oh[-1, 1] > 1e-2  # a stall, not a slow convergence
+
+
 def test_fp_diis_c2_diverges_like_the_oracle(handle, lib, histories):
     """FP+DIIS(8) on the Haar-rotated o=10/v=90 workload from the MP2 start:
     the oracle diverges (||r||_2 above 1e6) and so does the device, at the
