@@ -398,7 +398,11 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   // CU): for the o v x o v products of the rotated 10/90 workload that is 4
   // chunks, 10 % faster than 3 (a sweep over 3..12); thin products with a
   // long contraction stay near 512 (8 chunks for the ladder, its best).
-  if (d.ws && tiles < 256 && d.K >= 256) {
+  // Long contractions with fewer than 512 tiles (one or two workgroups per
+  // CU, each walking thousands of k steps) are split too: the T1 part of
+  // the ladder at o=20/v=180 (400 x 3600 x 32400, 399 tiles) ran at 22
+  // TFLOP/s unsplit.
+  if (d.ws && d.K >= 256 && (tiles < 256 || (tiles < 512 && d.K >= 8192))) {
     const bool thin = d.M <= 64 && d.K >= 1024;
     int64_t want = ceil_div(thin ? 512 : 900, tiles);
     want = std::min<int64_t>(want, d.K / (2 * BK));

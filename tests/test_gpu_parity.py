@@ -48,10 +48,12 @@ def _args(p):
 
 # ------------------------------------------------------------ GEMM -----
 # shapes cover the matrix-core tiles with ragged edges, one-row / one-column
-# products and the short-contraction kernel (K <= 32 with a side <= 32, long
-# side along N or along M)
+# products, the short-contraction kernel (K <= 32 with a side <= 32, long
+# side along N or along M) and tall ragged products as wide and long as the
+# ladder at o=20 (210 and 129 rows)
 @pytest.mark.parametrize("M,N,K", [(16, 16, 4), (33, 70, 19), (130, 257, 100), (400, 129, 300), (7, 1, 300),
-                                   (5, 3000, 20), (3000, 7, 11), (32, 33, 32), (1, 1, 1)])
+                                   (5, 3000, 20), (3000, 7, 11), (32, 33, 32), (1, 1, 1),
+                                   (210, 2100, 2100), (129, 2048, 2053)])
 @pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True), (True, True)])
 def test_gemm_fp64_matches_float64_reference(lib, M, N, K, ta, tb):
     g = torch.Generator(device="cpu").manual_seed(M * 1000 + N + K)

@@ -170,3 +170,40 @@ def test_server_rejects_a_request_larger_than_the_budget(lib):
         assert st["rejected"] == 1 and st["queued"] == 0 and st["finished"] == 0
     finally:
         srv.close()
+
+
+def test_serving_c5_sized_requests_match_solo_solves_and_fp64(lib):
+    """Requests of the serving stream's larger shapes (o = 8..12, v = 5..9
+    times o, naux = 3(o + v), canonical and rotated gauges), FP64 and
+    mixed precision (BF16 J v with the Krylov-loop inner solves to 1e-6, as
+    the stream runs them), three in flight: every result is bit for bit the
+    same request solved alone on a handle, and each mixed-precision energy
+    is within 1e-6 Eh of the FP64 one."""
+    shapes = [(8, 40, "haar"), (10, 70, "canonical"), (12, 60, "haar"), (9, 54, "canonical")]
+    probs = [make_problem(o, v, 3 * (o + v), 7300 + k, gauge=g) for k, (o, v, g) in enumerate(shapes)]
+    kinds = [dict(jvp_prec="fp64"), dict(jvp_prec="bf16", inner_rtol_jv=1e-6)]
+    h = lib.Handle(0)
+    solo = {}
+    for k, p in enumerate(probs):
+        for j, kw in enumerate(kinds):
+            t1, t2, info = h.solve_pnk(lib.DeviceProblem.from_problem(p), tol_inf=1e-8, max_newton=200, **kw)
+            assert info["status"] == "CC_OK", (k, kw, info)
+            solo[(k, j)] = (t1.cpu().numpy(), t2.cpu().numpy(), info)
+    h.close()
+    srv = lib.Server(0, max_slots=3)
+    try:
+        ids = {(k, j): srv.submit(p, tol_inf=1e-8, max_newton=200, **kw)
+               for k, p in enumerate(probs) for j, kw in enumerate(kinds)}
+        srv.drain()
+        res = {key: srv.poll(rid) for key, rid in ids.items()}
+        stats = srv.stats()
+    finally:
+        srv.close()
+    assert stats["peak_running"] >= 2
+    for key, r in res.items():
+        s1, s2, sinfo = solo[key]
+        assert r["status"] == "CC_OK", key
+        assert r["e_corr"] == sinfo["e_corr"], key
+        assert np.array_equal(r["t1"], s1) and np.array_equal(r["t2"], s2), key
+    for k in range(len(probs)):
+        assert abs(res[(k, 1)]["e_corr"] - res[(k, 0)]["e_corr"]) <= 1e-6, k
