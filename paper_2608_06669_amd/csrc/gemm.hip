@@ -22,10 +22,10 @@
 //   bf16 16x16x32: A[i][k..k+7] at i = l%16, k = 8*(l/16); B likewise;
 //        D as f32
 //
-// Workgroup order: tiles of one output column block (same B panel) are
-// consecutive and are placed on the same XCD (hardware dispatches block ids
-// round-robin over the 8 XCDs), so the B panel is fetched from HBM once and
-// re-read by its neighbours from that XCD's L2.
+// Workgroup order: each XCD takes a contiguous range of tiles (hardware
+// dispatches block ids round-robin over the 8 XCDs), ordered in groups of 8
+// row tiles with the row tile fastest, so the workgroups resident on one
+// XCD share their A and B panels in that XCD's L2.
 //
 // Products with too few output tiles to fill the GPU split the contraction
 // (split-K); partial sums are added afterwards in a fixed order, so results
@@ -82,8 +82,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   const int ntiles = p.tiles_m * p.tiles_n;
   int bid = blockIdx.x;
   if ((ntiles & 7) == 0) bid = (bid & 7) * (ntiles >> 3) + (bid >> 3);
-  const int tm = bid % p.tiles_m;
-  const int tn = bid / p.tiles_m;
+  // tiles in groups of (up to) 8 row tiles: within a group the row tile
+  // runs fastest, so the workgroups resident on one XCD share both their A
+  // and their B panels in L2 (with the row tile fastest over all rows, each
+  // XCD streamed every A panel once per column block)
+  constexpr int kGroupM = 8;
+  const int gsize = kGroupM * p.tiles_n;
+  const int grp = bid / gsize;
+  const int first_m = grp * kGroupM;
+  const int gm = min(p.tiles_m - first_m, kGroupM);
+  const int rem = bid - grp * gsize;
+  const int tm = first_m + rem % gm;
+  const int tn = rem / gm;
   const int m0 = tm * BM;
   const int n0 = tn * BN;
 
