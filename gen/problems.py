@@ -196,6 +196,28 @@ def nonorthogonal_gauge(nocc: int, nvir: int, seed: int, cond: float = 4.0):
     return out[0], out[1]
 
 
+def redundant_gauge(nocc: int, nvir: int, m_occ: int, m_vir: int, seed: int, cond: float = 4.0):
+    """Redundant gauge matrices W_o [o][m_occ] and W_v [v][m_vir] (m >= the
+    block size): m gauge functions spanning each block, as projected atomic
+    orbitals span the virtual space. W = Q1 [diag(s) 0] Q2 with Haar Q1
+    (n x n) and Q2 (m x m) and nonzero singular values s = cond^u, u uniform
+    on [-1/2, 1/2] with both ends drawn: full row rank, the nonzero part with
+    condition number `cond`; the overlap S = W^T W has rank n."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for n, m in ((nocc, m_occ), (nvir, m_vir)):
+        if m < n:
+            raise ValueError("a gauge needs at least as many functions as the block has orbitals")
+        u = rng.uniform(-0.5, 0.5, n)
+        if n >= 2:
+            u[0], u[1] = -0.5, 0.5
+        s = cond ** u
+        q1 = haar_orthogonal(rng, n)
+        q2 = haar_orthogonal(rng, m)
+        out.append(np.ascontiguousarray((q1 * s[None, :]) @ q2[:n, :]))
+    return out[0], out[1]
+
+
 def random_amplitudes(nocc: int, nvir: int, seed: int, scale: float = 0.05):
     """Random t1 [o][v] and pair-symmetric t2 [o][o][v][v] (t_ij^ab = t_ji^ba)."""
     rng = np.random.default_rng(seed)

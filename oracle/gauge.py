@@ -10,23 +10,31 @@ residual with its FP update).
 
 The gauge. Within each orbital block, gauge functions that span the same
 space as the orthonormal orbitals phi but need not be orthonormal:
-chi_occ = phi_occ W_o and chi_vir = phi_vir W_v, with W_o (o x o) and W_v
-(v x v) invertible. They overlap as S = W^T W. In the appendix's notation
-the gauge functions are the basis, the orbital coefficients in it are
-C = W^{-1} (so C^T S C = 1), the gauge map is U = C and U-bar = S U = W^T.
+chi_occ = phi_occ W_o and chi_vir = phi_vir W_v, with W_o (o x m_o) and W_v
+(v x m_v) of full row rank. They overlap as S = W^T W. With m = o (v) and W
+invertible the gauge is non-redundant; with m > o (v) it is redundant (more
+functions than the space they span, as projected atomic orbitals are) and S
+is singular. In the appendix's notation the gauge functions are the basis,
+the orbital coefficients in it are C = W^+ = W^T (W W^T)^{-1} (so W C = 1 and
+C^T S C = 1; W^+ = W^{-1} when W is square), the gauge map is U = C and
+U-bar = S U = W^T, and the appendix's projector onto the gauge space is
+Pi = U-bar C^T = W^T (W W^T)^{-1} W per block: the orthogonal projector, in
+gauge-index space, onto the range of U-bar. For a redundant gauge only that
+range holds amplitudes: theta and r(theta) lie in it, components outside it
+do not change t(theta), and the Jacobian of r(theta) is singular there.
 
 * Amplitudes: theta = U-bar^(x4) t, i.e.
   theta[mu, nu, lam, sig] = sum W[i, mu] W[j, nu] W[a, lam] W[b, sig] t[i, j, a, b]
   (covariant components); singles theta1 = W_o^T t1 W_v.
 * Residual: the first line of the random-gauge residual equation,
   r(theta) = U-bar^(x4) r(t) with t the back-transform of theta
-  (t = C^(x4) theta, C = W^{-1}). `residual` is that definition.
+  (t = C^(x4) theta, C = W^+). `residual` is that definition.
   `residual_ccd_explicit` writes the same CCD residual out in the gauge
   quantities of the appendix (Y + A theta + theta B + theta pi theta + the
   symmetrised Fock, J and K terms), so the two pin each other.
 * Fock blocks: the one-body part of the residual acts on a virtual index
-  of theta through Fv = W_v^T f_vv W_v^{-T} and on an occupied index
-  through Fo = W_o^T f_oo W_o^{-T}. Reading: the appendix's f-bar is the
+  of theta through Fv = W_v^T f_vv C_v^T and on an occupied index
+  through Fo = W_o^T f_oo C_o^T (m x m; W^T f W^{-T} for a square gauge). Reading: the appendix's f-bar is the
   Fock matrix in the gauge basis, <chi|f|chi> = W^T f W, which the
   projector products Q-bar f-bar Q and P-bar f-bar P turn into these
   similarity transforms. (The printed f-bar = U f U^T with U = C agrees
@@ -64,10 +72,24 @@ def forward(Wo, Wv, x1, x2):
     return y1, y2
 
 
+def coefficients(W):
+    """C = W^+ = W^T (W W^T)^{-1} (m x n): the orbital coefficients of a
+    block in its gauge functions; W^{-1} when W is square and invertible."""
+    return W.T @ np.linalg.inv(W @ W.T)
+
+
+def projector(W):
+    """Pi = W^T (W W^T)^{-1} W (m x m): projector onto the range of
+    U-bar = W^T, the gauge-index space amplitudes live in (the identity for
+    a non-redundant gauge)."""
+    return W.T @ np.linalg.inv(W @ W.T) @ W
+
+
 def backward(Wo, Wv, y1, y2):
-    """The inverse of `forward`: x = C^(x4) y with C = W^{-1}."""
-    Co = np.linalg.inv(Wo)
-    Cv = np.linalg.inv(Wv)
+    """x = C^(x4) y with C = W^+: the orbital amplitudes of gauge
+    amplitudes y (the inverse of `forward` on its range)."""
+    Co = coefficients(Wo)
+    Cv = coefficients(Wv)
     x1 = _es("Mi,La,ML->ia", Co, Cv, y1)
     x2 = _es("Mi,Nj,La,Sb,MNLS->ijab", Co, Co, Cv, Cv, y2)
     return x1, x2
@@ -75,9 +97,9 @@ def backward(Wo, Wv, y1, y2):
 
 def fock_blocks(f_oo, f_vv, Wo, Wv):
     """(Fo, Fv): the gauge's occupied and virtual Fock blocks,
-    W^T f W^{-T} per block."""
-    Fo = Wo.T @ f_oo @ np.linalg.inv(Wo).T
-    Fv = Wv.T @ f_vv @ np.linalg.inv(Wv).T
+    W^T f C^T per block (m x m; W^T f W^{-T} when W is square)."""
+    Fo = Wo.T @ f_oo @ coefficients(Wo).T
+    Fv = Wv.T @ f_vv @ coefficients(Wv).T
     return Fo, Fv
 
 
@@ -119,10 +141,11 @@ def fock_apply(f_ov, Wo, Wv, Fo, Fv, x1, x2):
 def residual_ccd_explicit(f_oo, f_vv, L, Wo, Wv, th2):
     """The random-gauge CCD residual (t1 = 0) written out in the appendix's
     gauge quantities; doubles only. Covariant gauge indices come from
-    W^T (U-bar), contravariant ones from C = W^{-1}."""
+    W^T (U-bar), contravariant ones from C = W^+."""
     o = f_oo.shape[0]
-    Co = np.linalg.inv(Wo)
-    Cv = np.linalg.inv(Wv)
+    # contravariant gauge indices: C = W^+, [gauge][orbital]
+    Co = coefficients(Wo)
+    Cv = coefficients(Wv)
     Loo, Lov, Lvv = L[:, :o, :o], L[:, :o, o:], L[:, o:, o:]
     Lvo = L[:, o:, :o]
     ovov = _es("Pia,Pjb->iajb", Lov, Lov)
@@ -165,6 +188,9 @@ class GaugeProblem(_Problem):
         super().__init__(f_oo, f_ov, f_vv, L, ccd)
         self.Wo, self.Wv = Wo, Wv
         self.Fo, self.Fv = fock_blocks(f_oo, f_vv, Wo, Wv)
+        # vectors are gauge vectors: m_o gauge functions for the occupied
+        # block, m_v for the virtual one
+        self.o, self.v = Wo.shape[1], Wv.shape[1]
 
     def residual(self, x):
         th1, th2 = unpack(x, self.o, self.v)

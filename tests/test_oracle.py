@@ -527,3 +527,137 @@ def test_gauge_ink_is_the_orbital_ink_transformed():
         c1, c2 = gauge.forward(Wo, Wv, b1, b2)
         assert ia.newton_iters == ib.newton_iters == 3
         assert np.abs(a2 - c2).max() < 1e-10 and np.abs(a1 - c1).max() < 1e-10
+
+
+# ------------------------------------------------------ redundant gauge ----
+# Gauges with more functions than the block has orbitals (W_o: o x m_o,
+# W_v: v x m_v, full row rank; the appendix's projectors for a rectangular
+# U), as projected atomic orbitals are for the virtual space.
+def _redundant(seed=1201, o=2, v=4, m_o=3, m_v=6, naux=12, cond=3.0, kind="haar"):
+    from gen import redundant_gauge
+    p = make_general(o, v, naux, seed) if kind == "general" else make_problem(o, v, naux, seed, gauge=kind)
+    Wo, Wv = redundant_gauge(o, v, m_o, m_v, seed + 7, cond)
+    return p, Wo, Wv
+
+
+def test_redundant_gauge_coefficients_and_projector():
+    """C = W^+ satisfies W C = 1; Pi = W^T (W W^T)^-1 W is the orthogonal
+    projector of rank n onto the range of U-bar = W^T, and gauge amplitudes
+    of orbital amplitudes lie in that range on every index; for a square W,
+    C is W^-1 and Pi the identity."""
+    from gen import nonorthogonal_gauge
+    from oracle import gauge
+    p, Wo, Wv = _redundant()
+    for W, n in ((Wo, 2), (Wv, 4)):
+        C = gauge.coefficients(W)
+        Pi = gauge.projector(W)
+        assert np.abs(W @ C - np.eye(n)).max() < 1e-13
+        assert np.abs(Pi @ Pi - Pi).max() < 1e-13 and np.abs(Pi - Pi.T).max() < 1e-13
+        assert np.linalg.matrix_rank(Pi, tol=1e-10) == n
+    t1, t2 = random_amplitudes(2, 4, 41)
+    th1, th2 = gauge.forward(Wo, Wv, t1, t2)
+    Po, Pv = gauge.projector(Wo), gauge.projector(Wv)
+    assert np.abs(np.einsum("MA,NB,LC,SD,ABCD->MNLS", Po, Po, Pv, Pv, th2) - th2).max() < 1e-13
+    b1, b2 = gauge.backward(Wo, Wv, th1, th2)
+    assert np.abs(b1 - t1).max() < 1e-13 and np.abs(b2 - t2).max() < 1e-13
+    Wq, _ = nonorthogonal_gauge(3, 5, 7, 4.0)
+    assert np.abs(gauge.coefficients(Wq) - np.linalg.inv(Wq)).max() < 1e-12
+
+
+@pytest.mark.parametrize("in_range", [True, False])
+def test_redundant_gauge_residual_equals_the_appendix_equations(in_range):
+    """The definition r(theta) = U-bar^(x4) r(C^(x4) theta) equals the
+    random-gauge CCD equations written out in the appendix's transformed
+    quantities, for a redundant gauge. Those equations carry theta's free
+    (covariant) indices through unchanged, so they presume theta in the range
+    of U-bar^(x4); the definition sees only the projection Pi^(x4) theta, and
+    for theta with components outside the range it equals the explicit
+    equations at that projection."""
+    from oracle import gauge
+    p, Wo, Wv = _redundant(cond=5.0)
+    _, t2 = random_amplitudes(2, 4, 42, scale=0.1)
+    _, th2 = gauge.forward(Wo, Wv, np.zeros((2, 4)), t2)
+    proj = th2
+    if not in_range:
+        rng = np.random.default_rng(43)
+        extra = rng.standard_normal(th2.shape)
+        th2 = th2 + 0.05 * (extra + np.transpose(extra, (1, 0, 3, 2)))
+        Po, Pv = gauge.projector(Wo), gauge.projector(Wv)
+        proj = np.einsum("MA,NB,LC,SD,ABCD->MNLS", Po, Po, Pv, Pv, th2)
+        assert np.abs(proj - th2).max() > 1e-3
+    _, r2 = gauge.residual(*_args(p), Wo, Wv, np.zeros((3, 6)), th2)
+    x2 = gauge.residual_ccd_explicit(p.f_oo, p.f_vv, p.L, Wo, Wv, proj)
+    assert np.abs(r2 - x2).max() < 1e-12 * max(1.0, np.abs(r2).max())
+
+
+def test_redundant_gauge_jacobian_has_the_orbital_spectrum_and_a_null_space():
+    """J_theta = U-bar^(x4) J C^(x4) with C^(x4) U-bar^(x4) = 1: its nonzero
+    eigenvalues are those of the orbital-basis Jacobian J, and the rest of the
+    gauge space (dimension m_o m_v + m_o^2 m_v^2 - (o v + o^2 v^2)) is null.
+    Dense matrices from complex-step products on unit vectors (o=1, v=2,
+    m_o=2, m_v=3)."""
+    from gen import redundant_gauge
+    from oracle import gauge
+    p = make_general(1, 2, 5, 1202)
+    Wo, Wv = redundant_gauge(1, 2, 2, 3, 1203, 3.0)
+    t1, t2 = random_amplitudes(1, 2, 44, scale=0.1)
+    th1, th2 = gauge.forward(Wo, Wv, t1, t2)
+
+    def dense(fn, n, shape1, shape2):
+        cols = []
+        for k in range(n):
+            e = np.zeros(n)
+            e[k] = 1.0
+            e1 = e[: np.prod(shape1)].reshape(shape1)
+            e2 = e[np.prod(shape1):].reshape(shape2)
+            j1, j2 = fn(e1, e2)
+            cols.append(np.concatenate([j1.ravel(), j2.ravel()]))
+        return np.array(cols).T
+
+    ng = 2 * 3 + 4 * 9
+    Jg = dense(lambda a, b: gauge.jvp_complex_step(*_args(p), Wo, Wv, th1, th2, a, b), ng, (2, 3), (2, 2, 3, 3))
+    Jo = dense(lambda a, b: ccsd.jvp_complex_step(*_args(p), t1, t2, a, b), 2 + 4, (1, 2), (1, 1, 2, 2))
+    eg = np.linalg.eigvals(Jg)
+    eo = np.linalg.eigvals(Jo)
+    scale = np.abs(eo).max()
+    nonzero = eg[np.abs(eg) > 1e-9 * scale]
+    assert len(nonzero) == len(eo) and np.linalg.matrix_rank(Jg, tol=1e-9 * scale) == 6
+    assert np.allclose(np.sort_complex(nonzero), np.sort_complex(eo), rtol=1e-8, atol=1e-10 * scale)
+
+
+def test_redundant_gauge_gmres_inverts_the_singular_fock_operator_on_its_range():
+    """A_F of a redundant gauge is singular (its null space is that of
+    C^(x4)); GMRES from zero on a right-hand side in its range converges to
+    the one solution in the range, U-bar^(x4) A_F^-1 C^(x4) b."""
+    from oracle import gauge
+    p, Wo, Wv = _redundant(o=3, v=5, m_o=4, m_v=8, naux=16)
+    Fo, Fv = gauge.fock_blocks(p.f_oo, p.f_vv, Wo, Wv)
+    t1, t2 = random_amplitudes(3, 5, 45, scale=1.0)
+    b1, b2 = gauge.forward(Wo, Wv, t1, t2)
+    res = solvers.gmres(lambda y: solvers.pack(*gauge.fock_apply(p.f_ov, Wo, Wv, Fo, Fv, *solvers.unpack(y, 4, 8))),
+                        solvers.pack(b1, b2), rtol=1e-12, maxit=400)
+    assert res.converged
+    e1, e2 = solvers.fock_solve_exact(p.f_oo, p.f_ov, p.f_vv, *gauge.backward(Wo, Wv, b1, b2))
+    x1, x2 = gauge.forward(Wo, Wv, e1, e2)
+    g1, g2 = solvers.unpack(res.x, 4, 8)
+    assert np.abs(g2 - x2).max() < 1e-10 * np.abs(x2).max() and np.abs(g1 - x1).max() < 1e-10 * np.abs(x1).max()
+
+
+def test_redundant_gauge_pnk_lands_on_the_transformed_root():
+    """PNK on the amplitudes of a redundant gauge (the Newton systems are
+    singular but consistent; GMRES's Krylov spaces stay in the range)
+    converges to U-bar^(x4) t* with the orbital-basis energy, its iterate in
+    the range of U-bar^(x4)."""
+    from gen import redundant_gauge
+    from oracle import gauge
+    p = make_problem(3, 8, 22, 1204, gauge="haar")
+    Wo, Wv = redundant_gauge(3, 8, 4, 11, 1205, 4.0)
+    a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-11, gauge=(Wo, Wv))
+    b1, b2, ib = solvers.solve_pnk(*_args(p), tol=1e-11)
+    c1, c2 = gauge.forward(Wo, Wv, b1, b2)
+    assert ia.converged and ib.converged
+    assert a2.shape == (4, 4, 11, 11)
+    assert np.abs(a1 - c1).max() < 1e-9 and np.abs(a2 - c2).max() < 1e-9
+    assert abs(ia.e_corr - ib.e_corr) < 1e-10
+    Po, Pv = gauge.projector(Wo), gauge.projector(Wv)
+    assert np.abs(np.einsum("MA,NB,LC,SD,ABCD->MNLS", Po, Po, Pv, Pv, a2) - a2).max() < 1e-10
