@@ -254,34 +254,52 @@ cc_status cc_fp_spectral_radius(cc_handle* h, const cc_problem* p, const double*
                                 double* ritz_im, int* n_ritz, void* stream);
 
 /* ---------------------------------------------------------------------
- * Non-orthogonal orbital gauges (Appendix A, random gauge representation).
+ * Non-orthogonal and redundant orbital gauges (Appendix A, random gauge
+ * representation).
  *
- * Per orbital block the gauge functions are chi = phi W with W invertible
- * but not necessarily orthogonal: w_oo [nocc][nocc] and w_vv [nvir][nvir]
- * (DEVICE, FP64, row-major, caller-owned), column mu holding gauge function
- * mu expanded in the orthonormal orbitals of the problem (the orbitals f and
- * L are given in). The gauge functions overlap as S = W^T W. The gauge
- * amplitudes are the covariant components (the appendix's theta = U-bar^(x4)
- * t with U-bar = S U = W^T):
+ * Per orbital block, m gauge functions chi = phi W that span the block's
+ * orbitals but need be neither orthonormal nor independent: w_oo
+ * [nocc][m_occ] and w_vv [nvir][m_vir] (DEVICE, FP64, row-major,
+ * caller-owned, full row rank, m >= the block size; m_occ = 0 or m_vir = 0
+ * means the square case m = nocc or nvir), column mu holding gauge function
+ * mu expanded in the orthonormal orbitals of the problem (the orbitals f
+ * and L are given in). The gauge functions overlap as S = W^T W, singular
+ * when m exceeds the block size (a redundant gauge, as projected atomic
+ * orbitals are). The orbital coefficients in them are C = W^+ =
+ * W^T (W W^T)^-1 (W^-1 for square W). The gauge amplitudes are the
+ * covariant components (the appendix's theta = U-bar^(x4) t with
+ * U-bar = S U = W^T), of shapes th1 [m_occ][m_vir] and th2
+ * [m_occ][m_occ][m_vir][m_vir]:
  *   th1[mu][lam]          = sum_ia W_o[i][mu] W_v[a][lam] t1[i][a]
  *   th2[mu][nu][lam][sig] = sum W_o[i][mu] W_o[j][nu] W_v[a][lam] W_v[b][sig] t2[i][j][a][b]
- * and the gauge residual is r(theta) = U-bar^(x4) r(t(theta)). The gauge's
- * Fock blocks W^T f W^-T make its A_F non-symmetric; its inverse is applied
- * as U-bar^(x4) A_F^-1 (W^-T)^(x4) with the orbital-basis inner solve. The
- * FP denominators are the diagonals of those blocks (the appendix's FP
- * update). Each call copies W to the host and inverts it (Gauss-Jordan,
- * partial pivoting): CC_ERR_ARG for a singular or non-finite W. The handle
- * keeps 3 N + 2 o^2 v^2 doubles of gauge buffers (N = o v + o^2 v^2) once
- * a gauge call has run. All calls synchronise.
+ * and the gauge residual is r(theta) = U-bar^(x4) r(t(theta)) with
+ * t(theta) = C^(x4) theta. Amplitudes and residuals lie in the range of
+ * U-bar^(x4); for a redundant gauge the components of theta outside it
+ * change neither t(theta) nor r(theta), the Jacobian is singular there and
+ * the solves below return amplitudes in the range. The gauge's Fock blocks
+ * W^T f C^T make its A_F non-symmetric; its inverse on the range is
+ * applied as U-bar^(x4) A_F^-1 C^(x4) with the orbital-basis inner solve.
+ * The FP denominators are the diagonals of those blocks (the appendix's FP
+ * update). Each call copies W to the host and inverts W (square) or W W^T
+ * (Gauss-Jordan, partial pivoting): CC_ERR_ARG for a W that is not finite
+ * or not of full row rank, or m below the block size. The handle keeps
+ * 3 N + N_g + 2 (m_occ m_vir)^2 doubles of gauge buffers (N = o v +
+ * o^2 v^2, N_g = m_occ m_vir + (m_occ m_vir)^2) once a gauge call has run,
+ * and a gauge solve sizes its outer Krylov and DIIS vectors for N_g. All
+ * calls synchronise.
  * --------------------------------------------------------------------- */
 typedef struct {
   const double* w_oo;
   const double* w_vv;
+  int m_occ; /* gauge functions of the occupied block (0: nocc) */
+  int m_vir; /* gauge functions of the virtual block (0: nvir) */
 } cc_gauge;
 
-/* y = U-bar^(x4) x (to_gauge != 0: orbital amplitudes or residuals to the
- * gauge's) or its inverse (to_gauge == 0), for (x1 [o][v], x2 [o][o][v][v])
- * (device); y must not overlap x. */
+/* y = U-bar^(x4) x (to_gauge != 0: orbital amplitudes or residuals
+ * (x1 [o][v], x2 [o][o][v][v]) to the gauge's (y1 [m_occ][m_vir], y2
+ * [m_occ][m_occ][m_vir][m_vir])) or y = C^(x4) x (to_gauge == 0: gauge
+ * components to orbital ones, the inverse of the first on its range), all
+ * device; y must not overlap x. */
 cc_status cc_gauge_transform(cc_handle* h, const cc_problem* p, const cc_gauge* g, int to_gauge, const double* x1,
                              const double* x2, double* y1, double* y2, void* stream);
 

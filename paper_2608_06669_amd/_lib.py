@@ -53,7 +53,8 @@ class cc_fp_opts(ctypes.Structure):
 
 
 class cc_gauge(ctypes.Structure):
-    _fields_ = [("w_oo", ctypes.c_void_p), ("w_vv", ctypes.c_void_p)]
+    _fields_ = [("w_oo", ctypes.c_void_p), ("w_vv", ctypes.c_void_p), ("m_occ", ctypes.c_int),
+                ("m_vir", ctypes.c_int)]
 
 
 class cc_info(ctypes.Structure):

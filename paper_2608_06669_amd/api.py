@@ -62,13 +62,28 @@ class DeviceProblem:
 
 
 class DeviceGauge:
-    """W_o [o][o] and W_v [v][v] of a non-orthogonal gauge as device tensors
-    plus the cc_gauge struct (column mu: gauge function mu in the orbitals)."""
+    """W_o [o][m_o] and W_v [v][m_v] of a non-orthogonal (m = o, v) or
+    redundant (m above) gauge as device tensors plus the cc_gauge struct
+    (column mu: gauge function mu in the orbitals)."""
 
     def __init__(self, w_oo, w_vv, device="cuda"):
         conv = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device).contiguous()  # noqa: E731
         self.w_oo, self.w_vv = conv(w_oo), conv(w_vv)
-        self.struct = cc_gauge(_ptr(self.w_oo), _ptr(self.w_vv))
+        self.m_occ, self.m_vir = int(self.w_oo.shape[1]), int(self.w_vv.shape[1])
+        self.struct = cc_gauge(_ptr(self.w_oo), _ptr(self.w_vv), self.m_occ, self.m_vir)
+
+    def zeros_theta(self):
+        dev = self.w_oo.device
+        mo, mv = self.m_occ, self.m_vir
+        return (torch.zeros(mo, mv, dtype=torch.float64, device=dev),
+                torch.zeros(mo, mo, mv, mv, dtype=torch.float64, device=dev))
+
+    def theta_shapes(self):
+        return (self.m_occ, self.m_vir), (self.m_occ, self.m_occ, self.m_vir, self.m_vir)
+
+    def orbital_shapes(self):
+        o, v = int(self.w_oo.shape[0]), int(self.w_vv.shape[0])
+        return (o, v), (o, o, v, v)
 
 
 def pnk_opts(**kw) -> cc_pnk_opts:
@@ -193,7 +208,9 @@ class Handle:
 
     # ---- non-orthogonal gauges ----
     def gauge_transform(self, p: DeviceProblem, g: DeviceGauge, x1, x2, to_gauge=True, stream=None):
-        y1, y2 = torch.empty_like(x1), torch.empty_like(x2)
+        s1, s2 = g.theta_shapes() if to_gauge else g.orbital_shapes()
+        y1 = torch.empty(s1, dtype=torch.float64, device=x1.device)
+        y2 = torch.empty(s2, dtype=torch.float64, device=x1.device)
         self._check(_lib().cc_gauge_transform(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct),
                                               1 if to_gauge else 0, _ptr(x1), _ptr(x2), _ptr(y1), _ptr(y2),
                                               _stream(stream)))
@@ -217,7 +234,7 @@ class Handle:
     def solve_pnk_gauge(self, p: DeviceProblem, g: DeviceGauge, th1=None, th2=None, stream=None, **opts):
         o = pnk_opts(**opts)
         if th1 is None:
-            th1, th2 = p.zeros_t()
+            th1, th2 = g.zeros_theta()
             o.init_mp2 = 1 if "init_mp2" not in opts else o.init_mp2
         info = cc_info()
         st = self._check(_lib().cc_solve_pnk_gauge(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct),
@@ -229,7 +246,7 @@ class Handle:
     def solve_fp_diis_gauge(self, p: DeviceProblem, g: DeviceGauge, th1=None, th2=None, stream=None, **opts):
         o = fp_opts(**opts)
         if th1 is None:
-            th1, th2 = p.zeros_t()
+            th1, th2 = g.zeros_theta()
         info = cc_info()
         st = self._check(_lib().cc_solve_fp_diis_gauge(self._h, ctypes.byref(p.struct), ctypes.byref(g.struct),
                                                        ctypes.byref(o), _ptr(th1), _ptr(th2), ctypes.byref(info),

@@ -19,12 +19,13 @@ using namespace pnk;
 
 namespace pnk {
 
-size_t workspace_bytes(int o, int v, int naux, int lowp, int m_max, int restart, int diis) {
+size_t workspace_bytes(int o, int v, int naux, int lowp, int m_max, int restart, int diis, int64_t outer_cap) {
   EngineOptions eo;
   eo.lowp_f32 = lowp & 1;
   eo.lowp_bf16 = (lowp >> 1) & 1;
   const int64_t nvec = (int64_t)o * v + (int64_t)o * o * v * v;
-  return engine_bytes(o, v, naux, eo) + Solver::bytes(nvec, m_max, restart, diis) + 2 * nvec * sizeof(double);
+  return engine_bytes(o, v, naux, eo) + Solver::bytes(nvec, m_max, restart, diis, outer_cap) +
+         2 * nvec * sizeof(double);
 }
 
 void check_problem(const cc_problem* p) {
@@ -64,14 +65,23 @@ Handle::~Handle() {
 Gauge* Handle::ensure_gauge(const cc_gauge* g, hipStream_t s) {
   PNK_REQUIRE(g && g->w_oo && g->w_vv, "gauge matrices must not be NULL");
   const int o = eng->o(), v = eng->v();
-  if (!gauge_mem || gauge.o != o || gauge.v != v) {
+  PNK_REQUIRE(g->m_occ >= 0 && g->m_vir >= 0, "gauge sizes must not be negative");
+  const int mo = g->m_occ ? g->m_occ : o, mv = g->m_vir ? g->m_vir : v;
+  PNK_REQUIRE(mo >= o && mv >= v, "a gauge needs at least as many functions as its block has orbitals");
+  PNK_REQUIRE(mo <= 255 && (int64_t)mo * mv <= 46000 && (int64_t)mv * mv <= 1000000,
+              "gauge sizes above m_occ 255, m_occ m_vir 46000 or m_vir 1000 are not supported");
+  const int64_t ng = (int64_t)mo * mv + (int64_t)mo * mo * mv * mv;
+  const int lowp = (eng->options().lowp_f32 ? 1 : 0) | (eng->options().lowp_bf16 ? 2 : 0);
+  const int64_t cap = std::max(sol_cap, ng);
+  const int64_t me = gauge_matrix_elems(o, v, mo, mv), ve = gauge_vector_elems(o, v, mo, mv);
+  const size_t gbytes = (size_t)(me + ve) * sizeof(double) + 16 * 256;
+  if (limit && workspace_bytes(o, v, eng->naux(), lowp, sol_m, sol_r, sol_d, cap) + gbytes > limit)
+    throw OomError("the gauge buffers (" + std::to_string(gbytes) + " bytes) and solver vectors of length " +
+                   std::to_string(ng) + " exceed the handle limit");
+  if (!gauge_mem || gauge.o != o || gauge.v != v || gauge.mo != mo || gauge.mv != mv) {
     dev_free(gauge_mem);
     gauge_mem = nullptr;
-    const int64_t me = gauge_matrix_elems(o, v), ve = gauge_vector_elems(o, v);
-    const size_t bytes = (size_t)(me + ve) * sizeof(double) + 16 * 256;
-    if (limit && workspace_bytes(o, v, eng->naux(), 0, sol_m, sol_r, sol_d) + bytes > limit)
-      throw OomError("the gauge buffers (" + std::to_string(bytes) + " bytes) exceed the handle limit");
-    gauge_mem = (double*)dev_alloc(bytes);
+    gauge_mem = (double*)dev_alloc(gbytes);
     // 256-byte aligned pieces
     char* base = (char*)gauge_mem;
     auto take = [&](int64_t elems) {
@@ -79,13 +89,22 @@ Gauge* Handle::ensure_gauge(const cc_gauge* g, hipStream_t s) {
       base += ((size_t)elems * sizeof(double) + 255) & ~(size_t)255;
       return p;
     };
-    const int64_t oo = (int64_t)o * o, vv = (int64_t)v * v, ov = (int64_t)o * v, n2 = ov * ov;
+    const int64_t ov = (int64_t)o * v, n = ov + ov * ov, mm = (int64_t)mo * mv;
     gauge.o = o;
     gauge.v = v;
-    gauge.fwd_o = take(oo); gauge.bwd_o = take(oo); gauge.Fo = take(oo);
-    gauge.fwd_v = take(vv); gauge.bwd_v = take(vv); gauge.Fv = take(vv);
-    gauge.t = take(ov + n2); gauge.w1 = take(ov + n2); gauge.w2 = take(ov + n2);
-    gauge.ta = take(n2); gauge.tb = take(n2);
+    gauge.mo = mo;
+    gauge.mv = mv;
+    gauge.fwd_o = take((int64_t)o * mo); gauge.bwd_o = take((int64_t)o * mo); gauge.Fo = take((int64_t)mo * mo);
+    gauge.fwd_v = take((int64_t)v * mv); gauge.bwd_v = take((int64_t)v * mv); gauge.Fv = take((int64_t)mv * mv);
+    gauge.t = take(n); gauge.w1 = take(n); gauge.w2 = take(n);
+    gauge.xg = take(ng); gauge.ta = take(mm * mm); gauge.tb = take(mm * mm);
+  }
+  if (sol->outer_capacity() < ng) {
+    // the outer Krylov and DIIS vectors of a redundant gauge are longer
+    // than the orbital ones
+    sol.reset();
+    sol = std::make_unique<Solver>(*eng, sol_m, sol_r, sol_d, alloc_stream, stream_ordered, ng);
+    sol_cap = ng;
   }
   gauge_setup(gauge, g->w_oo, g->w_vv, eng->f_oo(), eng->f_vv(), s);
   return &gauge;
@@ -107,7 +126,9 @@ void Handle::ensure(const cc_problem* p, int lowp, int m_max, int restart, int d
     const int R = std::max(restart, same_shape && sol ? sol_r : 0);
     const int Dd = std::max(diis, same_shape && sol ? sol_d : 0);
     const int lp = (want32 ? 1 : 0) | (want16 ? 2 : 0);
-    const size_t need = workspace_bytes(o, v, naux, lp, M, R, Dd);
+    // outer vectors keep a redundant gauge's length once one has been used
+    const int64_t cap = same_shape ? sol_cap : 0;
+    const size_t need = workspace_bytes(o, v, naux, lp, M, R, Dd, cap);
     if (limit && need > limit)
       throw OomError("problem needs " + std::to_string(need) + " workspace bytes; the handle limit is " +
                      std::to_string(limit));
@@ -130,7 +151,8 @@ void Handle::ensure(const cc_problem* p, int lowp, int m_max, int restart, int d
       xb = (double*)dev_alloc(n * sizeof(double));
     }
     sol.reset();
-    sol = std::make_unique<Solver>(*eng, M, R, Dd, alloc_stream, stream_ordered);
+    sol = std::make_unique<Solver>(*eng, M, R, Dd, alloc_stream, stream_ordered, cap);
+    sol_cap = cap;
     sol_m = M;
     sol_r = R;
     sol_d = Dd;
@@ -475,11 +497,8 @@ cc_status cc_gauge_transform(cc_handle* h, const cc_problem* p, const cc_gauge* 
   H->ensure(p, 0, 1, 1, 0, s);
   Gauge* G = H->ensure_gauge(g, s);
   const int o = H->eng->o(), v = H->eng->v();
-  const int64_t ov = (int64_t)o * v, n2 = H->eng->nvec() - ov;
-  pack(ov, n2, x1, x2, H->xa, s);
-  if (to_gauge) gauge_apply(o, v, G->fwd_o, G->fwd_v, H->xa, H->xb, G->ta, G->tb, s);
-  else gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, H->xb, G->ta, G->tb, s);
-  unpack(ov, n2, H->xb, y1, y2, s);
+  if (to_gauge) gauge_apply(o, v, G->mo, G->mv, G->fwd_o, G->fwd_v, x1, x2, y1, y2, G->ta, G->tb, s);
+  else gauge_apply(G->mo, G->mv, o, v, G->bwd_o, G->bwd_v, x1, x2, y1, y2, G->ta, G->tb, s);
   PNK_HIP(hipStreamSynchronize(s));
   return CC_OK;
   PNK_API_END
@@ -493,12 +512,10 @@ cc_status cc_residual_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g
   H->ensure(p, 0, 1, 1, 0, s);
   Gauge* G = H->ensure_gauge(g, s);
   const int o = H->eng->o(), v = H->eng->v();
-  const int64_t ov = (int64_t)o * v, n2 = H->eng->nvec() - ov;
-  pack(ov, n2, th1, th2, H->xa, s);
-  gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, G->t, G->ta, G->tb, s);
+  const int64_t ov = (int64_t)o * v;
+  gauge_apply(G->mo, G->mv, o, v, G->bwd_o, G->bwd_v, th1, th2, G->t, G->t + ov, G->ta, G->tb, s);
   H->eng->residual(G->t, G->t + ov, G->w1, G->w1 + ov, s);
-  gauge_apply(o, v, G->fwd_o, G->fwd_v, G->w1, H->xb, G->ta, G->tb, s);
-  unpack(ov, n2, H->xb, r1, r2, s);
+  gauge_apply(o, v, G->mo, G->mv, G->fwd_o, G->fwd_v, G->w1, G->w1 + ov, r1, r2, G->ta, G->tb, s);
   if (e_corr_host) {
     H->eng->energy(G->t, G->t + ov, H->eng->scratch_partials() + 1024, s);
     PNK_HIP(hipMemcpyAsync(e_corr_host, H->eng->scratch_partials() + 1024, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -518,16 +535,13 @@ cc_status cc_jvp_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* g, con
   H->ensure(p, lowp_for(prec), 1, 1, 0, s);
   Gauge* G = H->ensure_gauge(g, s);
   const int o = H->eng->o(), v = H->eng->v();
-  const int64_t ov = (int64_t)o * v, n2 = H->eng->nvec() - ov;
-  // linearise at t(theta), then J_theta v = (W^T)^(x4) J (W^-T)^(x4) v
-  pack(ov, n2, th1, th2, H->xa, s);
-  gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, G->t, G->ta, G->tb, s);
+  const int64_t ov = (int64_t)o * v;
+  // linearise at t(theta), then J_theta v = (W^T)^(x4) J (C^T)^(x4) v
+  gauge_apply(G->mo, G->mv, o, v, G->bwd_o, G->bwd_v, th1, th2, G->t, G->t + ov, G->ta, G->tb, s);
   H->eng->residual(G->t, G->t + ov, G->w1, G->w1 + ov, s);
-  pack(ov, n2, v1, v2, H->xa, s);
-  gauge_apply(o, v, G->bwd_o, G->bwd_v, H->xa, G->w1, G->ta, G->tb, s);
+  gauge_apply(G->mo, G->mv, o, v, G->bwd_o, G->bwd_v, v1, v2, G->w1, G->w1 + ov, G->ta, G->tb, s);
   H->eng->jvp(G->w1, G->w1 + ov, G->w2, G->w2 + ov, (Prec)prec, s);
-  gauge_apply(o, v, G->fwd_o, G->fwd_v, G->w2, H->xb, G->ta, G->tb, s);
-  unpack(ov, n2, H->xb, jv1, jv2, s);
+  gauge_apply(o, v, G->mo, G->mv, G->fwd_o, G->fwd_v, G->w2, G->w2 + ov, jv1, jv2, G->ta, G->tb, s);
   PNK_HIP(hipStreamSynchronize(s));
   return CC_OK;
   PNK_API_END
@@ -553,14 +567,14 @@ cc_status cc_solve_pnk_gauge(cc_handle* h, const cc_problem* p, const cc_gauge* 
   check_pnk_opts(o);
   H->ensure(p, lowp_for(o.jvp_prec), o.m_max, o.inner_restart, 0, s);
   Gauge* G = H->ensure_gauge(g, s);
-  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
-  if (!o.init_mp2) pack(ov, n2, th1, th2, H->xa, s);
+  const int64_t gov = (int64_t)G->mo * G->mv, gn2 = G->nvec() - gov;
+  if (!o.init_mp2) pack(gov, gn2, th1, th2, G->xg, s);
   SolveStats st;
   {
     GaugeScope scope(H->sol.get(), G);
-    H->sol->solve_pnk(H->xa, to_internal(o), &st, s);
+    H->sol->solve_pnk(G->xg, to_internal(o), &st, s);
   }
-  unpack(ov, n2, H->xa, th1, th2, s);
+  unpack(gov, gn2, G->xg, th1, th2, s);
   PNK_HIP(hipStreamSynchronize(s));
   H->history = H->sol->history();
   fill_info(st, info);
@@ -581,8 +595,8 @@ cc_status cc_solve_fp_diis_gauge(cc_handle* h, const cc_problem* p, const cc_gau
               "invalid FP options");
   H->ensure(p, 0, 1, 30, std::max(o.diis_size, 1), s);
   Gauge* G = H->ensure_gauge(g, s);
-  const int64_t ov = H->eng->o() * (int64_t)H->eng->v(), n2 = H->eng->nvec() - ov;
-  if (!o.init_mp2) pack(ov, n2, th1, th2, H->xa, s);
+  const int64_t gov = (int64_t)G->mo * G->mv, gn2 = G->nvec() - gov;
+  if (!o.init_mp2) pack(gov, gn2, th1, th2, G->xg, s);
   FpOptions fo;
   fo.tol_inf = o.tol_inf;
   fo.max_iter = o.max_iter;
@@ -594,9 +608,9 @@ cc_status cc_solve_fp_diis_gauge(cc_handle* h, const cc_problem* p, const cc_gau
   SolveStats st;
   {
     GaugeScope scope(H->sol.get(), G);
-    H->sol->solve_fp_diis(H->xa, fo, &st, s);
+    H->sol->solve_fp_diis(G->xg, fo, &st, s);
   }
-  unpack(ov, n2, H->xa, th1, th2, s);
+  unpack(gov, gn2, G->xg, th1, th2, s);
   PNK_HIP(hipStreamSynchronize(s));
   H->history = H->sol->history();
   fill_info(st, info);

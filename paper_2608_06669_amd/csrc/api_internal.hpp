@@ -30,6 +30,7 @@ struct Handle {
   std::unique_ptr<Engine> eng;
   std::unique_ptr<Solver> sol;
   int sol_m = 0, sol_r = 0, sol_d = 0;
+  int64_t sol_cap = 0;   // outer vector length of the solver, if a gauge's
   double* xa = nullptr;  // packed vectors
   double* xb = nullptr;
   uint64_t* hash_buf = nullptr;
@@ -41,8 +42,10 @@ struct Handle {
   Gauge gauge;                      // buffers of the non-orthogonal gauge entry points
   double* gauge_mem = nullptr;
   ~Handle();
-  // Size the gauge buffers for the engine's (o, v) and fill its matrices
-  // from g and the prepared problem's Fock blocks (after ensure()).
+  // Size the gauge buffers for the engine's (o, v) and g's (m_occ, m_vir),
+  // grow the solver's outer vectors to the gauge's length, and fill the
+  // gauge's matrices from g and the prepared problem's Fock blocks (after
+  // ensure()).
   Gauge* ensure_gauge(const cc_gauge* g, hipStream_t s);
   void* dev_alloc(size_t bytes);
   void dev_free(void* p);
@@ -51,7 +54,9 @@ struct Handle {
   void ensure(const cc_problem* p, int lowp, int m_max, int restart, int diis, hipStream_t s);
 };
 
-size_t workspace_bytes(int o, int v, int naux, int lowp, int m_max, int restart, int diis);
+// outer_cap: length of the solver's outer vectors when above the orbital
+// one (a redundant gauge's)
+size_t workspace_bytes(int o, int v, int naux, int lowp, int m_max, int restart, int diis, int64_t outer_cap = 0);
 // Scratch sizes of the batched diagnostic product: split-K partial sums
 // (elements, at most kDiagSplitElems) and rounded operand copies (bytes).
 constexpr int64_t kDiagSplitElems = int64_t(4) << 20;

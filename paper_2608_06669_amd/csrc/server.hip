@@ -89,7 +89,7 @@ size_t request_footprint(int o, int v, int naux, const cc_pnk_opts& op) {
 size_t handle_bytes(const Handle& H) {
   if (!H.eng) return 0;
   const int lp = (H.eng->options().lowp_f32 ? 1 : 0) | (H.eng->options().lowp_bf16 ? 2 : 0);
-  return workspace_bytes(H.eng->o(), H.eng->v(), H.eng->naux(), lp, H.sol_m, H.sol_r, H.sol_d);
+  return workspace_bytes(H.eng->o(), H.eng->v(), H.eng->naux(), lp, H.sol_m, H.sol_r, H.sol_d, H.sol_cap);
 }
 
 std::unique_ptr<Handle> take_cached(cc_server* S, int o, int v, int naux, int lowp, size_t* bytes) {

@@ -60,13 +60,18 @@ std::vector<double> back_substitute(const std::vector<double>& H, int ldh, const
 
 }  // namespace
 
-size_t Solver::bytes(int64_t n, int m_max, int restart, int diis) {
-  const size_t vecs = (size_t)(m_max + 1) + (restart + 1) + 4 + 2 * (size_t)diis;
-  return vecs * n * sizeof(double) + (kScal + reduce_partials_size(kMaxBasis)) * sizeof(double) + 16 * 256;
+size_t Solver::bytes(int64_t n, int m_max, int restart, int diis, int64_t outer_cap) {
+  const int64_t cap = std::max(n, outer_cap);
+  const size_t outer = (size_t)(m_max + 1) + 3 + 2 * (size_t)diis;
+  const size_t inner = (size_t)(restart + 1) + 1;
+  return (outer * cap + inner * n) * sizeof(double) + (kScal + reduce_partials_size(kMaxBasis)) * sizeof(double) +
+         16 * 256;
 }
 
-Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_stream, bool stream_ordered)
-    : eng_(eng), n_(eng.nvec()), m_max_(m_max), restart_(restart), diis_(diis), alloc_stream_(alloc_stream),
+Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_stream, bool stream_ordered,
+               int64_t outer_cap)
+    : eng_(eng), n_(eng.nvec()), cap_(std::max(eng.nvec(), outer_cap)), nv_(eng.nvec()), vo_(eng.o()),
+      vv_(eng.v()), m_max_(m_max), restart_(restart), diis_(diis), alloc_stream_(alloc_stream),
       async_(stream_ordered) {
   PNK_REQUIRE(m_max >= 1 && m_max < kMaxBasis && restart >= 1 && restart < kMaxBasis && diis >= 0 && diis < 64,
               "solver: Krylov or DIIS size out of range");
@@ -81,14 +86,14 @@ Solver::Solver(Engine& eng, int m_max, int restart, int diis, hipStream_t alloc_
     }
     return p;
   };
-  Qo_ = alloc((size_t)(m_max + 1) * n_);
+  Qo_ = alloc((size_t)(m_max + 1) * cap_);
   Qi_ = alloc((size_t)(restart + 1) * n_);
-  r_ = alloc(n_);
+  r_ = alloc(cap_);
   ri_ = alloc(n_);
-  w_ = alloc(n_);
-  w2_ = alloc(n_);
-  hx_ = alloc((size_t)diis * n_);
-  he_ = alloc((size_t)diis * n_);
+  w_ = alloc(cap_);
+  w2_ = alloc(cap_);
+  hx_ = alloc((size_t)diis * cap_);
+  he_ = alloc((size_t)diis * cap_);
   dsc_ = alloc(kScal);
   partials_ = alloc(reduce_partials_size(kMaxBasis));
   PNK_HIP(hipHostMalloc(&host_, kScal * sizeof(double), hipHostMallocDefault));
@@ -121,23 +126,38 @@ void Solver::read_scalars(double* host, const double* dev, int n, hipStream_t s)
   PNK_HIP(hipStreamSynchronize(s));
 }
 
-void Solver::norms(const double* r, double* ninf, double* n2, hipStream_t s) {
-  nrm_inf(n_, r, dsc_ + 0, partials_, s);
-  nrm2(n_, r, dsc_ + 1, partials_ + kReduceBlocks, s);
+void Solver::set_gauge(const Gauge* g) {
+  if (g) {
+    PNK_REQUIRE(g->nvec() <= cap_, "solver: the gauge's vectors exceed the outer capacity");
+    nv_ = g->nvec();
+    vo_ = g->mo;
+    vv_ = g->mv;
+  } else {
+    nv_ = n_;
+    vo_ = eng_.o();
+    vv_ = eng_.v();
+  }
+  gauge_ = g;
+}
+
+void Solver::norms(int64_t n, const double* r, double* ninf, double* n2, hipStream_t s) {
+  nrm_inf(n, r, dsc_ + 0, partials_, s);
+  nrm2(n, r, dsc_ + 1, partials_ + kReduceBlocks, s);
   read_scalars(host_, dsc_, 2, s);
   *ninf = host_[0];
   *n2 = host_[1];
 }
 
-double Solver::orthogonalise(double* Q, int64_t ldq, int m, double* w, std::vector<double>& h, hipStream_t s) {
+double Solver::orthogonalise(int64_t n, double* Q, int64_t ldq, int m, double* w, std::vector<double>& h,
+                             hipStream_t s) {
   double* h1 = dsc_;
   double* h2 = dsc_ + kMaxBasis;
   double* hn = dsc_ + 2 * kMaxBasis;
-  multi_dot(n_, m, Q, ldq, w, h1, partials_, s);
-  multi_axpy(n_, m, Q, ldq, h1, w, s);
-  multi_dot(n_, m, Q, ldq, w, h2, partials_, s);
-  multi_axpy(n_, m, Q, ldq, h2, w, s);
-  nrm2(n_, w, hn, partials_, s);
+  multi_dot(n, m, Q, ldq, w, h1, partials_, s);
+  multi_axpy(n, m, Q, ldq, h1, w, s);
+  multi_dot(n, m, Q, ldq, w, h2, partials_, s);
+  multi_axpy(n, m, Q, ldq, h2, w, s);
+  nrm2(n, w, hn, partials_, s);
   read_scalars(host_, dsc_, 2 * kMaxBasis + 1, s);
   h.assign(m, 0.0);
   for (int i = 0; i < m; ++i) h[i] = host_[i] + host_[kMaxBasis + i];
@@ -824,7 +844,7 @@ int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, in
     return precond_solve_sym(b, x, rtol, maxit, s, converged, packed);
   }
   double bn, dummy;
-  norms(b, &dummy, &bn, s);
+  norms(n, b, &dummy, &bn, s);
   fill(n, 0.0, x, s);
   if (converged) *converged = true;
   if (bn == 0.0) return 0;
@@ -849,7 +869,7 @@ int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, in
       double* wv = Qi_ + (size_t)(k + 1) * n;
       eng_.fock_apply(q, q + ov, wv, wv + ov, s);
       ++total;
-      const double hn = orthogonalise(Qi_, n, k + 1, wv, h, s);
+      const double hn = orthogonalise(n, Qi_, n, k + 1, wv, h, s);
       for (int i = 0; i <= k; ++i) H[i + (size_t)k * (restart + 1)] = h[i];
       H[k + 1 + (size_t)k * (restart + 1)] = hn;
       for (int i = 0; i < k; ++i) {
@@ -884,7 +904,7 @@ int Solver::precond_solve(const double* b, double* x, double rtol, int maxit, in
     eng_.fock_apply(x, x + ov, ri_, ri_ + ov, s);
     axpby(n, 1.0, b, -1.0, ri_, s);
     double rinf;
-    norms(ri_, &rinf, &beta, s);
+    norms(n, ri_, &rinf, &beta, s);
   }
 }
 
@@ -904,9 +924,10 @@ double forcing(int k, double rn, double rn_prev, double eta_prev, double tol, co
 }
 }  // namespace
 
-// In a gauge: r(theta) = (W^T)^(x4) r(t), t = (W^-T)^(x4) theta (kept in
+// In a gauge: r(theta) = (W^T)^(x4) r(t), t = (C^T)^(x4) theta (kept in
 // gauge_->t, the point J v is linearised at); A_F of the gauge is inverted
-// as (W^T)^(x4) A_F^-1 (W^-T)^(x4); the energy is that of t.
+// on the range of (W^T)^(x4) as (W^T)^(x4) A_F^-1 (C^T)^(x4); the energy is
+// that of t.
 void Solver::g_residual(const double* x, double* r, hipStream_t s) {
   const int o = eng_.o(), vir = eng_.v();
   const int64_t ov = (int64_t)o * vir;
@@ -915,18 +936,20 @@ void Solver::g_residual(const double* x, double* r, hipStream_t s) {
     return;
   }
   const Gauge& g = *gauge_;
-  gauge_apply(o, vir, g.bwd_o, g.bwd_v, x, g.t, g.ta, g.tb, s);
+  const int64_t gov = (int64_t)g.mo * g.mv;
+  gauge_apply(g.mo, g.mv, o, vir, g.bwd_o, g.bwd_v, x, x + gov, g.t, g.t + ov, g.ta, g.tb, s);
   eng_.residual(g.t, g.t + ov, g.w1, g.w1 + ov, s);
-  gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w1, r, g.ta, g.tb, s);
+  gauge_apply(o, vir, g.mo, g.mv, g.fwd_o, g.fwd_v, g.w1, g.w1 + ov, r, r + gov, g.ta, g.tb, s);
 }
 
 int Solver::g_precond(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s, bool* conv) {
   if (!gauge_) return precond_solve(b, x, rtol, maxit, restart, s, conv, true);
   const Gauge& g = *gauge_;
   const int o = eng_.o(), vir = eng_.v();
-  gauge_apply(o, vir, g.bwd_o, g.bwd_v, b, g.w2, g.ta, g.tb, s);
+  const int64_t ov = (int64_t)o * vir, gov = (int64_t)g.mo * g.mv;
+  gauge_apply(g.mo, g.mv, o, vir, g.bwd_o, g.bwd_v, b, b + gov, g.w2, g.w2 + ov, g.ta, g.tb, s);
   const int it = precond_solve(g.w2, g.w1, rtol, maxit, restart, s, conv, true);
-  gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w1, x, g.ta, g.tb, s);
+  gauge_apply(o, vir, g.mo, g.mv, g.fwd_o, g.fwd_v, g.w1, g.w1 + ov, x, x + gov, g.ta, g.tb, s);
   return it;
 }
 
@@ -938,8 +961,15 @@ void Solver::g_energy(const double* x, double* e_dev, hipStream_t s) {
     return;
   }
   const Gauge& g = *gauge_;
-  gauge_apply(o, vir, g.bwd_o, g.bwd_v, x, g.w1, g.ta, g.tb, s);
+  const int64_t gov = (int64_t)g.mo * g.mv;
+  gauge_apply(g.mo, g.mv, o, vir, g.bwd_o, g.bwd_v, x, x + gov, g.w1, g.w1 + ov, g.ta, g.tb, s);
   eng_.energy(g.w1, g.w1 + ov, e_dev, s);
+}
+
+const double* Solver::g_zeros(hipStream_t s) {
+  if (!gauge_) return eng_.zeros();
+  fill(nv_, 0.0, w2_, s);
+  return w2_;
 }
 
 void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s) {
@@ -947,14 +977,19 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   *st = SolveStats();
   hist_.clear();
   PNK_REQUIRE(opt.m_max >= 1 && opt.m_max <= m_max_, "pnk: m_max exceeds the allocated basis");
-  const int64_t n = n_;
-  const int o = eng_.o(), vir = eng_.v();
-  const int64_t ov = (int64_t)o * vir;
+  // outer vectors: length n with singles of gov elements over (vo, vv)
+  // (the orbital ones, or the gauge's); ov: the orbital singles
+  const int64_t n = nv_;
+  const int o = eng_.o(), vir = eng_.v(), vo = vo_, vv = vv_;
+  const int64_t ov = (int64_t)o * vir, gov = (int64_t)vo * vv;
   PNK_REQUIRE(opt.protocol == PnkOptions::kPNK || opt.protocol == PnkOptions::kNK ||
                   opt.protocol == PnkOptions::kINK,
               "pnk: unknown protocol");
   // CCD level: every vector keeps zero singles
   auto mask = [&](double* y) {
+    if (opt.ccd) fill(gov, 0.0, y, s);
+  };
+  auto mask_orb = [&](double* y) {
     if (opt.ccd) fill(ov, 0.0, y, s);
   };
   // tolerance of the inner solves of A_F^-1 J q inside the Krylov loop
@@ -964,9 +999,9 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
       // no preconditioner: the identity on pair-symmetric vectors, applied
       // as the projection (b2 + b2^T over pairs) / 2 so that rounding-level
       // antisymmetric parts do not enter the Krylov space
-      copy(ov, b, out, s);
-      fill(n - ov, 0.0, out + ov, s);
-      pair_symmetrize_add(o, vir, b + ov, 0.5, out + ov, s);
+      copy(gov, b, out, s);
+      fill(n - gov, 0.0, out + gov, s);
+      pair_symmetrize_add(vo, vv, b + gov, 0.5, out + gov, s);
     } else {
       bool conv = true;
       const int it = g_precond(b, out, rtol, opt.inner_maxit, opt.inner_restart, s, &conv);
@@ -977,7 +1012,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
   };
   if (opt.init_mp2) {
     // MP2-type start for every protocol (NK included): -A_F^-1 r(0)
-    g_residual(eng_.zeros(), r_, s);
+    g_residual(g_zeros(s), r_, s);
     st->n_residual++;
     mask(r_);
     bool conv = true;
@@ -997,7 +1032,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     st->n_residual++;
     mask(r_);
     double rinf, rn;
-    norms(r_, &rinf, &rn, s);
+    norms(n, r_, &rinf, &rn, s);
     hist_.push_back(rn);
     hist_.push_back(rinf);
     st->res_inf = rinf;
@@ -1030,7 +1065,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     // z = A_F^{-1} r, q_1 = z / beta
     Ainv(r_, w_, opt.inner_rtol);
     double zinf, beta;
-    norms(w_, &zinf, &beta, s);
+    norms(n, w_, &zinf, &beta, s);
     if (!(beta > 0.0) || !std::isfinite(beta)) { st->diverged = !std::isfinite(beta); break; }
     scale_by_inverse(n, w_, dsc_ + 1, Qo_, s);  // beta from norms()
     const int M = opt.m_max;
@@ -1042,7 +1077,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
     double delta = 0.0;
     if (opt.use_fd_jvp) {
       double xinf, xn;
-      norms(x, &xinf, &xn, s);
+      norms(n, x, &xinf, &xn, s);
       delta = std::sqrt(2.220446049250313e-16) * (1.0 + xn);
     }
     int m_done = 0;
@@ -1050,19 +1085,19 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
       double* q = Qo_ + (size_t)m * n;
       double* wv = Qo_ + (size_t)(m + 1) * n;
       if (gauge_ && !opt.use_fd_jvp && opt.protocol == PnkOptions::kPNK) {
-        // A_F^-1 J in the gauge is (W^T)^(x4) A_F^-1 J (W^-T)^(x4): the
+        // A_F^-1 J in the gauge is (W^T)^(x4) A_F^-1 J (C^T)^(x4): the
         // transforms between the two products cancel
         const Gauge& g = *gauge_;
-        gauge_apply(o, vir, g.bwd_o, g.bwd_v, q, g.w1, g.ta, g.tb, s);
+        gauge_apply(vo, vv, o, vir, g.bwd_o, g.bwd_v, q, q + gov, g.w1, g.w1 + ov, g.ta, g.tb, s);
         eng_.jvp(g.w1, g.w1 + ov, g.w2, g.w2 + ov, opt.jvp_prec, s);
         st->n_jvp++;
-        mask(g.w2);
+        mask_orb(g.w2);
         bool conv = true;
         const int it = precond_solve(g.w2, g.w1, krylov_rtol, opt.inner_maxit, opt.inner_restart, s, &conv, true);
         st->n_afmv += it;
         st->n_inner_iters += it;
-        mask(g.w1);
-        gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w1, wv, g.ta, g.tb, s);
+        mask_orb(g.w1);
+        gauge_apply(o, vir, vo, vv, g.fwd_o, g.fwd_v, g.w1, g.w1 + ov, wv, wv + gov, g.ta, g.tb, s);
       } else {
         if (opt.use_fd_jvp) {
           // (r(theta + delta q) - r(theta)) / delta, the paper's product
@@ -1072,9 +1107,9 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
           axpby(n, -1.0 / delta, r_, 1.0 / delta, w_, s);
         } else if (gauge_) {
           const Gauge& g = *gauge_;
-          gauge_apply(o, vir, g.bwd_o, g.bwd_v, q, g.w1, g.ta, g.tb, s);
+          gauge_apply(vo, vv, o, vir, g.bwd_o, g.bwd_v, q, q + gov, g.w1, g.w1 + ov, g.ta, g.tb, s);
           eng_.jvp(g.w1, g.w1 + ov, g.w2, g.w2 + ov, opt.jvp_prec, s);
-          gauge_apply(o, vir, g.fwd_o, g.fwd_v, g.w2, w_, g.ta, g.tb, s);
+          gauge_apply(o, vir, vo, vv, g.fwd_o, g.fwd_v, g.w2, g.w2 + ov, w_, w_ + gov, g.ta, g.tb, s);
         } else {
           eng_.jvp(q, q + ov, w_, w_ + ov, opt.jvp_prec, s);
         }
@@ -1082,7 +1117,7 @@ void Solver::solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStre
         mask(w_);
         Ainv(w_, wv, krylov_rtol);
       }
-      const double hn = orthogonalise(Qo_, n, m + 1, wv, h, s);
+      const double hn = orthogonalise(n, Qo_, n, m + 1, wv, h, s);
       for (int i = 0; i <= m; ++i) H[i + (size_t)m * (M + 1)] = h[i];
       for (int i = 0; i < m; ++i) {
         double& a = H[i + (size_t)m * (M + 1)];
@@ -1129,7 +1164,7 @@ double Solver::fp_spectral_radius(const double* t, const double* q0, double shif
   const int64_t ov = (int64_t)o * vir;
   eng_.residual(t, t + ov, r_, r_ + ov, s);  // linearise at t
   double qinf, qn;
-  norms(q0, &qinf, &qn, s);
+  norms(n, q0, &qinf, &qn, s);
   PNK_REQUIRE(qn > 0.0 && std::isfinite(qn), "fp_spectral_radius: the start vector is zero or not finite");
   scale_by_inverse(n, q0, dsc_ + 1, Qo_, s);
   std::vector<double> H((size_t)(m + 1) * m, 0.0), h;
@@ -1143,7 +1178,7 @@ double Solver::fp_spectral_radius(const double* t, const double* q0, double shif
     copy(ov, w2_, wv, s);
     fill(n - ov, 0.0, wv + ov, s);
     pair_symmetrize_add(o, vir, w2_ + ov, 0.5, wv + ov, s);
-    const double hn = orthogonalise(Qo_, n, k + 1, wv, h, s);
+    const double hn = orthogonalise(n, Qo_, n, k + 1, wv, h, s);
     for (int i = 0; i <= k; ++i) H[(size_t)i * m + k] = h[i];
     k_done = k + 1;
     if (!std::isfinite(hn)) break;
@@ -1243,17 +1278,18 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
   *st = SolveStats();
   hist_.clear();
   PNK_REQUIRE(opt.diis_size <= diis_, "fp: DIIS size exceeds the allocated history");
-  const int64_t n = n_;
-  const int64_t ov = (int64_t)eng_.o() * eng_.v();
+  // outer vectors: the orbital ones or the gauge's (dimensions vo_, vv_)
+  const int64_t n = nv_;
+  const int64_t gov = (int64_t)vo_ * vv_;
   auto mask = [&](double* y) {
-    if (opt.ccd) fill(ov, 0.0, y, s);
+    if (opt.ccd) fill(gov, 0.0, y, s);
   };
   // Jacobi denominators from the diagonals of the Fock blocks of the
   // gauge the iteration runs in
   const double* fo = gauge_ ? gauge_->Fo : eng_.f_oo();
   const double* fv = gauge_ ? gauge_->Fv : eng_.f_vv();
   if (opt.init_mp2) {
-    g_residual(eng_.zeros(), r_, s);
+    g_residual(g_zeros(s), r_, s);
     st->n_residual++;
     mask(r_);
     bool conv = true;
@@ -1272,7 +1308,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     st->n_residual++;
     mask(r_);
     double rinf, rn;
-    norms(r_, &rinf, &rn, s);
+    norms(n, r_, &rinf, &rn, s);
     hist_.push_back(rn);
     hist_.push_back(rinf);
     st->res_inf = rinf;
@@ -1282,7 +1318,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     if (rinf < opt.tol_inf) { st->converged = 1; break; }
     if (it >= opt.max_iter || rn > 1e6) break;
     if (nd == 0) {
-      jacobi_update(eng_.o(), eng_.v(), fo, fv, opt.level_shift, r_, x, nullptr, s);
+      jacobi_update(vo_, vv_, fo, fv, opt.level_shift, r_, x, nullptr, s);
       ++it;
       continue;
     }
@@ -1298,7 +1334,7 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     double* xs = hx_ + (size_t)slot * n;
     double* es = he_ + (size_t)slot * n;
     copy(n, x, xs, s);
-    jacobi_update(eng_.o(), eng_.v(), fo, fv, opt.level_shift, r_, xs, es, s);
+    jacobi_update(vo_, vv_, fo, fv, opt.level_shift, r_, xs, es, s);
     // B row of the new error vector against every stored one (slot order)
     const int m = (int)slots.size();
     const int mm = std::max(nd, 1);

@@ -60,13 +60,17 @@ struct SolveStats {
 // host scalars. Sized once; reused across solves of the same dimensions.
 class Solver {
  public:
+  // outer_cap: length the outer Krylov, residual and DIIS vectors are
+  // sized for (0: the engine's vector length; a redundant gauge needs its
+  // own, longer one)
   Solver(Engine& eng, int m_max, int inner_restart, int diis_size, hipStream_t alloc_stream = nullptr,
-         bool stream_ordered = false);
+         bool stream_ordered = false, int64_t outer_cap = 0);
   ~Solver();
   Solver(const Solver&) = delete;
   Solver& operator=(const Solver&) = delete;
 
-  static size_t bytes(int64_t nvec, int m_max, int inner_restart, int diis_size);
+  static size_t bytes(int64_t nvec, int m_max, int inner_restart, int diis_size, int64_t outer_cap = 0);
+  int64_t outer_capacity() const { return cap_; }
 
   // A_F x = b by restarted GMRES to ||b - A_F x|| <= rtol ||b||; packed
   // [t1 | t2] vectors of length nvec. Returns the number of A_F products.
@@ -95,13 +99,14 @@ class Solver {
   // (the packed three-launch form uses kLanczosBlock)
   void solve_pnk(double* x, const PnkOptions& opt, SolveStats* st, hipStream_t s);
   void solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipStream_t s);
-  // Solve for the amplitudes of a non-orthogonal gauge (nullptr: the
-  // orbital basis, the default). solve_pnk and solve_fp_diis then iterate
-  // on gauge vectors: x, the residual, the stopping test and the FP
-  // denominators (diagonals of the gauge's Fock blocks) are the gauge's,
-  // while the engine works in the orbital basis between the transforms.
-  // The gauge's buffers must outlive the solves that use it.
-  void set_gauge(const Gauge* g) { gauge_ = g; }
+  // Solve for the amplitudes of a non-orthogonal or redundant gauge
+  // (nullptr: the orbital basis, the default). solve_pnk and solve_fp_diis
+  // then iterate on gauge vectors (length g->nvec(), at most the outer
+  // capacity): x, the residual, the stopping test and the FP denominators
+  // (diagonals of the gauge's Fock blocks) are the gauge's, while the
+  // engine works in the orbital basis between the transforms. The gauge's
+  // buffers must outlive the solves that use it.
+  void set_gauge(const Gauge* g);
 
   // Residual history (norm-2, norm-inf) per outer residual evaluation.
   const std::vector<double>& history() const { return hist_; }
@@ -109,22 +114,25 @@ class Solver {
  private:
   void read_scalars(double* host, const double* dev, int n, hipStream_t s);
   void upload(double* dev, const double* src, int n, hipStream_t s);
-  // CGS2 against Q[0..m-1] (stride ldq), returns h (m entries) and ||w|| on
-  // the host; w is left orthogonalised, not normalised.
-  double orthogonalise(double* Q, int64_t ldq, int m, double* w, std::vector<double>& h, hipStream_t s);
-  void norms(const double* r, double* ninf, double* n2, hipStream_t s);
+  // CGS2 of w (length n) against Q[0..m-1] (stride ldq), returns h (m
+  // entries) and ||w|| on the host; w is left orthogonalised, not normalised.
+  double orthogonalise(int64_t n, double* Q, int64_t ldq, int m, double* w, std::vector<double>& h, hipStream_t s);
+  void norms(int64_t n, const double* r, double* ninf, double* n2, hipStream_t s);
 
   Engine& eng_;
-  int64_t n_;
+  int64_t n_;       // orbital vector length (the inner solves)
+  int64_t cap_;     // capacity of the outer vectors
+  int64_t nv_;      // current outer vector length: n_, or the gauge's
+  int vo_, vv_;     // occupied / virtual dimensions of the outer vectors
   int m_max_, restart_, diis_;
-  double* Qo_;     // outer Krylov basis (m_max + 1) x n
+  double* Qo_;     // outer Krylov basis (m_max + 1) x cap
   double* Qi_;     // inner Krylov basis (restart + 1) x n
-  double* r_;      // residual
-  double* ri_;     // inner GMRES residual
-  double* w_;      // work vectors
+  double* r_;      // residual (cap)
+  double* ri_;     // inner GMRES residual (n)
+  double* w_;      // work vectors (cap)
   double* w2_;
-  double* hx_;     // DIIS amplitudes, diis x n
-  double* he_;     // DIIS error vectors, diis x n
+  double* hx_;     // DIIS amplitudes, diis x cap
+  double* he_;     // DIIS error vectors, diis x cap
   double* dsc_;    // device scalars
   double* partials_;
   double* host_;   // pinned host scalars
@@ -161,6 +169,8 @@ class Solver {
   void g_residual(const double* x, double* r, hipStream_t s);
   int g_precond(const double* b, double* x, double rtol, int maxit, int restart, hipStream_t s, bool* conv);
   void g_energy(const double* x, double* e_dev, hipStream_t s);
+  // a zero outer vector (the engine's, or w2_ cleared to the gauge's length)
+  const double* g_zeros(hipStream_t s);
 };
 
 }  // namespace pnk

@@ -1,6 +1,11 @@
 """GPU parity in non-orthogonal gauges: the gauge entry points of the C
 boundary against the oracle's random-gauge equations (oracle.gauge).
 
+Redundant gauges (more gauge functions than orbitals, W of full row rank)
+are checked the same way, plus what is particular to them: the solves
+return amplitudes in the range of U-bar^(x4), components outside it change
+nothing, and a W that is not of full row rank is refused.
+
 Tolerances (FP64): the transforms are four short contractions (depth o or
 v) with entries of size cond(W); both sides sum in float64 in different
 orders, so we allow 1e-12 relative to the largest output. Residuals and J v
@@ -13,7 +18,7 @@ cond(W) = 4 we allow 1e-9 relative. Solves compare what is unique: the root
 import numpy as np
 import pytest
 
-from gen import make_config, make_general, make_problem, nonorthogonal_gauge, random_amplitudes
+from gen import make_config, make_general, make_problem, nonorthogonal_gauge, random_amplitudes, redundant_gauge
 from oracle import gauge, solvers
 
 pytestmark = pytest.mark.gpu
@@ -212,3 +217,149 @@ def test_gauge_covariance_at_the_full_c2_size(handle, lib):
         m, n, lam, sig = rng.integers(0, o), rng.integers(0, o), rng.integers(0, v), rng.integers(0, v)
         ref = np.einsum("i,j,a,b,ijab->", Wo[:, m], Wo[:, n], Wv[:, lam], Wv[:, sig], t2)
         assert abs(h2[m, n, lam, sig] - ref) < 1e-12 * max(1.0, np.abs(h2).max())
+
+
+# (o, v, m_o, m_v): one and several matrix-core tiles, ragged edges
+RSHAPES = [(1, 1, 2, 3, 3), (3, 7, 5, 11, 14), (5, 37, 8, 50, 40), (6, 70, 9, 90, 50)]
+
+
+def _theta(mo, mv, seed, scale):
+    """Random pair-symmetric gauge-shaped amplitudes (not in the range)."""
+    rng = np.random.default_rng(seed)
+    a1 = scale * rng.standard_normal((mo, mv))
+    a2 = scale * rng.standard_normal((mo, mo, mv, mv))
+    return a1, 0.5 * (a2 + a2.transpose(1, 0, 3, 2))
+
+
+@pytest.mark.parametrize("o,v,mo,mv,naux", RSHAPES)
+def test_redundant_gauge_transforms_match_the_oracle(handle, lib, o, v, mo, mv, naux):
+    p = make_general(o, v, naux, 600 + v)
+    Wo, Wv = redundant_gauge(o, v, mo, mv, 700 + v, 4.0)
+    P, G = lib.DeviceProblem.from_problem(p), lib.DeviceGauge(Wo, Wv)
+    x1, x2 = random_amplitudes(o, v, 800 + v, scale=0.3)
+    y1, y2 = handle.gauge_transform(P, G, dev(x1), dev(x2), to_gauge=True)
+    assert tuple(y2.shape) == (mo, mo, mv, mv)
+    e1, e2 = gauge.forward(Wo, Wv, x1, x2)
+    assert _rel(host(y1), e1) < 1e-12 and _rel(host(y2), e2) < 1e-12
+    g1, g2 = _theta(mo, mv, 900 + v, 0.3)
+    z1, z2 = handle.gauge_transform(P, G, dev(g1), dev(g2), to_gauge=False)
+    assert tuple(z2.shape) == (o, o, v, v)
+    b1, b2 = gauge.backward(Wo, Wv, g1, g2)
+    assert _rel(host(z1), b1) < 1e-11 and _rel(host(z2), b2) < 1e-11
+    # the back-transform inverts the forward one
+    w1, w2 = handle.gauge_transform(P, G, y1, y2, to_gauge=False)
+    assert _rel(host(w2), x2) < 1e-11 and _rel(host(w1), x1) < 1e-11
+
+
+@pytest.mark.parametrize("o,v,mo,mv,naux", RSHAPES)
+def test_redundant_gauge_residual_and_energy_match_the_oracle(handle, lib, o, v, mo, mv, naux):
+    """At gauge amplitudes with components outside the range: the residual
+    of the definition on both sides, and it lies in the range."""
+    p = make_general(o, v, naux, 610 + v)
+    Wo, Wv = redundant_gauge(o, v, mo, mv, 710 + v, 4.0)
+    P, G = lib.DeviceProblem.from_problem(p), lib.DeviceGauge(Wo, Wv)
+    th1, th2 = _theta(mo, mv, 910 + v, 0.05)
+    r1, r2, e = handle.residual_gauge(P, G, dev(th1), dev(th2), energy=True)
+    q1, q2 = gauge.residual(*_args(p), Wo, Wv, th1, th2)
+    assert _rel(host(r1), q1) < 1e-9 and _rel(host(r2), q2) < 1e-9
+    assert abs(e - gauge.energy(*_args(p), Wo, Wv, th1, th2)) < 1e-10 * max(1.0, abs(e))
+    Po, Pv = gauge.projector(Wo), gauge.projector(Wv)
+    pr2 = np.einsum("MA,NB,LC,SD,ABCD->MNLS", Po, Po, Pv, Pv, host(r2), optimize=True)
+    assert _rel(pr2, host(r2)) < 1e-10
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 2e-4), ("bf16", 5e-2)])
+def test_redundant_gauge_jvp_matches_the_oracle(handle, lib, prec, tol):
+    o, v, mo, mv, naux = 4, 23, 6, 31, 30
+    p = make_general(o, v, naux, 620)
+    Wo, Wv = redundant_gauge(o, v, mo, mv, 720, 4.0)
+    P, G = lib.DeviceProblem.from_problem(p), lib.DeviceGauge(Wo, Wv)
+    th1, th2 = _theta(mo, mv, 920, 0.05)
+    v1, v2 = _theta(mo, mv, 921, 1.0)
+    y1, y2 = handle.jvp_gauge(P, G, dev(th1), dev(th2), dev(v1), dev(v2), prec=prec)
+    j1, j2 = gauge.jvp_complex_step(*_args(p), Wo, Wv, th1, th2, v1, v2)
+    scale = max(np.abs(j1).max(), np.abs(j2).max())
+    assert np.abs(host(y1) - j1).max() < tol * scale and np.abs(host(y2) - j2).max() < tol * scale
+
+
+def _in_range(Wo, Wv, th2):
+    Po, Pv = gauge.projector(Wo), gauge.projector(Wv)
+    return np.einsum("MA,NB,LC,SD,ABCD->MNLS", Po, Po, Pv, Pv, th2, optimize=True)
+
+
+def test_redundant_gauge_pnk_matches_the_oracle(handle, lib):
+    """PNK in a redundant gauge (m_o = 6 for o = 4, m_v = 24 for v = 16,
+    cond 4): the device takes the oracle's Newton steps (the oracle runs
+    GMRES on the singular gauge A_F, the device the orbital inner solve
+    between the transforms: the same map on the range) to the same root,
+    which lies in the range and is the transformed orbital root."""
+    p = make_problem(4, 16, 48, 1001, gauge="haar")
+    Wo, Wv = redundant_gauge(4, 16, 6, 24, 2012, 4.0)
+    P, G = lib.DeviceProblem.from_problem(p), lib.DeviceGauge(Wo, Wv)
+    th1, th2, info = handle.solve_pnk_gauge(P, G, tol_inf=1e-10)
+    a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-10, gauge=(Wo, Wv))
+    assert info["status"] == "CC_OK" and ia.converged
+    assert info["newton_iters"] == ia.newton_iters
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-9
+    assert np.abs(host(th2) - a2).max() < 1e-8 and np.abs(host(th1) - a1).max() < 1e-8
+    h2 = host(th2)
+    assert np.abs(_in_range(Wo, Wv, h2) - h2).max() < 1e-10 * max(1.0, np.abs(h2).max())
+    b1, b2, ib = solvers.solve_pnk(*_args(p), tol=1e-11)
+    c1, c2 = gauge.forward(Wo, Wv, b1, b2)
+    assert np.abs(h2 - c2).max() < 1e-8 and abs(info["e_corr"] - ib.e_corr) < 1e-9
+
+
+def test_redundant_gauge_fp_diis_and_nk_match_the_oracle(handle, lib):
+    """FP+DIIS (the gauge's diagonal denominators) and NK in a redundant
+    gauge against the oracle's same iterations: same root and energy."""
+    p = make_problem(3, 7, 14, 97, gauge="haar")
+    Wo, Wv = redundant_gauge(3, 7, 4, 10, 2013, 3.0)
+    P, G = lib.DeviceProblem.from_problem(p), lib.DeviceGauge(Wo, Wv)
+    th1, th2, info = handle.solve_fp_diis_gauge(P, G, tol_inf=1e-9, max_iter=300)
+    a1, a2, ia = solvers.solve_fp_diis(*_args(p), tol=1e-9, max_iter=300, gauge=(Wo, Wv))
+    assert info["status"] == "CC_OK" and ia.converged
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-8
+    assert abs(info["newton_iters"] - ia.newton_iters) <= 3
+    # the Jacobi steps leave the range; what is unique is the projection
+    assert np.abs(_in_range(Wo, Wv, host(th2)) - _in_range(Wo, Wv, a2)).max() < 1e-7
+    th1, th2, info = handle.solve_pnk_gauge(P, G, tol_inf=1e-10, protocol="nk", max_newton=200)
+    a1, a2, ia = solvers.solve_pnk(*_args(p), tol=1e-10, gauge=(Wo, Wv), precond=False, max_newton=200)
+    assert info["status"] == "CC_OK" and ia.converged
+    assert info["newton_iters"] == ia.newton_iters
+    assert abs(info["e_corr"] - ia.e_corr) < 1e-9
+    assert np.abs(host(th2) - a2).max() < 1e-8
+
+
+def test_redundant_then_square_gauge_and_orbital_solves_on_one_handle(handle, lib):
+    """The solver's outer vectors grow for the redundant gauge and keep
+    serving the square gauge and the orbital basis afterwards."""
+    p = make_problem(3, 9, 20, 1105, gauge="haar")
+    P = lib.DeviceProblem.from_problem(p)
+    t1, t2, i0 = handle.solve_pnk(P, tol_inf=1e-10)
+    Wr = redundant_gauge(3, 9, 5, 14, 2014, 3.0)
+    _, r2, ir = handle.solve_pnk_gauge(P, lib.DeviceGauge(*Wr), tol_inf=1e-10)
+    Ws = nonorthogonal_gauge(3, 9, 2015, 3.0)
+    _, s2, is_ = handle.solve_pnk_gauge(P, lib.DeviceGauge(*Ws), tol_inf=1e-10)
+    u1, u2, i1 = handle.solve_pnk(P, tol_inf=1e-10)
+    assert all(i["status"] == "CC_OK" for i in (i0, ir, is_, i1))
+    e = i0["e_corr"]
+    assert max(abs(ir["e_corr"] - e), abs(is_["e_corr"] - e), abs(i1["e_corr"] - e)) < 1e-9
+    assert np.array_equal(host(u2), host(t2))
+    assert np.abs(host(r2) - gauge.forward(*Wr, host(t1), host(t2))[1]).max() < 1e-8
+    assert np.abs(host(s2) - gauge.forward(*Ws, host(t1), host(t2))[1]).max() < 1e-8
+
+
+def test_rank_deficient_or_short_gauges_are_rejected(handle, lib):
+    p = make_problem(3, 7, 14, 1106)
+    P = lib.DeviceProblem.from_problem(p)
+    Wo, Wv = redundant_gauge(3, 7, 4, 10, 2016, 3.0)
+    Wd = Wv.copy()
+    Wd[3] = 2.0 * Wd[1] - Wd[0]  # rows dependent: rank 6 < 7
+    G = lib.DeviceGauge(Wo, Wd)
+    t1, t2 = G.zeros_theta()
+    with pytest.raises(lib.CCError, match="full row rank"):
+        handle.residual_gauge(P, G, t1, t2)
+    G = lib.DeviceGauge(Wo[:, :2], Wv)  # 2 functions for 3 occupied orbitals
+    t1, t2 = G.zeros_theta()
+    with pytest.raises(lib.CCError, match="at least as many"):
+        handle.residual_gauge(P, G, t1, t2)
