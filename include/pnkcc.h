@@ -21,7 +21,9 @@
  * - Indices: i,j,k,l occupied (0..nocc-1), a,b,c,d virtual (0..nvir-1),
  *   n = nocc + nvir, P auxiliary (0..naux-1).
  * - Amplitudes and residuals: t1[i][a] (nocc*nvir) and t2[i][j][a][b]
- *   (nocc^2*nvir^2) with t2[i][j][a][b] == t2[j][i][b][a]. Residual
+ *   (nocc^2*nvir^2) with t2[i][j][a][b] == t2[j][i][b][a] (a precondition
+ *   of every entry point, not checked: the particle-particle ladder skips
+ *   what vanishes under it). Residual
  *   components are the projections onto a+_{a,alpha} a_{i,alpha}|Phi_0> and
  *   a+_{a,alpha} a_{i,alpha} a+_{b,beta} a_{j,beta}|Phi_0> of
  *   e^{-T} H e^{T}|Phi_0>, with T = sum t1 E_ai + 1/2 sum t2 E_ai E_bj.

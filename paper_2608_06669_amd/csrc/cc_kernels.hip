@@ -148,6 +148,13 @@ __device__ inline int64_t upair(int x, int y, int n) {  // x <= y
 __device__ inline int64_t spair(int x, int y, int n) {  // x < y
   return (int64_t)x * (n - 1) - (int64_t)x * (x - 1) / 2 + (y - x - 1);
 }
+// Occupied pairs of the ladder, i <= j: the n(n-1)/2 pairs i < j first (in
+// spair order), then the n diagonal pairs. The antisymmetric ladder
+// vanishes on i = j for pair-symmetric t2, so its product runs over the
+// first n(n-1)/2 rows only.
+__device__ inline int64_t opair(int i, int j, int n) {  // i <= j
+  return i < j ? spair(i, j, n) : (int64_t)n * (n - 1) / 2 + i;
+}
 
 __global__ void ppl_pack_w_kernel(int v, int a0, int na, const double* __restrict__ Wblk,
                                   const int* __restrict__ pa, const int* __restrict__ pb,
@@ -179,18 +186,23 @@ __global__ void ppl_pack_t_kernel(int o, int v, const double* __restrict__ t2, c
                                   const int* __restrict__ pb, const int* __restrict__ ma,
                                   const int* __restrict__ mb, double* __restrict__ Tp, double* __restrict__ Tm) {
   const int64_t P2 = (int64_t)v * (v + 1) / 2, P2m = (int64_t)v * (v - 1) / 2;
-  const int64_t O2 = (int64_t)o * (o + 1) / 2;
+  const int64_t O2 = (int64_t)o * (o + 1) / 2, O2m = (int64_t)o * (o - 1) / 2;
   const int64_t vv = (int64_t)v * v;
-  const int64_t np = O2 * P2, nm = O2 * P2m;
+  const int64_t np = O2 * P2, nm = O2m * P2m;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np + nm; e += (int64_t)gridDim.x * blockDim.x) {
     const bool plus = e < np;
     const int64_t f = plus ? e : e - np;
     const int64_t width = plus ? P2 : P2m;
     const int64_t ij = f / width, q = f % width;
-    // occupied pair (i <= j) from its packed index
-    int i = 0;
-    while (upair(i + 1, i + 1, o) <= ij && i + 1 < o) ++i;
-    const int j = i + (int)(ij - upair(i, i, o));
+    // occupied pair (i <= j) from its index (opair order)
+    int i, j;
+    if (ij < O2m) {
+      i = 0;
+      while (i + 2 < o && spair(i + 1, i + 2, o) <= ij) ++i;
+      j = i + 1 + (int)(ij - spair(i, i + 1, o));
+    } else {
+      i = j = (int)(ij - O2m);
+    }
     const double* t = t2 + ((int64_t)i * o + j) * vv;
     if (plus) {
       const int c = pa[q], d = pb[q];
@@ -216,13 +228,15 @@ __global__ void ppl_unpack_kernel(int o, int v, const double* __restrict__ Rp, c
       const int t = i; i = j; j = t;
       const int u = a; a = b; b = u;
     }
-    const int64_t ij = upair(i, j, o);
+    const int64_t ij = opair(i, j, o);
+    const bool offd = i < j;  // the antisymmetric part has rows i < j only
     double x;
     if (a <= b) {
       x = Rp[ij * P2 + upair(a, b, v)];
-      if (a < b) x += Rm[ij * P2m + spair(a, b, v)];
+      if (a < b && offd) x += Rm[ij * P2m + spair(a, b, v)];
     } else {
-      x = Rp[ij * P2 + upair(b, a, v)] - Rm[ij * P2m + spair(b, a, v)];
+      x = Rp[ij * P2 + upair(b, a, v)];
+      if (offd) x -= Rm[ij * P2m + spair(b, a, v)];
     }
     R[e] += x;
   }

@@ -143,14 +143,16 @@ struct Sizes {
   }
 };
 
-// Split-K scratch. Products are split only when they have fewer than 256
-// output tiles; the chunk count is also capped by this size (splits * M * N
-// * batch must fit). 16 times the largest o^2 v^2-class tensor, at most 8 M
-// elements (64 MB): room for the four chunks of the o v x o v products at
-// o = 10, v = 90 and the twelve of their 300 x 900 x 900 ones.
+// Split-K scratch. Products with few output tiles, or with a long
+// contraction, split it; the chunk count is also capped by this size
+// (splits * M * N * batch must fit). 16 times the largest o^2 v^2-class
+// tensor, at most 16 M elements (128 MB): room for the four chunks of the
+// o v x o v products at o = 10, v = 90, the twelve of their 300 x 900 x 900
+// ones, and the three to seven chunks of the ladder products at o = 20,
+// v = 180.
 int64_t splitk_elems(const Sizes& z) {
   const int64_t big = std::max<int64_t>({z.o * z.o * z.v * z.v, z.ov * z.ov, (int64_t)z.o * z.o * z.o * z.o});
-  return std::min<int64_t>(std::max<int64_t>(16 * big, 1 << 16), 8 * 1024 * 1024);
+  return std::min<int64_t>(std::max<int64_t>(16 * big, 1 << 16), 16 * 1024 * 1024);
 }
 
 // Rounded copies of FP64 operands for the FP32/BF16 products of J v: room
@@ -608,14 +610,15 @@ void Engine::run(Mode m) {
     // S and A are symmetric matrices: read them along the contiguous index
     // the compute type stages best (n for FP64/FP32, k for BF16)
     const bool kc = mode_ == Mode::Tangent && jprec_ == Prec::BF16;
-    const int P2 = (int)p2_, P2m = (int)p2m_, O2 = (int)o2_;
+    const int P2 = (int)p2_, P2m = (int)p2m_, O2 = (int)o2_, O2m = o_ * (o_ - 1) / 2;
     // row length of the copy the product reads (padded in FP32 / BF16)
     const bool t32 = mode_ == Mode::Tangent && jprec_ == Prec::F32;
     const int64_t ls = kc && S.lp16 ? ld16_ : (t32 && S.lp32 ? ld32_ : p2_);
     const int64_t lm = kc && Am.lp16 ? ld16m_ : (t32 && Am.lp32 ? ld32m_ : p2m_);
     if (timers_) timers_->begin(kTimerPPL, s_);
     mm(gd(O2, P2, P2, p2_, 1, kc ? 1 : ls, kc ? ls : 1, p2_, 1), Tp, S, Rp);
-    if (P2m > 0) mm(gd(O2, P2m, P2m, p2m_, 1, kc ? 1 : lm, kc ? lm : 1, p2m_, 1), Tm, Am, Rm);
+    // the antisymmetric pairs over i < j only (t_ii^cd = t_ii^dc)
+    if (P2m > 0 && O2m > 0) mm(gd(O2m, P2m, P2m, p2m_, 1, kc ? 1 : lm, kc ? lm : 1, p2m_, 1), Tm, Am, Rm);
     if (timers_) timers_->end(kTimerPPL, s_);
   }
   lin_ppl_unpack(Rp, Rm, R2);

@@ -59,6 +59,21 @@ struct KArgs {
   double alpha, beta;
 };
 
+// LDS row padding of an FP64 panel stored [k][rows + pad]. The 4x4x4 f64
+// reads take, per k, 4 consecutive values of A or 16 of B; half a wave (two
+// k rows) is served per LDS cycle, so the two rows must fall on disjoint
+// banks (64 banks of 4 bytes): a row stride of 9 modulo 32 doubles offsets
+// them by 18 banks, 16 modulo 32 by 32 banks (the 16-value B reads need
+// that). A panel loaded along k (KC) is written one value per lane at a
+// stride of two rows, which a 16-modulo-32 stride turns into an 8-way
+// conflict, so those panels take 9. Other compute types keep kPad.
+template <class Mma, int ROWS, bool KC, bool IS_B>
+constexpr int lds_pad() {
+  if constexpr (sizeof(typename Mma::L) != 8) return kPad;
+  const int want = (IS_B && !KC) ? 16 : 9;
+  return ((want - ROWS) % 32 + 32) % 32;
+}
+
 template <class Mma, typename TA, typename TB, typename TC, int BM, int BN, int BK, int WGM, bool A_KC, bool B_KC>
 __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   using L = typename Mma::L;
@@ -68,8 +83,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
   constexpr int TMI = WTM / Mma::TM, TNI = WTN / Mma::TN;
   static_assert(WTM % Mma::TM == 0 && WTN % Mma::TN == 0, "wave tile must split into instruction tiles");
   static_assert(BK % Mma::KSTEP == 0, "BK must be a multiple of the MFMA depth");
-  constexpr int ALDS = lds_elems<Mma, BM, BK>();
-  constexpr int BLDS = lds_elems<Mma, BN, BK>();
+  constexpr int PA = lds_pad<Mma, BM, A_KC, false>();
+  constexpr int PB = lds_pad<Mma, BN, B_KC, true>();
+  constexpr int ALDS = lds_elems<Mma, BM, BK, PA>();
+  constexpr int BLDS = lds_elems<Mma, BN, BK, PB>();
   __shared__ __attribute__((aligned(16))) L As[2][ALDS];
   __shared__ __attribute__((aligned(16))) L Bs[2][BLDS];
 
@@ -116,8 +133,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
 #pragma unroll
     for (int j = 0; j < TNI; ++j) acc[i][j] = Acc{};
 
-  Panel<Mma, TA, BM, BK, A_KC> pa;
-  Panel<Mma, TB, BN, BK, B_KC> pb;
+  Panel<Mma, TA, BM, BK, A_KC, PA> pa;
+  Panel<Mma, TB, BN, BK, B_KC, PB> pb;
   const bool avec = p.a_vec != 0, bvec = p.b_vec != 0;
   const int64_t a_row = p.a_m, a_kk = p.a_k, b_row = p.b_n, b_kk = p.b_k;
 
@@ -166,9 +183,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
         const int kk = ks + (lane >> 4);
         double af[TMI], bfr[TNI];
 #pragma unroll
-        for (int i = 0; i < TMI; ++i) af[i] = Ac[kk * (BM + kPad) + wm * WTM + i * 4 + (lane & 3)];
+        for (int i = 0; i < TMI; ++i) af[i] = Ac[kk * (BM + PA) + wm * WTM + i * 4 + (lane & 3)];
 #pragma unroll
-        for (int j = 0; j < TNI; ++j) bfr[j] = Bc[kk * (BN + kPad) + wn * WTN + j * 16 + (lane & 15)];
+        for (int j = 0; j < TNI; ++j) bfr[j] = Bc[kk * (BN + PB) + wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
         for (int i = 0; i < TMI; ++i)
 #pragma unroll
@@ -178,9 +195,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(KArgs p) {
         const int kk = ks + (lane >> 4);
         L af[TMI], bfr[TNI];
 #pragma unroll
-        for (int i = 0; i < TMI; ++i) af[i] = Ac[kk * (BM + kPad) + wm * WTM + i * 16 + (lane & 15)];
+        for (int i = 0; i < TMI; ++i) af[i] = Ac[kk * (BM + PA) + wm * WTM + i * 16 + (lane & 15)];
 #pragma unroll
-        for (int j = 0; j < TNI; ++j) bfr[j] = Bc[kk * (BN + kPad) + wn * WTN + j * 16 + (lane & 15)];
+        for (int j = 0; j < TNI; ++j) bfr[j] = Bc[kk * (BN + PB) + wn * WTN + j * 16 + (lane & 15)];
 #pragma unroll
         for (int i = 0; i < TMI; ++i)
 #pragma unroll
@@ -412,11 +429,31 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   // CU, each walking thousands of k steps) are split too: the T1 part of
   // the ladder at o=20/v=180 (400 x 3600 x 32400, 399 tiles) ran at 22
   // TFLOP/s unsplit.
-  if (d.ws && d.K >= 256 && (tiles < 256 || (tiles < 512 && d.K >= 8192))) {
-    const bool thin = d.M <= 64 && d.K >= 1024;
+  const bool thin = d.M <= 64 && d.K >= 1024;
+  const int64_t ws_fit = d.ws ? d.ws_elems / std::max<int64_t>(1, nb * d.M * d.N) : 0;
+  constexpr bool f64 = sizeof(typename Mma::L) == 8;
+  if (f64 && d.ws && !thin && d.K >= 8192 && tiles >= 256 && tiles < 2048) {
+    // Long FP64 contractions with a few hundred tiles or more: split into up
+    // to 8 chunks so that the work items (tiles x chunks) reach about 2048 of
+    // 64 x 64 tiles' worth (8 per CU, enough resident workgroups to hide
+    // latency) and fill the 256 CUs in whole rounds. At o = 20, v = 180 this took the antisymmetric ladder
+    // (756 tiles) from 3.0 to 2.5 ms with 3 chunks and the symmetric one
+    // (384 tiles of 72 x 128) to 2.7 ms with 4 (3 chunks, 4.5 rounds: 3.15).
+    const double target = 2048.0 * 4096.0 / (BM * BN);
+    double best = -1.0;
+    for (int64_t sp = 1; sp <= 8 && sp <= d.K / (2 * BK) && sp <= ws_fit; ++sp) {
+      const int64_t items = tiles * sp;
+      const double fill = std::min(1.0, (double)items / target);
+      const double rounds = (double)items / (double)(ceil_div(items, 256) * 256);
+      if (fill * rounds > best + 1e-9) {
+        best = fill * rounds;
+        splits = (int)sp;
+      }
+    }
+  } else if (d.ws && d.K >= 256 && (tiles < 256 || (tiles < 512 && d.K >= 8192))) {
     int64_t want = ceil_div(thin ? 512 : 900, tiles);
     want = std::min<int64_t>(want, d.K / (2 * BK));
-    want = std::min<int64_t>(want, d.ws_elems / std::max<int64_t>(1, nb * d.M * d.N));
+    want = std::min<int64_t>(want, ws_fit);
     want = std::min<int64_t>(want, 256);
     if (want >= 2) splits = (int)want;
   }
@@ -447,16 +484,29 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
 
 // Tile choice. FP64: 64 x 64 with 16-deep panels (a sweep over 32/64/96/128
 // x 64 tiles and 16/32-deep panels on MI355X put it at or within 3 % of the
-// best for square products from 900 to 3600 and for the ladder shapes);
-// thin products (at most 64 rows) with a long contraction stream their wide
-// operand from HBM and take 32-deep panels (about 20 % faster there).
+// best for square products from 900 to 3600); row counts that 72-row tiles
+// fit much better take 72 x 128; thin products (at most 64 rows) with a
+// long contraction stream their wide operand from HBM and take 32-deep
+// panels (about 20 % faster there).
 // FP32/BF16: 128 x 128. Small products: 64 x 64 (split-K fills the GPU).
 template <class Mma, typename TA, typename TB, typename TC, int BK>
 void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, void* C,
                   hipStream_t s) {
   const int64_t nb = (int64_t)d.nb0 * d.nb1;
   if constexpr (sizeof(typename Mma::L) == 8) {
-    if (d.M <= 64 && d.K >= 1024) launch_cfg<Mma, TA, TB, TC, 64, 64, 32, 2>(d, A, B, A2, B2, C, s);
+    // row counts that 72- or 80-row tiles cover with at least 10 % less
+    // padding than 64-row ones (at o = 20: the ladder's 210 pair rows, 216
+    // against 256; the 400 pair rows of the T1 part of the ladder, 400
+    // against 448), with a long contraction: 72 x 128 or 80 x 128 with
+    // 8-deep panels (9 % and 16 % faster than 64 x 64 there)
+    const int64_t r64 = ceil_div(d.M, 64) * 64, r72 = ceil_div(d.M, 72) * 72, r80 = ceil_div(d.M, 80) * 80;
+    // (at least 128 such tiles: fewer go to 64 x 64 tiles and many chunks)
+    const int64_t n128 = ceil_div(d.N, 128) * nb;
+    if (d.K >= 1024 && r80 < r72 && 10 * r80 <= 9 * r64 && (r80 / 80) * n128 >= 128)
+      launch_cfg<Mma, TA, TB, TC, 80, 128, 8, 2>(d, A, B, A2, B2, C, s);
+    else if (d.K >= 1024 && 10 * r72 <= 9 * r64 && (r72 / 72) * n128 >= 128)
+      launch_cfg<Mma, TA, TB, TC, 72, 128, 8, 2>(d, A, B, A2, B2, C, s);
+    else if (d.M <= 64 && d.K >= 1024) launch_cfg<Mma, TA, TB, TC, 64, 64, 32, 2>(d, A, B, A2, B2, C, s);
     else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
     return;
   }

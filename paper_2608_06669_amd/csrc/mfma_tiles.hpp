@@ -65,17 +65,18 @@ struct MmaBF16 {
 template <class Acc> __device__ inline double acc_get(const Acc& a, int r) { return (double)a[r]; }
 template <> __device__ inline double acc_get<double>(const double& a, int) { return a; }
 
-constexpr int kPad = 1;   // [k][rows + kPad]
+constexpr int kPad = 1;   // [k][rows + pad], default pad
 constexpr int kPadK = 8;  // [rows][k + kPadK]
 
-template <class Mma, int ROWS, int BK>
+template <class Mma, int ROWS, int BK, int PAD = kPad>
 constexpr int lds_elems() {
-  return Mma::KCONTIG_LDS ? ROWS * (BK + kPadK) : BK * (ROWS + kPad);
+  return Mma::KCONTIG_LDS ? ROWS * (BK + kPadK) : BK * (ROWS + PAD);
 }
 
 // Loads a ROWS x BK panel (ROWS = BM for A, BN for B) into registers and
-// writes it to one LDS buffer. KC: the operand is contiguous along k.
-template <class Mma, typename T, int ROWS, int BK, bool KC>
+// writes it to one LDS buffer. KC: the operand is contiguous along k. PAD:
+// row padding of the [k][rows + PAD] layout.
+template <class Mma, typename T, int ROWS, int BK, bool KC, int PAD = kPad>
 struct Panel {
   using L = typename Mma::L;
   static constexpr int V = 16 / (int)sizeof(T);
@@ -163,7 +164,7 @@ struct Panel {
         const int kx = KC ? kk + u : kk;
         const L x = to_lds<T, L>(r[e * V + u]);
         if constexpr (Mma::KCONTIG_LDS) lds[rr * (BK + kPadK) + kx] = x;
-        else lds[kx * (ROWS + kPad) + rr] = x;
+        else lds[kx * (ROWS + PAD) + rr] = x;
       }
     }
   }
