@@ -702,8 +702,10 @@ def bench_gauge(args):
 
 
 def bench_residual(args):
-    """Residual and FP64 J v evaluations alone (recorded graphs replayed) on
-    c2_haar and c4_mixed at seeded amplitudes, --steps of each, plus one
+    """Residual and J v (FP64, FP32, BF16) evaluations alone (recorded graphs
+    replayed) on c2_haar and c4_mixed at seeded amplitudes, --steps of each
+    (a J v call also evaluates the residual at its point; the J v times
+    subtract the residual's), plus one
     1024^3 FP64 product through cc_diag_gemm (2^31 flops). A torch
     elementwise kernel runs before every evaluation and after the last, so
     that a counter run (rocprofv3 --pmc) can attribute the dispatches
@@ -717,7 +719,7 @@ def bench_residual(args):
     pk.load()
     h = pk.Handle(0)
     mark = torch.zeros(1, dtype=torch.float64, device="cuda")
-    out = {"workload": "residual and FP64 J v alone (c2_haar, c4_mixed)", "steps": args.steps, "configs": []}
+    out = {"workload": "residual and J v alone (c2_haar, c4_mixed)", "steps": args.steps, "configs": []}
     A = torch.randn(1024, 1024, dtype=torch.float64, device="cuda")
     B = torch.randn(1024, 1024, dtype=torch.float64, device="cuda")
     C = torch.zeros(1024, 1024, dtype=torch.float64, device="cuda")
@@ -763,6 +765,19 @@ def bench_residual(args):
         rec = {"config": cfg, "nocc": o, "nvir": v, "naux": naux, "residual_ms": res_ms,
                "residual_tflops_nominal": F_R / (res_ms * 1e-3) / 1e12, "nominal_residual_flops": F_R,
                "residual_plus_jvp_ms": rj_ms, "jvp_ms": rj_ms - res_ms}
+        # the low-precision products of the Krylov loop, each after a
+        # marker: a residual (FP64) then J v in that precision
+        for prec in ("fp32", "bf16"):
+            for _ in range(3):
+                h.jvp(P, t1, t2, q1, q2, prec=prec, out=y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                mark.add_(1.0)
+                h.jvp(P, t1, t2, q1, q2, prec=prec, out=y)
+            mark.add_(1.0)
+            torch.cuda.synchronize()
+            rec[f"jvp_{prec}_ms"] = 1000.0 * (time.perf_counter() - t0) / max(args.steps, 1) - res_ms
         out["configs"].append(rec)
         print(f"{cfg}: {rec}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
