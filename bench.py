@@ -32,6 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2_haar"      # the FP64 solve line (--workload c2_haar)
 HEADLINE = "c4_mixed"     # the default line
@@ -217,13 +218,6 @@ def bench_c2(args):
     h.close()
 
 
-def residual_algorithmic_flops(o, v, naux):
-    """Flops of one residual as evaluated here: the nominal count with the
-    particle-particle ladder at o^2 v^4 (its symmetric / antisymmetric pair
-    form contracts v(v+1)/2 and v(v-1)/2 pair indices instead of v^2)."""
-    return nominal_residual_flops(o, v, naux) - o * o * v ** 4
-
-
 def occ_packed_bytes(o, v):
     """Algorithmic HBM bytes of one occupied A_F launch of the packed inner
     step (three-launch form): v_k, the virtual part of p and v_{k-1} read,
@@ -335,7 +329,9 @@ def bench_headline(args):
         print(f"FP64 reference solve: {ref['seconds']:.1f} s", file=sys.stderr, flush=True)
 
     F_R = nominal_residual_flops(o, v, naux)
-    F_alg = residual_algorithmic_flops(o, v, naux)
+    # algorithmic flops: 2 M N K of every contraction as the library runs it
+    # (symmetry-adapted ladder; tiles' padding not counted), from the library
+    F_alg, F_jv = h.contraction_flops(probs[0], prec)
     res_ms = ms_res / max(n_res, 1)
     roof = None
     if n_res:
@@ -345,6 +341,15 @@ def bench_headline(args):
                 "kernel": "FP64 residual evaluation (recorded graph of matrix-core products: ladder in the "
                           "symmetric/antisymmetric pair basis, ring, hole-hole, Fock and dressing terms)",
                 "launches_timed": n_res, "avg_ms": res_ms, "flops_per_launch": F_alg}
+    roof_jvp = None
+    if n_jvp and prec == "bf16":
+        jv_ms = ms_jvp / n_jvp
+        tj = F_jv / (jv_ms * 1e-3) / 1e12
+        roof_jvp = {"bound": "mfma", "achieved": tj, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": tj / BF16_PEAK_TFLOPS, "traffic": None,
+                    "kernel": "BF16 J v product (recorded graph: the tangent contractions in BF16 with float "
+                              "accumulation, their FP64 operands rounded once per product)",
+                    "launches_timed": n_jvp, "avg_ms": jv_ms, "flops_per_launch": F_jv}
     roof_inner = None
     if n_afm:
         af_ms = ms_afm / n_afm
@@ -386,6 +391,8 @@ def bench_headline(args):
         "counts_per_solve": {k: infos[-1][k] for k in ("newton_iters", "n_residual", "n_jvp", "n_afmv")},
         "residual_tflops_fp64_nominal": F_R / (res_ms * 1e-3) / 1e12 if n_res else None,
         "residual_tflops_fp64_algorithmic": F_alg / (res_ms * 1e-3) / 1e12 if n_res else None,
+        "flops_per_residual": {"nominal": F_R, "algorithmic": F_alg},
+        "flops_per_jvp_algorithmic": F_jv,
         "residual_ms": res_ms if n_res else None,
         "jvp_ms": ms_jvp / n_jvp if n_jvp else None,
         "precond_solve_ms": ms_pre / n_pre if n_pre else None,
@@ -393,6 +400,7 @@ def bench_headline(args):
                        "precond_solve": ms_pre / (1000 * elapsed)},
         "roofline": roof,
         "roofline_inner": roof_inner,
+        "roofline_jvp": roof_jvp,
     }
     if not args.no_cpu_baseline:
         cb, check = cpu_baseline_sample(p, infos[-1], t1.cpu().numpy(), t2.cpu().numpy(), e)
@@ -525,7 +533,7 @@ def bench_serving(args):
 
 
 def bench_inner(args):
-    """Inner A_F solves alone (the C2 shapes): `steps` solves of A_F x = b
+    """Inner A_F solves alone (--config, default the C2 shapes): `steps` solves of A_F x = b
     with a seeded pair-symmetric b; used for kernel counters. Each solve
     ends with one copy of the N-vector (a copy kernel of known size)."""
     import torch
@@ -534,12 +542,14 @@ def bench_inner(args):
     from gen import make_config, random_amplitudes
 
     pk.load()
-    p = make_config(WORKLOAD)
+    cfg = args.config or WORKLOAD
+    p = make_config(cfg)
     o, v = p.nocc, p.nvir
     h = pk.Handle(0)
     P = pk.DeviceProblem.from_problem(p)
     b1, b2 = (torch.as_tensor(a, device="cuda") for a in random_amplitudes(o, v, 77, scale=1.0))
-    out = {"workload": "inner A_F solves, o=10 v=90", "solves": args.steps, "n_vector": o * v + o * o * v * v}
+    out = {"workload": f"inner A_F solves, {cfg} (o={o} v={v})", "solves": args.steps,
+           "n_vector": o * v + o * o * v * v}
     # full layout (cc_precond_solve), then the packed pair layout the PNK
     # solver uses (cc_precond_solve_pairsym); --layout picks one of them
     layouts = [("full", False), ("pairsym", True)]
@@ -778,6 +788,13 @@ def bench_residual(args):
             mark.add_(1.0)
             torch.cuda.synchronize()
             rec[f"jvp_{prec}_ms"] = 1000.0 * (time.perf_counter() - t0) / max(args.steps, 1) - res_ms
+        # 2 M N K of every contraction as run (an eager evaluation after the
+        # last marker of this configuration)
+        fr, fj = h.contraction_flops(P, "fp64")
+        rec["flops_algorithmic"] = {"residual": fr, "jvp": fj}
+        rec["residual_tflops_algorithmic"] = fr / (res_ms * 1e-3) / 1e12
+        rec["jvp_fp64_tflops_algorithmic"] = fj / (rec["jvp_ms"] * 1e-3) / 1e12
+        rec["jvp_bf16_tflops_algorithmic"] = fj / (rec["jvp_bf16_ms"] * 1e-3) / 1e12
         out["configs"].append(rec)
         print(f"{cfg}: {rec}", file=sys.stderr, flush=True)
     print(json.dumps(out), flush=True)
@@ -802,6 +819,8 @@ def main():
                     help="tolerance of the inner solves of A_F^-1 J q in the Krylov loop (0: --inner-rtol)")
     ap.add_argument("--layout", default="both", choices=["both", "full", "pairsym"],
                     help="inner: which inner-solve layout to time")
+    ap.add_argument("--config", default=None, choices=["c2_haar", "c4_mixed"],
+                    help="inner: the workload whose shapes the inner solves take (default c2_haar)")
     ap.add_argument("--requests", type=int, default=40)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--stall-window", type=int, default=10, help="serving: stagnation stop window (0: off)")

@@ -396,6 +396,16 @@ void cc_server_destroy(cc_server* s);
 cc_status cc_diag_timing(cc_handle* h, int enable);
 cc_status cc_diag_timing_read(cc_handle* h, int slot, int* count, double* total_ms);
 
+/* Matrix-core flops of one residual evaluation (equations CC_ampl and
+ * CC_energy as implemented: T1-dressed terms, symmetry-adapted ladder) and
+ * of one J v product in precision prec, counted as 2 M N K per contraction
+ * at the contractions' own sizes (the tiles' padding is not counted): the
+ * algorithmic flop count of the roofline figures. Runs one eager residual
+ * and J v at t = 0 on the handle (problem device arrays as for
+ * cc_residual) and writes the two counts to the host doubles. Synchronises. */
+cc_status cc_diag_contraction_flops(cc_handle* h, const cc_problem* p, cc_precision prec, double* residual_flops,
+                                    double* jvp_flops, void* stream);
+
 /* Eigenvalues of an m x m real upper Hessenberg matrix H (host, row-major;
  * entries below the subdiagonal ignored) into re[m], im[m] (host), by the
  * shifted QR iteration the spectral-radius call uses (host code, no GPU).

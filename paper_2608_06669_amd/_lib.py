@@ -125,6 +125,7 @@ SIGNATURES = {
     "cc_server_destroy": (None, [P]),
     "cc_diag_timing": (I, [P, I]),
     "cc_diag_timing_read": (I, [P, I, ctypes.POINTER(I), ctypes.POINTER(D)]),
+    "cc_diag_contraction_flops": (I, [P, ctypes.POINTER(cc_problem), I, ctypes.POINTER(D), ctypes.POINTER(D), P]),
     "cc_diag_gemm": (I, [I, I, I, P, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64, ctypes.c_int64, P,
                          ctypes.c_int64, ctypes.c_int64, D, D, I, P]),
     "cc_diag_gemm_batched": (I, [I, I, I, I, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, P, ctypes.c_int64,

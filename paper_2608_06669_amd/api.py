@@ -257,6 +257,15 @@ class Handle:
     def timing(self, enable: bool = True):
         self._check(_lib().cc_diag_timing(self._h, 1 if enable else 0))
 
+    def contraction_flops(self, p: DeviceProblem, prec="fp64", stream=None):
+        """(residual, J v) matrix-core flops as implemented: 2 M N K per
+        contraction at its own sizes (cc_diag_contraction_flops)."""
+        rf, jf = ctypes.c_double(0.0), ctypes.c_double(0.0)
+        pr = L.PRECISIONS[prec] if isinstance(prec, str) else int(prec)
+        self._check(_lib().cc_diag_contraction_flops(self._h, ctypes.byref(p.struct), pr, ctypes.byref(rf),
+                                                     ctypes.byref(jf), _stream(stream)))
+        return rf.value, jf.value
+
     def timing_read(self, slot: int):
         """(launch count, total ms) of a timing slot: 0 ladder contraction,
         1 residual, 2 J v, 3 A_F product, 4 inner A_F solve."""

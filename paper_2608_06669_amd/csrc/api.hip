@@ -655,6 +655,35 @@ cc_status cc_diag_timing_read(cc_handle* h, int slot, int* count, double* total_
   PNK_API_END
 }
 
+cc_status cc_diag_contraction_flops(cc_handle* h, const cc_problem* p, cc_precision prec, double* residual_flops,
+                                    double* jvp_flops, void* stream) {
+  PNK_API_BEGIN(h)
+  hipStream_t s = (hipStream_t)stream;
+  PNK_REQUIRE(residual_flops && jvp_flops, "output pointers must not be NULL");
+  PNK_REQUIRE(prec == CC_FP64 || prec == CC_FP32 || prec == CC_BF16, "unknown precision");
+  H->ensure(p, lowp_for(prec), 1, 1, 0, s);
+  Engine& E = *H->eng;
+  const int64_t ov = (int64_t)E.o() * E.v();
+  // eager evaluations: a recorded graph's replay launches nothing the host
+  // could count
+  E.set_graphs(false);
+  try {
+    E.reset_contraction_flops();
+    E.residual(E.zeros(), E.zeros() + ov, H->xa, H->xa + ov, s);
+    *residual_flops = E.contraction_flops();
+    E.reset_contraction_flops();
+    E.jvp(E.zeros(), E.zeros() + ov, H->xb, H->xb + ov, (Prec)prec, s);
+    *jvp_flops = E.contraction_flops();
+  } catch (...) {
+    E.set_graphs(true);
+    throw;
+  }
+  E.set_graphs(true);
+  PNK_HIP(hipStreamSynchronize(s));
+  return CC_OK;
+  PNK_API_END
+}
+
 cc_status cc_diag_hessenberg_eigenvalues(int m, const double* H, double* re, double* im) {
   if (m < 1 || !H || !re || !im) return CC_ERR_ARG;
   return hessenberg_eigenvalues(H, m, re, im) ? CC_OK : CC_NOT_CONVERGED;

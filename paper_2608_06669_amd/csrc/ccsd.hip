@@ -367,11 +367,16 @@ void Engine::operand(const Ten& t, bool tangent, const void** p, Prec* prec) con
 
 // C = alpha A B + beta C, or its tangent dC = alpha (dA B + A dB) + beta dC
 void Engine::mm(const GemmDesc& d, const Ten& A, const Ten& B, const Ten& C) {
+  const double f = 2.0 * d.M * d.N * d.K * (double)d.nb0 * d.nb1;
   if (mode_ == Mode::Value) {
+    mm_flops_ += f;
     gemm64(with_ws(d), A.v, B.v, C.v, s_);
     return;
   }
   if (!C.var) return;
+  // the tangent of a product with one varying operand is one product, with
+  // two varying operands two
+  mm_flops_ += (A.var && B.var) ? 2.0 * f : f;
   PNK_REQUIRE(A.var || B.var, "internal: variable output of a constant product");
   const void *pa, *pb;
   Prec qa, qb;

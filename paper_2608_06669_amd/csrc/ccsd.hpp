@@ -122,6 +122,12 @@ class Engine {
   // the same buffers (default on).
   void set_graphs(bool on) { use_graphs_ = on; }
   Timers* timers() const { return timers_; }
+  // Matrix-core flops launched by the host side of the evaluations since
+  // the last reset: 2 M N K per product and batch entry at the products'
+  // own sizes (tiles' padding not counted). Graph replays launch nothing
+  // from the host, so count on an eager evaluation (set_graphs(false)).
+  double contraction_flops() const { return mm_flops_; }
+  void reset_contraction_flops() { mm_flops_ = 0.0; }
 
  private:
   struct Ten {
@@ -175,6 +181,7 @@ class Engine {
   double* partials_;
   double* zeros_;  // zero t-vector for the residual at t = 0
   Timers* timers_ = nullptr;
+  double mm_flops_ = 0.0;
   // recorded graphs of the residual (value) and J v (tangent, per precision)
   struct GraphSlot {
     hipGraphExec_t exec = nullptr;

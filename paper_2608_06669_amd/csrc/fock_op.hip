@@ -565,10 +565,45 @@ struct OccPackedArgs {
 
 __device__ inline int packed_pair(int i, int j, int o) { return i * o - i * (i - 1) / 2 + (j - i); }  // i <= j
 
+// Tile c (0 <= c < ntile (ntile + 1) / 2) of the upper tile triangle in
+// block order: the triangle is cut into blocks of S x S tiles (S t = 16
+// elements, one 128-byte line of doubles per row), taken row by row over
+// the upper block triangle, and the tiles of a block (ta <= tb within a
+// diagonal block) row by row. Consecutive tiles run on one XCD, so the
+// lines of x2 that neighbouring tiles and their mirrors share are fetched
+// into that XCD's L2 once.
+__device__ inline void block_order_tile(int c, int ntile, int S, int* ta, int* tb) {
+  const int nst = (ntile + S - 1) / S;
+  for (int sa = 0; sa < nst; ++sa) {
+    const int ra = min(S, ntile - sa * S);
+    for (int sb = sa; sb < nst; ++sb) {
+      const int rb = min(S, ntile - sb * S);
+      const int cnt = sa == sb ? ra * (ra + 1) / 2 : ra * rb;
+      if (c < cnt) {
+        if (sa == sb) {
+          int r = 0;
+          while (c >= ra - r) {
+            c -= ra - r;
+            ++r;
+          }
+          *ta = sa * S + r;
+          *tb = *ta + c;
+        } else {
+          *ta = sa * S + c / rb;
+          *tb = sb * S + c % rb;
+        }
+        return;
+      }
+      c -= cnt;
+    }
+  }
+  *ta = *tb = 0;  // c out of range (not reached)
+}
+
 // Dynamic LDS: xs[npair][ns] then fo[o][o]; ns = t^2 (diagonal tile) or
 // 2 t^2. The first dwg workgroups do the doubles: workgroup b takes the
-// unit c = (b % 8) (dwg / 8) + b / 8, i.e. tile c / psplit and the packed
-// pairs pr = c % psplit + psplit m. Workgroups are dispatched round-robin
+// unit c = (b % 8) (dwg / 8) + b / 8, i.e. tile c / psplit (in block order)
+// and the packed pairs pr = c % psplit + psplit m. Workgroups are dispatched round-robin
 // over the 8 XCDs, so the psplit workgroups of a tile run on one XCD and
 // its staged blocks are fetched into that L2 once. Units past
 // nchunks * psplit only write zero partial sums; the remaining workgroups
@@ -589,14 +624,10 @@ __global__ __launch_bounds__(256) void fock_occ_packed_kernel(OccPackedArgs p) {
 
   const int unit = (int)(blockIdx.x % 8) * (p.dwg / 8) + (int)(blockIdx.x / 8);
   if ((int)blockIdx.x < p.dwg && unit < p.nchunks * ps) {
-    // tile (ta, tb), ta <= tb, row by row over the upper triangle
-    int c = unit / ps, ta = 0;
+    // tile (ta, tb), ta <= tb, in block order
+    int ta, tb;
+    block_order_tile(unit / ps, p.ntile, 16 / p.t, &ta, &tb);
     const int part = unit % ps;
-    while (c >= p.ntile - ta) {
-      c -= p.ntile - ta;
-      ++ta;
-    }
-    const int tb = ta + c;
     const int a0 = ta * t, b0 = tb * t, tt = t * t;
     const bool diag = ta == tb;
     const int ns = diag ? tt : 2 * tt;

@@ -458,3 +458,27 @@ def test_fp_spectral_radius_matches_the_oracle(handle, lib, o, v, m, shift):
     top_o = np.sort(np.abs(ritz_o))[-3:]
     top = np.sort(np.abs(ritz))[-3:]
     assert np.allclose(top, top_o, rtol=1e-6, atol=1e-10)
+
+
+@pytest.mark.parametrize("o,v,naux", [(4, 16, 48), (6, 37, 50)])
+def test_contraction_flop_count(handle, lib, o, v, naux):
+    """cc_diag_contraction_flops (the roofline's algorithmic count) covers
+    the symmetry-adapted ladder and the ring products exactly once, stays
+    below the nominal count of the unreduced equations plus the T1 part of
+    the ladder (2 o^3 v^3), and counts the same tangent products in every
+    J v precision."""
+    p = make_general(o, v, naux, 700 + v)
+    P = lib.DeviceProblem.from_problem(p)
+    fr, fj = handle.contraction_flops(P, "fp64")
+    _, fj16 = handle.contraction_flops(P, "bf16")
+    _, fj32 = handle.contraction_flops(P, "fp32")
+    assert fj == fj16 == fj32
+    p2, p2m = v * (v + 1) // 2, v * (v - 1) // 2
+    ladder = 2 * (o * (o + 1) // 2) * p2 * p2 + 2 * (o * (o - 1) // 2) * p2m * p2m
+    ring = 6 * 2 * (o * v) ** 3
+    nominal = (2 * o * o * v ** 4 + 12 * o ** 3 * v ** 3 + 4 * o ** 4 * v * v + 8 * naux * o * o * v * v
+               + 4 * o * o * v ** 3 + 4 * o ** 3 * v * v)
+    assert ladder + ring < fr < nominal + 2 * o ** 3 * v ** 3
+    # the tangent of every product with a varying operand: at least the
+    # residual's amplitude-dependent products once
+    assert fj > ladder + ring
