@@ -436,19 +436,30 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   // CU, each walking thousands of k steps) are split too: the T1 part of
   // the ladder at o=20/v=180 (400 x 3600 x 32400, 399 tiles) ran at 22
   // TFLOP/s unsplit.
+  // gridDim.y * gridDim.z covers the batch; y is a multiple of nb0, and z
+  // also carries the chunks
+  int64_t gy = d.nb0, gz = d.nb1;
+  while (gy * 2 <= 65535 && gz % 2 == 0) { gy *= 2; gz /= 2; }
   const bool thin = d.M <= 64 && d.K >= 1024;
-  const int64_t ws_fit = d.ws ? d.ws_elems / std::max<int64_t>(1, nb * d.M * d.N) : 0;
+  const int64_t ws_fit =
+      d.ws ? std::min<int64_t>(d.ws_elems / std::max<int64_t>(1, nb * d.M * d.N), 65535 / gz) : 0;
   constexpr bool f64 = sizeof(typename Mma::L) == 8;
-  if (f64 && d.ws && !thin && d.K >= 8192 && tiles >= 256 && tiles < 2048) {
-    // Long FP64 contractions with a few hundred tiles or more: split into up
-    // to 8 chunks so that the work items (tiles x chunks) reach about 2048 of
-    // 64 x 64 tiles' worth (8 per CU, enough resident workgroups to hide
-    // latency) and fill the 256 CUs in whole rounds. At o = 20, v = 180 this took the antisymmetric ladder
-    // (756 tiles) from 3.0 to 2.5 ms with 3 chunks and the symmetric one
-    // (384 tiles of 72 x 128) to 2.7 ms with 4 (3 chunks, 4.5 rounds: 3.15).
+  if (f64 && d.ws && ((d.K >= 8192 && tiles < 2048) || (d.K >= 2048 && tiles >= 256 && tiles < 1024))) {
+    // Long FP64 contractions: split so that the work items (tiles x
+    // chunks) reach about 2048 of 64 x 64 tiles' worth (8 per CU, enough
+    // resident workgroups to hide latency) and fill the 256 CUs in whole
+    // rounds; up to 8 chunks for a few hundred tiles or more, up to 1024 for
+    // a handful (thin products streaming a long operand). Contractions of
+    // 2048 or more with a few hundred tiles (2 or 3 per CU, unevenly) are
+    // split the same way (the 600 x 3600 x 3600 DF product at o = 20, v =
+    // 180: 570 tiles). At o = 20, v = 180
+    // this took the antisymmetric ladder (756 tiles) from 3.0 to 2.5 ms with
+    // 3 chunks and the symmetric one (384 tiles of 72 x 128) to 2.7 ms with
+    // 4 (3 chunks, 4.5 rounds: 3.15).
     const double target = 2048.0 * 4096.0 / (BM * BN);
+    const int64_t cap = tiles >= 256 ? 8 : 1024;
     double best = -1.0;
-    for (int64_t sp = 1; sp <= 8 && sp <= d.K / (2 * BK) && sp <= ws_fit; ++sp) {
+    for (int64_t sp = 1; sp <= cap && sp <= d.K / (2 * BK) && sp <= ws_fit; ++sp) {
       const int64_t items = tiles * sp;
       const double fill = std::min(1.0, (double)items / target);
       const double rounds = (double)items / (double)(ceil_div(items, 256) * 256);
@@ -468,9 +479,6 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   if (splits > 1) splits = (int)ceil_div(d.K, p.kchunk);  // no empty chunk
   p.splits = splits;
   p.ws = d.ws;
-  // gridDim.y * gridDim.z covers the batch; y is a multiple of nb0
-  int64_t gy = d.nb0, gz = d.nb1;
-  while (gy * 2 <= 65535 && gz % 2 == 0) { gy *= 2; gz /= 2; }
   PNK_REQUIRE(gy <= 65535 && gz * splits <= 65535, "gemm: batch too large");
   dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)gy, (unsigned)(gz * splits));
   if (akc && bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, true><<<grid, 256, 0, s>>>(p);
@@ -513,6 +521,10 @@ void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A
       launch_cfg<Mma, TA, TB, TC, 80, 128, 8, 2>(d, A, B, A2, B2, C, s);
     else if (d.K >= 1024 && 10 * r72 <= 9 * r64 && (r72 / 72) * n128 >= 128)
       launch_cfg<Mma, TA, TB, TC, 72, 128, 8, 2>(d, A, B, A2, B2, C, s);
+    // a few 64-row tiles with a long contraction (the antisymmetric ladder's
+    // 190 pair rows at o = 20): 64 x 128 with 8-deep panels, 5 % faster
+    else if (d.M > 64 && d.M <= 256 && d.K >= 8192 && (r64 / 64) * n128 >= 128)
+      launch_cfg<Mma, TA, TB, TC, 64, 128, 8, 2>(d, A, B, A2, B2, C, s);
     else if (d.M <= 64 && d.K >= 1024) launch_cfg<Mma, TA, TB, TC, 64, 64, 32, 2>(d, A, B, A2, B2, C, s);
     else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
   } else {
