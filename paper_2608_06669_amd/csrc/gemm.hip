@@ -531,8 +531,13 @@ void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A
     const int64_t big = ceil_div(d.M, 128) * ceil_div(d.N, 128) * nb;
     // BF16 128 x 128 tiles take two matrix-core steps per panel (64-deep):
     // 25-45 % faster than one on the ring, ladder and T1-ladder products
-    constexpr int BK128 = std::is_same<Mma, MmaBF16>::value ? 64 : BK;
-    if (d.M >= 64 && d.N >= 96 && big >= 256) launch_cfg<Mma, TA, TB, TC, 128, 128, BK128, 2>(d, A, B, A2, B2, C, s);
+    constexpr bool bf16 = std::is_same<Mma, MmaBF16>::value;
+    constexpr int BK128 = bf16 ? 64 : BK;
+    // (BF16 with a long contraction takes them from 64 tiles on, split-K
+    // filling the GPU: 1.2-2.3x faster than 64 x 64 on the T1 part of the
+    // ladder and the antisymmetric ladder at o = 20, v = 180)
+    const bool wide = big >= 256 || (bf16 && d.K >= 8192 && big >= 64);
+    if (d.M >= 64 && d.N >= 96 && wide) launch_cfg<Mma, TA, TB, TC, 128, 128, BK128, 2>(d, A, B, A2, B2, C, s);
     else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
   }
 }
