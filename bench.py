@@ -47,10 +47,12 @@ RUN_BUDGET_S = 540.0
 VIR_LZ_TRAFFIC_BYTES = 33288550
 # HBM bytes of one residual evaluation and of one occupied A_F launch on the
 # default workload, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (each
-# scaled by the same counter for a copy kernel of known size); None until
-# counters of the current kernels are taken.
-RESIDUAL_TRAFFIC_BYTES = None
-OCC_PACKED_TRAFFIC_BYTES = None
+# scaled by the same counter for a copy of known size) in
+# profiles/residual_jvp_c2_c4_mfma_and_hbm_counters.md and
+# profiles/fock_occ_packed_kernel_c2_c4_counters.md; None when a kernel has
+# changed since the counters were taken.
+RESIDUAL_TRAFFIC_BYTES = 38647522449
+OCC_PACKED_TRAFFIC_BYTES = 362818867
 
 
 def nominal_residual_flops(o, v, naux):
