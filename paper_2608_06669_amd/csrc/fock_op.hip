@@ -146,7 +146,7 @@ struct OccArgs {
 // a fixed-order butterfly. The A_F part is scaled by s1; in the Lanczos
 // form the update and the shares of the three sums are added to dot, nrm,
 // vv2 (weight 1).
-template <bool LZ>
+template <bool LZ, int PER = 16>
 __device__ inline void singles_part(int o, int v, const double* __restrict__ f_oo, const double* __restrict__ f_vv,
                                     const double* __restrict__ x1, double* __restrict__ y1,
                                     const double* __restrict__ vprev1, double beta, double s1, int sb, double& dot,
@@ -154,7 +154,7 @@ __device__ inline void singles_part(int o, int v, const double* __restrict__ f_o
   const int tid = threadIdx.x;
   const int64_t ov = (int64_t)o * v;
   const int w = tid >> 4, l = tid & 15;
-  const int64_t out = (int64_t)sb * 16 + w;
+  const int64_t out = (int64_t)sb * PER + w;
   double part = 0.0;
   if (out < ov) {
     const int i = (int)(out / v), a = (int)(out % v);
@@ -715,6 +715,308 @@ __global__ __launch_bounds__(256) void fock_occ_packed_kernel(OccPackedArgs p) {
     for (int c = 0; c < 3; ++c) p.partials[c * gridDim.x + blockIdx.x] = rr[c];
 }
 
+// Register-blocked form of the packed occupied part. For one (a, b)
+// position e, the occupied terms are Y^e = -(F^T M^e + M^e F) with M^e the
+// o x o matrix M^e_ij = x_ij^ab, whose lower triangle the packed layout
+// keeps at the transposed position: M^e_ij = x_ji^ba for i > j. A workgroup
+// takes a set of 64 positions closed under transposition, one per lane
+// (occ_set_lane), stages x at them for every packed pair in LDS
+// (xs[pair][lane]), and each wave forms 4 x 4 blocks (I, J), I <= J, of the
+// upper triangle of Y^e for its lane's e: per k it reads M^e_kJ and M^e_Ik
+// (8 LDS reads, the lane or its transposed lane depending on k <= j) and
+// f_kI, f_kJ (4 broadcast LDS reads) for 32 fused multiply-adds.
+struct OccSetArgs {
+  int o, v, npair, nb, units, bsplit, nblk, dwg;
+  const double* f_oo;
+  const double* f_vv;
+  const double* x1;
+  const double* x2;  // packed
+  double* y1;
+  double* y2;  // packed; holds the virtual part on entry
+  const double* vprev1;
+  const double* vprev2;
+  const double* beta;
+  double* partials;
+  double s1;
+  const double* done;
+};
+
+// Position set u (0 <= u < nb^2) over the 8 x 8 blocks of the v x v grid
+// (nb = ceil(v / 8) per side): a diagonal block (T, T), or half h of an
+// off-diagonal block pair (Ta < Tb): rows 8 Ta + 4 h .. + 4 by columns 8
+// Tb .. + 8 together with its transpose. The blocks are taken in 2 x 2
+// groups (16 x 16 elements: two 128-byte lines of doubles per row), the
+// upper group triangle row by row, so that the sets of a group, which share
+// the lines they touch, run one after another on one XCD. A diagonal group
+// holds 4 sets: (2g, 2g), (2g, 2g + 1) halves 0 and 1, (2g + 1, 2g + 1);
+// an off-diagonal one 8: w = 4 dTa + 2 dTb + h; with nb odd the last
+// diagonal group holds 1 and the last column's groups 4 (dTb = 0).
+__device__ inline bool occ_set_decode(int u, int nb, bool* diag, int* a0, int* b0) {
+  const int ng = (nb + 1) / 2;
+  const bool odd = nb & 1;
+  for (int ga = 0; ga < ng; ++ga) {
+    const int cd = odd && ga == ng - 1 ? 1 : 4, noff = ng - 1 - ga;
+    const int row = cd + 8 * noff - (odd && noff > 0 ? 4 : 0);
+    if (u >= row) {
+      u -= row;
+      continue;
+    }
+    const int T = 2 * ga;
+    if (u < cd) {
+      *diag = u == 0 || u == 3;
+      *a0 = *diag ? 8 * (T + (u == 3 ? 1 : 0)) : 8 * T + 4 * (u - 1);
+      *b0 = *diag ? *a0 : 8 * (T + 1);
+      return true;
+    }
+    u -= cd;
+    const int gb = ga + 1 + u / 8, w = u % 8;
+    const bool half = odd && gb == ng - 1;
+    const int dTa = half ? w >> 1 : w >> 2, dTb = half ? 0 : (w >> 1) & 1, h = w & 1;
+    *diag = false;
+    *a0 = 8 * (T + dTa) + 4 * h;
+    *b0 = 8 * (2 * gb + dTb);
+    return true;
+  }
+  return false;  // u out of range
+}
+
+// Lane l's position (a, b) in the set, and the lane lT holding (b, a).
+__device__ inline void occ_set_lane(bool diag, int l, int a0, int b0, int* a, int* b, int* lT) {
+  if (diag) {
+    const int r = l >> 3, c = l & 7;
+    *a = a0 + r;
+    *b = a0 + c;
+    *lT = 8 * c + r;
+  } else if (l < 32) {
+    const int r = l >> 3, c = l & 7;
+    *a = a0 + r;
+    *b = b0 + c;
+    *lT = 32 + 4 * c + r;
+  } else {
+    const int m = l - 32, r = m >> 2, c = m & 3;
+    *a = b0 + r;
+    *b = a0 + c;
+    *lT = 8 * c + r;
+  }
+}
+
+// One k of the 4 x 4 block (I0, J0) of Y^e: acc_ij += f_ki M_kj + M_ik
+// f_kj. M_kj is read from pair (k, j) at the lane's own position when k <=
+// j, else from pair (j, k) at the transposed one; M_ik from pair (i, k) at
+// its own position when i <= k, else from pair (k, i) transposed. With the
+// packed index P(a, b) = R(a) + b, R(a) = a o - a (a - 1) / 2 - a, the
+// four reads of a term are R(k) + J0 + q (one address, immediate offsets)
+// or R(J0 + q) + k (and likewise with I0). T1 / T2 give the form of the two
+// terms for the whole block: 0 own position, 1 transposed, 2 split at k =
+// J0 + D (M_kj transposed for q < D) or k = I0 + D (M_ik own for q <= D).
+// Own-form reads of M_kj at j = J0 + q >= o, and transposed-form reads of
+// M_ik at i >= o, land up to three pairs past the last one (outputs that are
+// not written; the staging area is padded for them).
+template <int T1, int T2, int D, bool FENCE>
+__device__ inline void occ_kstep(int k, int o, int I0, int J0, const double* xl, const double* xt, const double* fs,
+                                 int ldf, double (&acc)[4][4]) {
+  if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
+  const double2 fi01 = *reinterpret_cast<const double2*>(fs + k * ldf + I0);
+  const double2 fi23 = *reinterpret_cast<const double2*>(fs + k * ldf + I0 + 2);
+  const double2 fj01 = *reinterpret_cast<const double2*>(fs + k * ldf + J0);
+  const double2 fj23 = *reinterpret_cast<const double2*>(fs + k * ldf + J0 + 2);
+  const double fi[4] = {fi01.x, fi01.y, fi23.x, fi23.y};
+  const double fj[4] = {fj01.x, fj01.y, fj23.x, fj23.y};
+  auto R = [o](int a) { return a * o - a * (a - 1) / 2 - a; };
+  double mkj[4], mik[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (T1 == 1 || (T1 == 2 && q < D)) mkj[q] = xt[(R(J0 + q) + k) * 64];
+    else mkj[q] = xl[(R(k) + J0 + q) * 64];
+    if (T2 == 0 || (T2 == 2 && q <= D)) mik[q] = xl[(R(I0 + q) + k) * 64];
+    else mik[q] = xt[(R(k) + I0 + q) * 64];
+  }
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      acc[ii][jj] = fma(fi[ii], mkj[jj], acc[ii][jj]);
+      acc[ii][jj] = fma(mik[ii], fj[jj], acc[ii][jj]);
+    }
+}
+
+// The block's sum over k = 0 .. o - 1 in ranges of one read form each
+// (diagonal blocks: I0 = J0). FENCE keeps the scheduler from hoisting the
+// reads of later steps above earlier ones (register budget of 16-wave
+// workgroups).
+template <bool FENCE>
+__device__ inline void occ_block(int o, int I0, int J0, const double* xl, const double* xt, const double* fs, int ldf,
+                                 double (&acc)[4][4]) {
+  int k = 0;
+  for (; k < I0; ++k) occ_kstep<0, 1, 0, FENCE>(k, o, I0, J0, xl, xt, fs, ldf, acc);
+  if (I0 == J0) {
+    occ_kstep<2, 2, 0, FENCE>(k, o, I0, J0, xl, xt, fs, ldf, acc);
+    if (k + 1 < o) occ_kstep<2, 2, 1, FENCE>(k + 1, o, I0, J0, xl, xt, fs, ldf, acc);
+    if (k + 2 < o) occ_kstep<2, 2, 2, FENCE>(k + 2, o, I0, J0, xl, xt, fs, ldf, acc);
+    if (k + 3 < o) occ_kstep<2, 2, 3, FENCE>(k + 3, o, I0, J0, xl, xt, fs, ldf, acc);
+  } else {
+    // k in [I0, I0 + 4) < J0 <= o - 1
+    occ_kstep<0, 2, 0, FENCE>(k, o, I0, J0, xl, xt, fs, ldf, acc);
+    occ_kstep<0, 2, 1, FENCE>(k + 1, o, I0, J0, xl, xt, fs, ldf, acc);
+    occ_kstep<0, 2, 2, FENCE>(k + 2, o, I0, J0, xl, xt, fs, ldf, acc);
+    occ_kstep<0, 2, 3, FENCE>(k + 3, o, I0, J0, xl, xt, fs, ldf, acc);
+    for (k = I0 + 4; k < J0; ++k) occ_kstep<0, 0, 0, FENCE>(k, o, I0, J0, xl, xt, fs, ldf, acc);
+    occ_kstep<2, 0, 0, FENCE>(k, o, I0, J0, xl, xt, fs, ldf, acc);
+    if (k + 1 < o) occ_kstep<2, 0, 1, FENCE>(k + 1, o, I0, J0, xl, xt, fs, ldf, acc);
+    if (k + 2 < o) occ_kstep<2, 0, 2, FENCE>(k + 2, o, I0, J0, xl, xt, fs, ldf, acc);
+    if (k + 3 < o) occ_kstep<2, 0, 3, FENCE>(k + 3, o, I0, J0, xl, xt, fs, ldf, acc);
+  }
+  for (k = J0 + 4; k < o; ++k) occ_kstep<1, 0, 0, FENCE>(k, o, I0, J0, xl, xt, fs, ldf, acc);
+}
+
+// Dynamic LDS: xs[npair + 3][64] (the last three rows only padding), then
+// f_oo with rows padded to ldf = 4 ceil(o / 4) (zeros past o). NW waves per
+// workgroup. Workgroup bid < dwg takes the unit u = (bid % 8) (dwg / 8) +
+// bid / 8: position set u / bsplit, and of the nblk blocks of the upper
+// block triangle those with index part NW + wave + NW bsplit m (part = u %
+// bsplit). Units past units * bsplit only write zero partial sums; the
+// remaining workgroups compute the singles, 4 NW outputs each.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void fock_occ_set_kernel(OccSetArgs p) {
+  extern __shared__ __attribute__((aligned(16))) double xs[];
+  __shared__ double red[3][NW];
+  if (p.done && *p.done != 0.0) return;
+  const int o = p.o, v = p.v, npair = p.npair;
+  const int64_t vv = (int64_t)v * v;
+  const int tid = threadIdx.x;
+  const int l = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double beta = *p.beta;
+  double dot = 0.0, nrm = 0.0, vv2 = 0.0;
+
+  const int unit = (int)(blockIdx.x % 8) * (p.dwg / 8) + (int)(blockIdx.x / 8);
+  bool diag = false;
+  int a0 = 0, b0 = 0;
+  if ((int)blockIdx.x < p.dwg && unit < p.units * p.bsplit &&
+      occ_set_decode(unit / p.bsplit, p.nb, &diag, &a0, &b0)) {
+    int a, b, lT;
+    occ_set_lane(diag, l, a0, b0, &a, &b, &lT);
+    const int part = unit % p.bsplit;
+    const bool valid = a < v && b < v;
+    const int64_t e = valid ? (int64_t)a * v + b : 0;  // (invalid lanes read position 0 and discard it)
+    const int bg = (o + 3) / 4, ldf = 4 * bg;
+    double* fs = xs + (int64_t)(npair + 3) * 64;
+    const int step = NW * p.bsplit;
+    // PRE: the y and vprev elements of a wave's block of outputs are read
+    // before its contractions (their latency hidden behind them) and kept
+    // as pre = y - beta vprev; 16-wave workgroups (128 registers) read them
+    // after the contractions instead. Outputs with i > j, i >= o or j >= o
+    // are not written: a valid element is read in their place.
+    constexpr bool PRE = NW < 16;
+    double pre[4][4];
+    auto block_of = [&](int blk, int* I0, int* J0) {
+      int bi = 0, rem = blk;
+      while (rem >= bg - bi) {
+        rem -= bg - bi;
+        ++bi;
+      }
+      *I0 = 4 * bi;
+      *J0 = 4 * (bi + rem);
+    };
+    auto read_pre = [&](int I0, int J0) {
+      double yin[4][4], vin[4][4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int i = min(I0 + ii, o - 1), j = max(min(J0 + jj, o - 1), i);
+          const int64_t idx = (int64_t)(i * o - i * (i - 1) / 2 + (j - i)) * vv + e;
+          yin[ii][jj] = p.y2[idx];
+          vin[ii][jj] = p.vprev2[idx];
+        }
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) pre[ii][jj] = yin[ii][jj] - beta * vin[ii][jj];
+    };
+    int blk = part * NW + wave;
+    {
+      // wave w stages pairs w, w + NW, ..., 16 loads in flight per lane
+      // (clamped to the last pair), and f_oo; the first batch is issued
+      // before the reads of the wave's first block of outputs
+      const double* src = p.x2 + e;
+      const int nf = o * ldf;
+      const double fv = tid < nf && tid % ldf < o ? p.f_oo[(tid / ldf) * o + tid % ldf] : 0.0;
+      double t[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) t[u] = src[(int64_t)min(wave + NW * u, npair - 1) * vv];
+      if constexpr (PRE) {
+        int I0 = 0, J0 = 0;
+        if (blk < p.nblk) block_of(blk, &I0, &J0);
+        read_pre(I0, J0);
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (wave + NW * u < npair) xs[(wave + NW * u) * 64 + l] = valid ? t[u] : 0.0;
+      if (tid < nf) fs[tid] = fv;
+      for (int pr0 = wave + 16 * NW; pr0 < npair; pr0 += 16 * NW) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) t[u] = src[(int64_t)min(pr0 + NW * u, npair - 1) * vv];
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (pr0 + NW * u < npair) xs[(pr0 + NW * u) * 64 + l] = valid ? t[u] : 0.0;
+      }
+      for (int q = tid + 64 * NW; q < nf; q += 64 * NW) {
+        const int k = q / ldf, i = q % ldf;
+        fs[q] = i < o ? p.f_oo[k * o + i] : 0.0;
+      }
+    }
+    __syncthreads();
+    const double* xl = xs + l;
+    const double* xt = xs + lT;
+    for (; blk < p.nblk; blk += step) {
+      int I0, J0;
+      block_of(blk, &I0, &J0);
+      double acc[4][4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) acc[ii][jj] = 0.0;
+      occ_block<NW == 16>(o, I0, J0, xl, xt, fs, ldf, acc);
+      if constexpr (!PRE) read_pre(I0, J0);
+      // outputs i <= j < o of valid positions; the sums weight the other
+      // (padded) outputs by 0 and the blocks of pairs i < j by 2 (x_ij and
+      // x_ji = x_ij^T both count)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int i = I0 + ii, j = J0 + jj;
+          const bool out = i < o && j < o && i <= j;  // wave-uniform
+          if (!out) continue;
+          const int pr = i * o - i * (i - 1) / 2 + (j - i);
+          const double q = pre[ii][jj] - acc[ii][jj];
+          const double vk = xl[pr * 64];
+          const double w = !valid ? 0.0 : (i == j ? 1.0 : 2.0);
+          if (valid) p.y2[(int64_t)pr * vv + e] = q;
+          dot += w * vk * q;
+          nrm += w * q * q;
+          vv2 += w * vk * vk;
+        }
+      if constexpr (PRE) {
+        if (blk + step < p.nblk) {
+          int I1, J1;
+          block_of(blk + step, &I1, &J1);
+          read_pre(I1, J1);
+        }
+      }
+    }
+  } else if ((int)blockIdx.x >= p.dwg) {
+    singles_part<true, 4 * NW>(p.o, p.v, p.f_oo, p.f_vv, p.x1, p.y1, p.vprev1, beta, p.s1, blockIdx.x - p.dwg, dot,
+                               nrm, vv2);
+  }
+
+  double rr[3] = {dot, nrm, vv2};
+  block_sum_waves<3, NW>(rr, red);
+  if (tid == 0)
+    for (int c = 0; c < 3; ++c) p.partials[c * gridDim.x + blockIdx.x] = rr[c];
+}
+
 bool aligned16(const void* q) { return ((uintptr_t)q & 15u) == 0; }
 
 // npairs: o^2 for the full layout, o (o + 1) / 2 for the packed one (the
@@ -771,6 +1073,33 @@ void launch_occ(const FockOp& op, const double* x1, const double* x2, double* y1
   a.done = done;
   fock_occ_kernel<LZ><<<(unsigned)op.nparts(), 256, occ_lds_bytes(op.o, op.ch), s>>>(a);
   PNK_CHECK_LAUNCH();
+}
+
+size_t occ_set_lds_bytes(int o) {
+  const size_t npair = (size_t)o * (o + 1) / 2, ldf = 4 * (size_t)((o + 3) / 4);
+  return sizeof(double) * (64 * (npair + 3) + (size_t)o * ldf);
+}
+
+// Dynamic LDS a workgroup of the register-blocked occupied kernel may use:
+// the device's per-workgroup maximum, opted into for that kernel (0 when
+// the opt-in fails).
+size_t occ_set_lds_limit() {
+  int dev = 0, lim = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  const size_t avail = (size_t)lim > 2048 ? (size_t)lim - 2048 : 0;  // the kernel's static reduction buffer
+  const void* k[3] = {reinterpret_cast<const void*>(&fock_occ_set_kernel<4>),
+                      reinterpret_cast<const void*>(&fock_occ_set_kernel<8>),
+                      reinterpret_cast<const void*>(&fock_occ_set_kernel<16>)};
+  for (const void* f : k)
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)avail) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+  return avail;
 }
 
 }  // namespace
@@ -836,6 +1165,7 @@ bool fock_op_plan(FockOp& op) {
     if (nt * (nt + 1) / 2 >= 256) { op.pt = tt; break; }
   }
   if (op.pt > 0) {
+    op.psingles = op.nsingles;
     op.pntile = (int)ceil_div(op.v, op.pt);
     op.pnchunks = op.pntile * (op.pntile + 1) / 2;
     // split the packed pairs of a tile over up to 4 workgroups (each stages
@@ -845,6 +1175,28 @@ bool fock_op_plan(FockOp& op) {
     while (!small_tiles && op.psplit < 4 && (int64_t)op.pnchunks * op.psplit < 1024 && op.npair >= 8 * 2 * op.psplit)
       ++op.psplit;
     op.pdwg = (int)(8 * ceil_div((int64_t)op.pnchunks * op.psplit, 8));
+    // the register-blocked form when 64 positions of every packed pair fit
+    // in LDS (o <= 24 with 160 KB per workgroup): split each set's output
+    // blocks over more workgroups while there are fewer than 512 and every
+    // workgroup still gets a block
+    const size_t set_lds = occ_set_lds_bytes(op.o), lds_limit = occ_set_lds_limit();
+    if (set_lds <= lds_limit) {
+      op.psets = 1;
+      op.pnb = (int)ceil_div(op.v, 8);
+      const int bg = (op.o + 3) / 4;
+      op.pnblk = bg * (bg + 1) / 2;
+      const int64_t units = (int64_t)op.pnb * op.pnb;
+      // waves per workgroup: about 16 resident per CU (the workgroups that
+      // fit a CU's LDS, taken as the per-workgroup maximum, times NW), with
+      // at most half of them idle in the block loop
+      const int per_cu = (int)((lds_limit + 2048) / set_lds);
+      op.pnw = per_cu >= 4 ? 4 : (per_cu >= 2 ? 8 : 16);
+      while (op.pnw > 4 && op.pnblk <= op.pnw / 2) op.pnw /= 2;
+      op.pbsplit = 1;
+      while (units * op.pbsplit < 512 && op.pnblk > op.pnw * op.pbsplit) ++op.pbsplit;
+      op.pdwg = (int)(8 * ceil_div(units * op.pbsplit, 8));
+      op.psingles = (int)ceil_div((int64_t)op.o * op.v, 4 * op.pnw);
+    }
   }
   return (int64_t)op.tiles * op.o * op.o < (1ll << 31) - 8 && op.nparts() <= 0x7fffffff;
 }
@@ -854,7 +1206,10 @@ bool fock_op_fused_step(const FockOp& op) { return op.pt > 0 && op.bm == 32; }
 bool fock_op_is_timed_lanczos_kernel(const void* func, bool fused) {
   if (!fused)
     return func == reinterpret_cast<const void*>(&fock_occ_kernel<true>) ||
-           func == reinterpret_cast<const void*>(&fock_occ_packed_kernel);
+           func == reinterpret_cast<const void*>(&fock_occ_packed_kernel) ||
+           func == reinterpret_cast<const void*>(&fock_occ_set_kernel<4>) ||
+           func == reinterpret_cast<const void*>(&fock_occ_set_kernel<8>) ||
+           func == reinterpret_cast<const void*>(&fock_occ_set_kernel<16>);
   const void* timed[] = {reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 16>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 32>),
                          reinterpret_cast<const void*>(&fock_vir_lz_kernel<32, 2, 64>),
@@ -972,6 +1327,38 @@ void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double*
   a.partials = partials;
   a.s1 = singles_scale;
   a.done = done;
+  if (op.psets) {
+    OccSetArgs c;
+    c.o = op.o;
+    c.v = op.v;
+    c.npair = op.npair;
+    c.nb = op.pnb;
+    c.units = op.pnb * op.pnb;
+    c.bsplit = op.pbsplit;
+    c.nblk = op.pnblk;
+    c.dwg = op.pdwg;
+    c.f_oo = op.f_oo;
+    c.f_vv = op.f_vv;
+    c.x1 = a.x1;
+    c.x2 = a.x2;
+    c.y1 = a.y1;
+    c.y2 = a.y2;
+    c.vprev1 = a.vprev1;
+    c.vprev2 = a.vprev2;
+    c.beta = beta;
+    c.partials = partials;
+    c.s1 = singles_scale;
+    c.done = done;
+    const unsigned grid = (unsigned)op.nparts_packed();
+    const size_t lds = occ_set_lds_bytes(op.o);
+    switch (op.pnw) {
+      case 4: fock_occ_set_kernel<4><<<grid, 256, lds, s>>>(c); break;
+      case 8: fock_occ_set_kernel<8><<<grid, 512, lds, s>>>(c); break;
+      default: fock_occ_set_kernel<16><<<grid, 1024, lds, s>>>(c); break;
+    }
+    PNK_CHECK_LAUNCH();
+    return;
+  }
   const size_t lds = sizeof(double) * ((size_t)op.npair * 2 * op.pt * op.pt + (size_t)op.o * op.o);
   fock_occ_packed_kernel<<<(unsigned)op.nparts_packed(), 256, lds, s>>>(a);
   PNK_CHECK_LAUNCH();

@@ -32,8 +32,15 @@ struct FockOp {
   // psplit workgroups share a tile, each taking every psplit-th pair;
   // pdwg = pnchunks * psplit rounded up to a multiple of 8 (XCD grouping)
   int npair = 0, pt = 0, pntile = 0, pnchunks = 0, psplit = 1, pdwg = 0;
+  // register-blocked form (used when its staging fits a workgroup's LDS):
+  // psets = 1, sets of 64 positions over pnb = ceil(v / 8) blocks per side
+  // (pnb^2 sets), each split over pbsplit workgroups by its pnblk 4 x 4
+  // blocks of the upper triangle of the o x o output; pdwg counts these
+  // workgroups instead
+  int psets = 0, pnb = 0, pbsplit = 1, pnblk = 0, pnw = 4;  // pnw: waves per workgroup
   int64_t nparts() const { return (int64_t)nchunks + nsingles; }
-  int64_t nparts_packed() const { return (int64_t)pdwg + nsingles; }
+  int psingles = 0;  // singles workgroups of the packed form
+  int64_t nparts_packed() const { return (int64_t)pdwg + psingles; }
 };
 
 // Picks the launch shapes; false when these kernels do not apply (o too

@@ -201,11 +201,15 @@ def test_precond_solve_symmetric_fock_operator(handle, lib):
 
 
 @pytest.mark.parametrize("o,v,seed", [(5, 23, 47), (1, 9, 48), (10, 90, 49), (7, 40, 50), (12, 60, 51), (5, 64, 52),
-                                      (6, 96, 53), (4, 91, 54)])
+                                      (6, 96, 53), (4, 91, 54), (16, 40, 57), (24, 20, 58), (25, 30, 59)])
 def test_precond_solve_pair_symmetric_packed_layout(handle, lib, o, v, seed):
-    """cc_precond_solve_pairsym: the Lanczos vectors hold pairs i <= j only
-    (the occupied kernel's tile edge is 8 at o=5/v=23, with a ragged last
-    tile, and 2 with the pairs unsplit at v=90, 91 and 96, ragged at 91).
+    """cc_precond_solve_pairsym: the Lanczos vectors hold pairs i <= j only.
+    The occupied part runs in the register-blocked form (64 positions per
+    workgroup over 8 x 8 blocks, ragged at v=23, 9, 91, 90 and 20; 4 x 4
+    blocks of the o x o output, ragged at o=5, 1, 10, 7, 6 and 13) up to
+    o=24, whose staging just fits a workgroup's LDS; a set's output blocks
+    are split over two workgroups at o=10/v=90 and o=12/v=60 and over three
+    at o=16/v=40. At o=25 it falls back to the tile form (tile edge 2).
     The virtual contraction of the fused step runs in panels of 32 at v=23,
     in one panel of 96 at v=90 and 91 and of 64 at v=60 (o=12: 32-wide
     blocks), and exactly fills its one panel at v=64 and v=96; v=40 takes
