@@ -49,10 +49,10 @@ VIR_LZ_TRAFFIC_BYTES = 33288550
 # default workload, from the rocprofv3 FETCH_SIZE / WRITE_SIZE passes (each
 # scaled by the same counter for a copy of known size) in
 # profiles/residual_jvp_c2_c4_mfma_and_hbm_counters.md and
-# profiles/fock_occ_packed_kernel_c2_c4_counters.md; None when a kernel has
+# profiles/fock_occ_set_kernel_c2_c4_counters.md; None when a kernel has
 # changed since the counters were taken.
 RESIDUAL_TRAFFIC_BYTES = 38647522449
-OCC_PACKED_TRAFFIC_BYTES = 362817863
+OCC_PACKED_TRAFFIC_BYTES = 289373094
 
 
 def nominal_residual_flops(o, v, naux):
@@ -359,8 +359,9 @@ def bench_headline(args):
         gbs = b / (af_ms * 1e-3) / 1e9
         roof_inner = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                       "frac": gbs / HBM_PEAK_GBS, "traffic": OCC_PACKED_TRAFFIC_BYTES,
-                      "kernel": "fock_occ_packed_kernel (occupied A_F contractions of the inner Lanczos step on "
-                                "the packed pairs)", "launches_timed": n_afm, "avg_us": af_ms * 1e3,
+                      "kernel": "fock_occ_set_kernel (occupied A_F contractions of the inner Lanczos step on "
+                                "the packed pairs, register-blocked over transpose-closed position sets)",
+                      "launches_timed": n_afm, "avg_us": af_ms * 1e3,
                       "bytes_per_launch": b}
     out = {
         "metric": "PNK CCSD solves/s + p50/p99 latency at |dE|<1e-6 Eh; residual TFLOP/s vs FP64",

@@ -206,10 +206,11 @@ def test_precond_solve_pair_symmetric_packed_layout(handle, lib, o, v, seed):
     """cc_precond_solve_pairsym: the Lanczos vectors hold pairs i <= j only.
     The occupied part runs in the register-blocked form (64 positions per
     workgroup over 8 x 8 blocks, ragged at v=23, 9, 91, 90 and 20; 4 x 4
-    blocks of the o x o output, ragged at o=5, 1, 10, 7, 6 and 13) up to
-    o=24, whose staging just fits a workgroup's LDS; a set's output blocks
-    are split over two workgroups at o=10/v=90 and o=12/v=60 and over three
-    at o=16/v=40. At o=25 it falls back to the tile form (tile edge 2).
+    blocks of the o x o output, ragged at o=5, 1, 10, 7 and 6) up to o=24,
+    whose staging just fits a workgroup's LDS: 4 waves per workgroup at o <=
+    8, 8 waves at o=10, 12 and 16, 16 at o=24, with a set's output blocks
+    split over two workgroups at o=16/v=40 and o=24/v=20. At o=25 it falls
+    back to the tile form (tile edge 2).
     The virtual contraction of the fused step runs in panels of 32 at v=23,
     in one panel of 96 at v=90 and 91 and of 64 at v=60 (o=12: 32-wide
     blocks), and exactly fills its one panel at v=64 and v=96; v=40 takes
