@@ -160,7 +160,8 @@ int64_t splitk_elems(const Sizes& z) {
 // with rows padded to 16 bytes.
 int64_t cast_bytes(const Sizes& z, const EngineOptions& opt) {
   if (!opt.lowp_f32 && !opt.lowp_bf16) return 0;
-  return (opt.lowp_f32 ? 4 : 2) * (4 * z.n2 + 32 * z.ov) + (1 << 20);
+  // (rows of the packed copies are padded along k, to 64 elements in BF16)
+  return (opt.lowp_f32 ? 4 : 2) * (4 * z.n2 + 160 * z.ov) + (1 << 20);
 }
 
 // Calls `f(count_doubles)` for every FP64 buffer in allocation order, and
@@ -179,8 +180,8 @@ void for_each_buffer(const Sizes& z, const EngineOptions& opt, F f, G g) {
     g(4 * o * v * v * v); g(4 * n2); g(4 * n2); g(4 * n2); g(4 * n2);
   }
   if (opt.lowp_bf16) {
-    g(2 * p2 * pad_to(p2, 8)); g(2 * p2m * pad_to(p2m, 8));
-    g(2 * o * v * v * v); g(2 * n2); g(2 * n2); g(2 * n2); g(2 * n2);
+    g(2 * p2 * pad_to(p2, 64)); g(2 * p2m * pad_to(p2m, 64));
+    g(2 * o * v * v * v); g(2 * n2); g(2 * ov * pad_to(ov, 64)); g(2 * ov * pad_to(ov, 64)); g(2 * n2);
   }
   g(cast_bytes(z, opt));
   // intermediates, value and tangent
@@ -231,7 +232,7 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
   // the low-precision ladder tensors keep rows of a 16-byte multiple (the
   // pair counts v(v+1)/2, v(v-1)/2 need not be), for vector loads
   ld32_ = pad_to(z.p2, 4); ld32m_ = pad_to(z.p2m, 4);
-  ld16_ = pad_to(z.p2, 8); ld16m_ = pad_to(z.p2m, 8);
+  ld16_ = pad_to(z.p2, 64); ld16m_ = pad_to(z.p2m, 64);  // whole 64-deep panels, zero-padded
   if (opt.lowp_f32) {
     S.lp32 = arena_.take<float>(z.p2 * ld32_); Am.lp32 = arena_.take<float>(z.p2m * ld32m_);
     Wov.lp32 = arena_.take<float>(O * V * V * V);
@@ -241,8 +242,12 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
   if (opt.lowp_bf16) {
     S.lp16 = arena_.take<uint16_t>(z.p2 * ld16_); Am.lp16 = arena_.take<uint16_t>(z.p2m * ld16m_);
     Wov.lp16 = arena_.take<uint16_t>(O * V * V * V);
-    Ioovv.lp16 = arena_.take<uint16_t>(N2); Iovov.lp16 = arena_.take<uint16_t>(N2);
-    Ix.lp16 = arena_.take<uint16_t>(N2); Ikldc.lp16 = arena_.take<uint16_t>(N2);
+    // the ring integrals in BF16 are read along k (the matrix-core operand
+    // layout), rows zero-padded to whole 64-deep panels: Iovov as is (it is
+    // symmetric), Ix transposed
+    ldov16_ = pad_to(OV, 64);
+    Ioovv.lp16 = arena_.take<uint16_t>(N2); Iovov.lp16 = arena_.take<uint16_t>(OV * ldov16_);
+    Ix.lp16 = arena_.take<uint16_t>(OV * ldov16_); Ikldc.lp16 = arena_.take<uint16_t>(N2);
   }
   cast_bytes_ = cast_bytes(z, opt);
   if (cast_bytes_) cast_ws_ = arena_.take<char>((size_t)cast_bytes_);
@@ -550,7 +555,16 @@ void Engine::prepare(const ProblemView& p, hipStream_t s) {
   const int64_t lsz[] = {(int64_t)o * v * vv, n2_, n2_, n2_, n2_};
   for (int k = 0; k < 5; ++k) {
     if (lows[k]->lp32) cast_f64_to_f32(lsz[k], lows[k]->v, (float*)lows[k]->lp32, s);
-    if (lows[k]->lp16) cast_f64_to_bf16(lsz[k], lows[k]->v, (uint16_t*)lows[k]->lp16, s);
+    if (lows[k]->lp16 && lows[k] != &Iovov && lows[k] != &Ix)
+      cast_f64_to_bf16(lsz[k], lows[k]->v, (uint16_t*)lows[k]->lp16, s);
+  }
+  if (Iovov.lp16) {
+    cast_f64_to_bf16_rows(ov, ov, ldov16_, Iovov.v, (uint16_t*)Iovov.lp16, s);
+    // Ix^T[(k,c)][(l,d)] = Ix[(l,d)][(k,c)] = (kd|lc), staged in Tmp
+    const int dims[4] = {o, v, o, v};
+    const int pm[4] = {0, 3, 2, 1};
+    permute4(Iovov.v, Tmp.v, dims, pm, 1.0, 0.0, s);
+    cast_f64_to_bf16_rows(ov, ov, ldov16_, Tmp.v, (uint16_t*)Ix.lp16, s);
   }
   fill(ov_ + n2_, 0.0, zeros_, s);
   // f_ov == 0 lets A_F skip its singles-doubles coupling
@@ -621,9 +635,17 @@ void Engine::run(Mode m) {
     const int64_t ls = kc && S.lp16 ? ld16_ : (t32 && S.lp32 ? ld32_ : p2_);
     const int64_t lm = kc && Am.lp16 ? ld16m_ : (t32 && Am.lp32 ? ld32m_ : p2m_);
     if (timers_) timers_->begin(kTimerPPL, s_);
-    mm(gd(O2, P2, P2, p2_, 1, kc ? 1 : ls, kc ? ls : 1, p2_, 1), Tp, S, Rp);
+    // (the BF16 copies' rows are zero from P2 to their length: the packed
+    // amplitudes may run the contraction over whole panels)
+    GemmDesc gs = gd(O2, P2, P2, p2_, 1, kc ? 1 : ls, kc ? ls : 1, p2_, 1);
+    if (kc && S.lp16) gs.b_kzero = ld16_;
+    mm(gs, Tp, S, Rp);
     // the antisymmetric pairs over i < j only (t_ii^cd = t_ii^dc)
-    if (P2m > 0 && O2m > 0) mm(gd(O2m, P2m, P2m, p2m_, 1, kc ? 1 : lm, kc ? lm : 1, p2m_, 1), Tm, Am, Rm);
+    if (P2m > 0 && O2m > 0) {
+      GemmDesc ga = gd(O2m, P2m, P2m, p2m_, 1, kc ? 1 : lm, kc ? lm : 1, p2m_, 1);
+      if (kc && Am.lp16) ga.b_kzero = ld16m_;
+      mm(ga, Tm, Am, Rm);
+    }
     if (timers_) timers_->end(kTimerPPL, s_);
   }
   lin_ppl_unpack(Rp, Rm, R2);
@@ -649,11 +671,19 @@ void Engine::run(Mode m) {
 
   // ---- ring terms ----
   mm(gd(OV, OV, naux, 1, ov, ov, 1, ov, 1), Lvo, Lov0, J);         // (ai|kc)~
-  mm(gd(OV, OV, OV, ov, 1, ov, 1, ov, 1, 0.5, 1.0), Uail, Iovov, J);
-  mm(gd(OV, OV, OV, ov, 1, ov, 1, ov, 1, -0.5, 1.0), Tail, Ix, J);
+  // (BF16 tangents read the ring integrals along k: Iovov is symmetric, and
+  // the BF16 copy of Ix holds its transpose)
+  const bool kc16 = mode_ == Mode::Tangent && jprec_ == Prec::BF16 && Iovov.lp16;
+  auto ring = [&](double alpha) {
+    GemmDesc g = gd(OV, OV, OV, ov, 1, kc16 ? 1 : ov, kc16 ? ldov16_ : 1, ov, 1, alpha, 1.0);
+    if (kc16) g.b_kzero = ldov16_;
+    return g;
+  };
+  mm(ring(0.5), Uail, Iovov, J);
+  mm(ring(-0.5), Tail, Ix, J);
   mm(gd(OO, VV, naux, 1, oo, vv, 1, vv, 1), Loo, Lvv, Tmp);        // (ki|ac)~ as [(k,i)][(a,c)]
   perm(Tmp, Kp, o, o, v, v, 2, 1, 0, 3, 1.0, 0.0);                 // K'[(a,i)][(k,c)]
-  mm(gd(OV, OV, OV, ov, 1, ov, 1, ov, 1, -0.5, 1.0), Tsail, Ix, Kp);
+  mm(ring(-0.5), Tsail, Ix, Kp);
   mm(gd(OV, OV, OV, ov, 1, 1, ov, ov, 1), J, Uail, Tmp);           // J u_jk^bc
   mm(gd(OV, OV, OV, ov, 1, 1, ov, ov, 1, -1.0, 1.0), Kp, Tail, Tmp);  // - K t_kj^cb
   perm(Tmp, X, v, o, v, o, 1, 3, 0, 2, 1.0, 1.0);

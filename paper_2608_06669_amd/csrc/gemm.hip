@@ -310,6 +310,154 @@ __global__ __launch_bounds__(256) void splitk_reduce_wide(KArgs p) {
   }
 }
 
+// BF16 product of two k-contiguous BF16 operands (rows 16-byte aligned, the
+// contraction a multiple of 64, zero-padded), 128 x 128 tiles, 64-deep
+// panels in a ring of three LDS stages filled straight from global memory
+// (16 bytes per lane, no register staging), so two panels' loads are in
+// flight while the matrix cores work on the third. A stage holds A then B,
+// [row][64] each; the eight 16-byte chunks of a row are stored at slot
+// chunk ^ ((row / 2) % 8), which spreads the fragment reads of 16
+// consecutive rows over all 64 banks (each wave's load writes 1 KB
+// contiguously: its lanes fetch the chunks in slot order). Same tile order,
+// split-K and epilogue as gemm_kernel.
+template <int N>
+__device__ inline void wait_vm_lgkm0() {  // vmcnt(N), lgkmcnt(0)
+  __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
+}
+
+__global__ __launch_bounds__(256) void gemm_bf16_pipe(KArgs p) {
+  constexpr int BM = 128, BN = 128, BK = 64, STAGES = 3;
+  constexpr int SE = (BM + BN) * BK;  // elements per stage
+  __shared__ __attribute__((aligned(1024))) uint16_t st0[SE], st1[SE], st2[SE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int ntiles = p.tiles_m * p.tiles_n;
+  int bid = blockIdx.x;
+  {
+    const int q = ntiles >> 3, r = ntiles & 7, x = bid & 7;
+    bid = x * q + min(x, r) + (bid >> 3);
+  }
+  constexpr int kGroupM = 8;
+  const int gsize = kGroupM * p.tiles_n;
+  const int grp = bid / gsize;
+  const int first_m = grp * kGroupM;
+  const int gm = min(p.tiles_m - first_m, kGroupM);
+  const int rem = bid - grp * gsize;
+  const int m0 = (first_m + rem % gm) * BM;
+  const int n0 = (rem / gm) * BN;
+
+  const int split = blockIdx.z % p.splits;
+  const int zb = blockIdx.z / p.splits;
+  const int b0 = blockIdx.y % p.nb0;
+  const int b1 = blockIdx.y / p.nb0 + zb * (gridDim.y / p.nb0);
+  const int kbeg = split * p.kchunk;
+  const int nk = (min(p.K, kbeg + p.kchunk) - kbeg) / BK;  // >= 1
+  const uint16_t* __restrict__ Ag = (const uint16_t*)p.A + b0 * p.a_b0 + b1 * p.a_b1 + kbeg;
+  const uint16_t* __restrict__ Bg = (const uint16_t*)p.B + b0 * p.b_b0 + b1 * p.b_b1 + kbeg;
+  double* __restrict__ Cg = (double*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
+
+  // this thread's chunks c = j 256 + tid (row c / 8, slot c % 8), j = 0..3,
+  // of A and of B (rows past the matrix read its last row; those outputs are
+  // not written)
+  const uint16_t* ga[4];
+  const uint16_t* gb[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = j * 256 + tid, r = c >> 3, slot = c & 7, g = slot ^ ((r >> 1) & 7);
+    ga[j] = Ag + (int64_t)min(m0 + r, p.M - 1) * p.a_m + 8 * g;
+    gb[j] = Bg + (int64_t)min(n0 + r, p.N - 1) * p.b_n + 8 * g;
+  }
+  // panel t into stage st (past the last panel: the last one again, never read)
+  auto issue = [&](uint16_t* st, int t) {
+    const int k0 = min(t, nk - 1) * BK;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      __builtin_amdgcn_global_load_lds(ga[j] + k0, (__attribute__((address_space(3))) void*)(st + (j * 256 + wave * 64) * 8),
+                                       16, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      __builtin_amdgcn_global_load_lds(gb[j] + k0,
+                                       (__attribute__((address_space(3))) void*)(st + BM * BK + (j * 256 + wave * 64) * 8),
+                                       16, 0, 0);
+  };
+  f4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+  auto compute = [&](const uint16_t* st) {
+#pragma unroll
+    for (int ks = 0; ks < BK / 32; ++ks) {
+      const int q = 4 * ks + (lane >> 4);  // this lane's 8-element chunk of the 32-deep step
+      bf8 af[4], bfr[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = wm * 64 + i * 16 + (lane & 15);
+        af[i] = __builtin_bit_cast(bf8, *reinterpret_cast<const u16x8*>(st + row * BK + 8 * (q ^ ((row >> 1) & 7))));
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int row = wn * 64 + j * 16 + (lane & 15);
+        bfr[j] = __builtin_bit_cast(
+            bf8, *reinterpret_cast<const u16x8*>(st + BM * BK + row * BK + 8 * (q ^ ((row >> 1) & 7))));
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+  };
+  issue(st0, 0);
+  issue(st1, 1);
+  // step t: wait for panel t (8 loads per panel per thread; the next
+  // panel's 8 may still be in flight) and for this wave's earlier LDS
+  // reads, then a barrier (every wave's share of panel t has landed and
+  // every wave is done with the stage about to be refilled), refill that
+  // stage with panel t + 2, and compute panel t. (A plain barrier: the
+  // workgroup fence of __syncthreads would wait for all loads in flight.)
+  auto step = [&](int t, const uint16_t* cur, uint16_t* nxt) {
+    wait_vm_lgkm0<8 * (STAGES - 2)>();
+    __builtin_amdgcn_s_barrier();
+    issue(nxt, t + STAGES - 1);
+    compute(cur);
+  };
+  // panel t sits in stage t % 3. Whole rounds of three in the loop, the
+  // rest after it: with steps under a condition inside the loop the compiler
+  // no longer tells the stages apart and waits for every load in flight
+  // before each LDS read
+  int t = 0;
+  for (; t + 3 <= nk; t += 3) {
+    step(t, st0, st2);
+    step(t + 1, st1, st0);
+    step(t + 2, st2, st1);
+  }
+  if (t < nk) step(t, st0, st2);
+  if (t + 1 < nk) step(t + 1, st1, st0);
+  wait_vm_lgkm0<0>();  // no load still writing LDS when the workgroup ends
+
+  const double alpha = p.alpha, beta = p.beta;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gmr = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+        const int gn = n0 + wn * 64 + j * 16 + (lane & 15);
+        if (gmr >= p.M || gn >= p.N) continue;
+        if (p.splits > 1) {
+          const int64_t b = (int64_t)b1 * p.nb0 + b0;
+          p.ws[(((int64_t)split * p.nbtot + b) * p.M + gmr) * p.N + gn] = (double)acc[i][j][r];
+        } else {
+          double* c = Cg + gmr * p.c_m + gn * p.c_n;
+          double v = alpha * (double)acc[i][j][r];
+          if (beta != 0.0) v += beta * *c;
+          *c = v;
+        }
+      }
+}
+
 // Products with a short contraction (K <= kSmallK) and a short output side
 // (<= kSmallSide): a matrix-core tile would be mostly padding and the cost
 // is one pass over the long operand. Each lane owns one index of the long
@@ -481,7 +629,14 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   p.ws = d.ws;
   PNK_REQUIRE(gy <= 65535 && gz * splits <= 65535, "gemm: batch too large");
   dim3 grid((unsigned)(p.tiles_m * p.tiles_n), (unsigned)gy, (unsigned)(gz * splits));
-  if (akc && bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, true><<<grid, 256, 0, s>>>(p);
+  // BF16 operands both k-contiguous with whole 64-deep panels (the packed
+  // copies): the pipelined kernel
+  constexpr bool pipe_cfg = std::is_same<Mma, MmaBF16>::value && std::is_same<TA, uint16_t>::value &&
+                            std::is_same<TB, uint16_t>::value && std::is_same<TC, double>::value && BM == 128 &&
+                            BN == 128 && BK == 64;
+  if (pipe_cfg && akc && bkc && !A2 && d.K % 64 == 0 && p.a_vec && p.b_vec) {
+    gemm_bf16_pipe<<<grid, 256, 0, s>>>(p);
+  } else if (akc && bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, true><<<grid, 256, 0, s>>>(p);
   else if (akc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, false><<<grid, 256, 0, s>>>(p);
   else if (bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, false, true><<<grid, 256, 0, s>>>(p);
   else gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, false, false><<<grid, 256, 0, s>>>(p);
@@ -554,14 +709,14 @@ namespace {
 struct PackArgs {
   const double* in;
   int64_t s_r, s_k, s_b0, s_b1;
-  int rows, K, nb0, ld, koff;
+  int rows, K, kz, nb0, ld, koff;  // columns koff .. koff + kz - 1 written, zeros past K
   void* out;
 };
 
 template <typename T>
 __global__ __launch_bounds__(256) void pack_operand(PackArgs p) {
   __shared__ double tile[32][33];
-  const int tiles_k = (p.K + 31) / 32;
+  const int tiles_k = (p.kz + 31) / 32;
   const int r0 = (blockIdx.x / tiles_k) * 32, k0 = (blockIdx.x % tiles_k) * 32;
   const int b = blockIdx.y;
   const int b0 = b % p.nb0, b1 = b / p.nb0;
@@ -581,15 +736,15 @@ __global__ __launch_bounds__(256) void pack_operand(PackArgs p) {
   T* out = (T*)p.out + (int64_t)b * p.rows * p.ld;
   for (int j = ty; j < 32; j += 8) {
     const int r = r0 + j, k = k0 + tx;
-    if (r < p.rows && k < p.K) out[(int64_t)r * p.ld + p.koff + k] = to_lds<double, T>(tile[j][tx]);
+    if (r < p.rows && k < p.kz) out[(int64_t)r * p.ld + p.koff + k] = to_lds<double, T>(tile[j][tx]);
   }
 }
 
 template <typename T>
-void pack(const double* in, int64_t s_r, int64_t s_k, int64_t s_b0, int64_t s_b1, int rows, int K, int nb0, int nb1,
-          int ld, int koff, void* out, hipStream_t s) {
-  PackArgs p{in, s_r, s_k, s_b0, s_b1, rows, K, nb0, ld, koff, out};
-  dim3 grid((unsigned)(ceil_div(rows, 32) * ceil_div(K, 32)), (unsigned)(nb0 * nb1));
+void pack(const double* in, int64_t s_r, int64_t s_k, int64_t s_b0, int64_t s_b1, int rows, int K, int kz, int nb0,
+          int nb1, int ld, int koff, void* out, hipStream_t s) {
+  PackArgs p{in, s_r, s_k, s_b0, s_b1, rows, K, kz, nb0, ld, koff, out};
+  dim3 grid((unsigned)(ceil_div(rows, 32) * ceil_div(kz, 32)), (unsigned)(nb0 * nb1));
   pack_operand<T><<<grid, 256, 0, s>>>(p);
   PNK_CHECK_LAUNCH();
 }
@@ -611,8 +766,11 @@ bool gemm_precast(const GemmDesc& d, const void* A, const void* B, const void* A
   if (dual && pa != pb) return false;
   const int64_t es = compute == Prec::BF16 ? 2 : 4;
   const int kt = dual ? 2 * d.K : d.K;
-  // rows of the copies start on 16-byte boundaries (vector loads)
-  const int ld = (int)((kt + 16 / es - 1) / (16 / es) * (16 / es));
+  // rows of the copies start on 16-byte boundaries (vector loads); BF16
+  // rows are zero-padded to a multiple of 64 elements (whole panels of the
+  // pipelined kernel)
+  const int lq = compute == Prec::BF16 ? 64 : 16 / (int)es;
+  const int ld = (int)((kt + lq - 1) / lq * lq);
   const int64_t need = es * nb * ((pa ? (int64_t)d.M * ld : 0) + (pb ? (int64_t)d.N * ld : 0)) + 256;
   if (need > d.cast_ws_bytes) return false;
   char* base = (char*)d.cast_ws;
@@ -622,13 +780,15 @@ bool gemm_precast(const GemmDesc& d, const void* A, const void* B, const void* A
   e.cast_ws = nullptr;
   const void *An = A, *Bn = B;
   Prec apn = ap, bpn = bp;
+  // (the last segment of a row also writes the zeros up to ld)
   auto run_pack = [&](const void* src, bool is_a, int koff, void* dst) {
     const double* in = (const double*)src;
     const int rows = is_a ? d.M : d.N;
     const int64_t sr = is_a ? d.a_m : d.b_n, sk = is_a ? d.a_k : d.b_k;
     const int64_t sb0 = is_a ? d.a_b0 : d.b_b0, sb1 = is_a ? d.a_b1 : d.b_b1;
-    if (es == 2) pack<uint16_t>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, ld, koff, dst, s);
-    else pack<float>(in, sr, sk, sb0, sb1, rows, d.K, d.nb0, d.nb1, ld, koff, dst, s);
+    const int kz = koff + d.K == kt ? ld - koff : d.K;
+    if (es == 2) pack<uint16_t>(in, sr, sk, sb0, sb1, rows, d.K, kz, d.nb0, d.nb1, ld, koff, dst, s);
+    else pack<float>(in, sr, sk, sb0, sb1, rows, d.K, kz, d.nb0, d.nb1, ld, koff, dst, s);
   };
   if (pa) {
     run_pack(A, true, 0, abuf);
@@ -644,13 +804,12 @@ bool gemm_precast(const GemmDesc& d, const void* A, const void* B, const void* A
     bpn = compute;
     e.b_n = ld; e.b_k = 1; e.b_b0 = (int64_t)d.N * ld; e.b_b1 = (int64_t)d.nb0 * d.N * ld;
   }
-  if (dual) {
-    // both products packed along k: one product of depth 2K
-    e.K = kt;
-    gemm_impl(e, An, Bn, nullptr, nullptr, apn, bpn, C, cp, compute, s);
-  } else {
-    gemm_impl(e, An, Bn, nullptr, nullptr, apn, bpn, C, cp, compute, s);
-  }
+  // both products of a dual call packed along k: one product of depth 2K;
+  // with both operands zero-padded to ld the contraction runs over the
+  // padding too
+  const bool bpad = !pb && bp == compute && d.b_k == 1 && d.b_kzero >= ld;
+  e.K = pa && (pb || bpad) ? ld : kt;
+  gemm_impl(e, An, Bn, nullptr, nullptr, apn, bpn, C, cp, compute, s);
   return true;
 }
 

@@ -34,6 +34,10 @@ struct GemmDesc {
   // it. Products whose packed operands do not fit are converted on load.
   void* cast_ws = nullptr;
   int64_t cast_ws_bytes = 0;
+  // B stored in the compute type along k, rows readable and zero from K up
+  // to this length (0: not known): a product whose A is packed may then run
+  // its contraction over whole panels
+  int64_t b_kzero = 0;
 };
 
 // Pointers carry their storage precision; `compute` selects the matrix-core
