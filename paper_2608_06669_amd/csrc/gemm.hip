@@ -436,26 +436,48 @@ __global__ __launch_bounds__(256) void gemm_bf16_pipe(KArgs p) {
   if (t + 1 < nk) step(t + 1, st1, st0);
   wait_vm_lgkm0<0>();  // no load still writing LDS when the workgroup ends
 
+  // epilogue (three uniform cases, each straight-line so the compiler can
+  // count its memory operations): split-K partial sums; C = alpha acc; C =
+  // alpha acc + beta C with the 16 reads of C of a row of tiles issued
+  // together before its writes
   const double alpha = p.alpha, beta = p.beta;
+  auto row_of = [&](int i, int r) { return m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r; };
+  auto col_of = [&](int j) { return n0 + wn * 64 + j * 16 + (lane & 15); };
+  if (p.splits > 1) {
+    double* __restrict__ W = p.ws + ((int64_t)split * p.nbtot + (int64_t)b1 * p.nb0 + b0) * p.M * p.N;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+      for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int gmr = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
-        const int gn = n0 + wn * 64 + j * 16 + (lane & 15);
-        if (gmr >= p.M || gn >= p.N) continue;
-        if (p.splits > 1) {
-          const int64_t b = (int64_t)b1 * p.nb0 + b0;
-          p.ws[(((int64_t)split * p.nbtot + b) * p.M + gmr) * p.N + gn] = (double)acc[i][j][r];
-        } else {
-          double* c = Cg + gmr * p.c_m + gn * p.c_n;
-          double v = alpha * (double)acc[i][j][r];
-          if (beta != 0.0) v += beta * *c;
-          *c = v;
-        }
-      }
+        for (int r = 0; r < 4; ++r)
+          if (row_of(i, r) < p.M && col_of(j) < p.N) W[(int64_t)row_of(i, r) * p.N + col_of(j)] = (double)acc[i][j][r];
+  } else if (beta == 0.0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row_of(i, r) < p.M && col_of(j) < p.N)
+            Cg[row_of(i, r) * p.c_m + col_of(j) * p.c_n] = alpha * (double)acc[i][j][r];
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      double cv[4][4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          cv[j][r] = Cg[min(row_of(i, r), p.M - 1) * p.c_m + min(col_of(j), p.N - 1) * p.c_n];
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (row_of(i, r) < p.M && col_of(j) < p.N)
+            Cg[row_of(i, r) * p.c_m + col_of(j) * p.c_n] = alpha * (double)acc[i][j][r] + beta * cv[j][r];
+    }
+  }
 }
 
 // Products with a short contraction (K <= kSmallK) and a short output side
