@@ -181,7 +181,7 @@ void for_each_buffer(const Sizes& z, const EngineOptions& opt, F f, G g) {
   }
   if (opt.lowp_bf16) {
     g(2 * p2 * pad_to(p2, 64)); g(2 * p2m * pad_to(p2m, 64));
-    g(2 * o * v * v * v); g(2 * n2); g(2 * ov * pad_to(ov, 64)); g(2 * ov * pad_to(ov, 64)); g(2 * n2);
+    g(2 * ov * pad_to(v * v, 64)); g(2 * n2); g(2 * ov * pad_to(ov, 64)); g(2 * ov * pad_to(ov, 64)); g(2 * n2);
   }
   g(cast_bytes(z, opt));
   // intermediates, value and tangent
@@ -241,7 +241,8 @@ Engine::Engine(int o, int v, int naux, const EngineOptions& opt)
   }
   if (opt.lowp_bf16) {
     S.lp16 = arena_.take<uint16_t>(z.p2 * ld16_); Am.lp16 = arena_.take<uint16_t>(z.p2m * ld16m_);
-    Wov.lp16 = arena_.take<uint16_t>(O * V * V * V);
+    ldw16_ = pad_to(V * V, 64);  // rows along k, zero-padded to whole panels
+    Wov.lp16 = arena_.take<uint16_t>(OV * ldw16_);
     // the ring integrals in BF16 are read along k (the matrix-core operand
     // layout), rows zero-padded to whole 64-deep panels: Iovov as is (it is
     // symmetric), Ix transposed
@@ -555,9 +556,10 @@ void Engine::prepare(const ProblemView& p, hipStream_t s) {
   const int64_t lsz[] = {(int64_t)o * v * vv, n2_, n2_, n2_, n2_};
   for (int k = 0; k < 5; ++k) {
     if (lows[k]->lp32) cast_f64_to_f32(lsz[k], lows[k]->v, (float*)lows[k]->lp32, s);
-    if (lows[k]->lp16 && lows[k] != &Iovov && lows[k] != &Ix)
+    if (lows[k]->lp16 && lows[k] != &Iovov && lows[k] != &Ix && lows[k] != &Wov)
       cast_f64_to_bf16(lsz[k], lows[k]->v, (uint16_t*)lows[k]->lp16, s);
   }
+  if (Wov.lp16) cast_f64_to_bf16_rows(ov, (int64_t)v * v, ldw16_, Wov.v, (uint16_t*)Wov.lp16, s);
   if (Iovov.lp16) {
     cast_f64_to_bf16_rows(ov, ov, ldov16_, Iovov.v, (uint16_t*)Iovov.lp16, s);
     // Ix^T[(k,c)][(l,d)] = Ix[(l,d)][(k,c)] = (kd|lc), staged in Tmp
@@ -665,7 +667,13 @@ void Engine::run(Mode m) {
   mm(batch0(gd(o, VV, o, 1, o, vv, 1, vv, 1, -1.0, 1.0), o, 0, O * vv, O * vv), Go, T2, X);
 
   // ---- T1 part of the dressed ladder ----
-  mm(gd(OO, OV, VV, vv, 1, 1, vv, ov, 1), T2, Wov, Z);             // Z[(i,j)][(k,b)]
+  {
+    // Z[(i,j)][(k,b)]; BF16 tangents read the padded BF16 copy of Wov
+    const bool kcw = mode_ == Mode::Tangent && jprec_ == Prec::BF16 && Wov.lp16;
+    GemmDesc gz = gd(OO, OV, VV, vv, 1, 1, kcw ? ldw16_ : vv, ov, 1);
+    if (kcw) gz.b_kzero = ldw16_;
+    mm(gz, T2, Wov, Z);
+  }
   mm(batch0(gd(OO, v, o, 1, oo, v, 1, ov, 1, -0.5, 1.0), o, O * oo, 0, v), Y, T1, Z);
   mm(batch0(gd(v, v, o, 1, v, v, 1, v, 1, -1.0, 1.0), OO, 0, ov, vv), T1, Z, X);
 

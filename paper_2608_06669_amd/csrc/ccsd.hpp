@@ -172,6 +172,7 @@ class Engine {
   int64_t p2_, p2m_, o2_;
   int64_t ld32_ = 0, ld32m_ = 0, ld16_ = 0, ld16m_ = 0;  // row lengths of the low-precision ladder copies
   int64_t ldov16_ = 0;  // row length of the BF16 ring integrals (read along k)
+  int64_t ldw16_ = 0;   // row length of the BF16 copy of Wov
   // amplitudes and outputs
   Ten T1, T2, R1, R2;
   // intermediates
