@@ -713,7 +713,11 @@ void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A
     // (BF16 with a long contraction takes them from 64 tiles on, split-K
     // filling the GPU: 1.2-2.3x faster than 64 x 64 on the T1 part of the
     // ladder and the antisymmetric ladder at o = 20, v = 180)
-    const bool wide = big >= 256 || (bf16 && d.K >= 8192 && big >= 64);
+    // (BF16 products the pipelined kernel takes, two packed operands with
+    // whole panels: from 32 tiles on, split-K filling the GPU)
+    const bool pipe_ok = bf16 && std::is_same<TA, uint16_t>::value && std::is_same<TB, uint16_t>::value &&
+                         d.a_k == 1 && d.b_k == 1 && d.K % 64 == 0 && !A2;
+    const bool wide = big >= 256 || (bf16 && d.K >= 8192 && big >= 64) || (pipe_ok && big >= 32);
     if (d.M >= 64 && d.N >= 96 && wide) launch_cfg<Mma, TA, TB, TC, 128, 128, BK128, 2>(d, A, B, A2, B2, C, s);
     else launch_cfg<Mma, TA, TB, TC, 64, 64, BK, 2>(d, A, B, A2, B2, C, s);
   }
@@ -780,7 +784,10 @@ void gemm_impl(const GemmDesc& d, const void* A, const void* B, const void* A2, 
 bool gemm_precast(const GemmDesc& d, const void* A, const void* B, const void* A2, const void* B2, Prec ap, Prec bp,
                   void* C, Prec cp, Prec compute, hipStream_t s) {
   if (!d.cast_ws || (compute != Prec::F32 && compute != Prec::BF16)) return false;
-  const bool pa = ap == Prec::F64, pb = bp == Prec::F64;
+  // an operand is rounded once only when more than one column (row) of
+  // tiles reads it; a thin product (the o x o outputs of the Fock terms)
+  // streams it once, and rounding it on load saves a pass over it
+  const bool pa = ap == Prec::F64 && d.N > 64, pb = bp == Prec::F64 && d.M > 64;
   if (!pa && !pb) return false;
   const int64_t nb = (int64_t)d.nb0 * d.nb1;
   if ((double)d.M * d.N * d.K * nb < 1e7) return false;  // small: convert on load
