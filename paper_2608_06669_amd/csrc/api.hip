@@ -715,8 +715,9 @@ int64_t diag_splitk_elems(int64_t nbatch, int M, int N) {
   return std::min<int64_t>(64 * nbatch * (int64_t)M * N, kDiagSplitElems);
 }
 int64_t diag_cast_bytes(int64_t nbatch, int M, int N, int K, cc_precision prec) {
-  // rows of the copies padded to 16 bytes
-  const int64_t es = prec == CC_BF16 ? 2 : 4, per = 16 / es;
+  // rows of the copies padded to 16 bytes (BF16: to 64 elements, whole
+  // panels of the pipelined kernel)
+  const int64_t es = prec == CC_BF16 ? 2 : 4, per = prec == CC_BF16 ? 64 : 16 / es;
   return es * nbatch * ((int64_t)M + N) * ((K + per - 1) / per * per) + 512;
 }
 }  // namespace pnk

@@ -75,22 +75,34 @@ def _load(name):
 U_IN = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}
 
 LAYOUTS = {
-    # name: (M, N, K, nbatch, transpose A, transpose B, precast)
-    "nn": (2100, 2100, 512, 1, False, False, False),
-    "tn": (2100, 2100, 512, 1, True, False, False),
-    "nt": (2100, 2100, 300, 1, False, True, False),
-    "nn_precast": (2100, 2100, 512, 1, False, False, True),
-    "tt_precast": (2100, 2050, 300, 1, True, True, True),
-    "batched": (1024, 1030, 300, 4, False, False, False),
-    "batched_precast_t": (1024, 1030, 300, 4, True, False, True),
+    # name: (M, N, K, nbatch, transpose A, transpose B, precast, beta)
+    "nn": (2100, 2100, 512, 1, False, False, False, 0.25),
+    "tn": (2100, 2100, 512, 1, True, False, False, 0.25),
+    "nt": (2100, 2100, 300, 1, False, True, False, 0.25),
+    "nn_precast": (2100, 2100, 512, 1, False, False, True, 0.25),
+    "tt_precast": (2100, 2050, 300, 1, True, True, True, 0.25),
+    "batched": (1024, 1030, 300, 4, False, False, False, 0.25),
+    "batched_precast_t": (1024, 1030, 300, 4, True, False, True, 0.25),
+    # few tiles and a long contraction: split-K (in BF16 through the
+    # pipelined kernel, the contraction zero-padded from 4100 to 4160)
+    "splitk_precast_nt": (768, 1030, 4100, 1, False, True, True, 0.25),
+    "splitk_precast_beta0": (768, 1030, 4100, 1, True, False, True, 0.0),
+    # beta = 0 with whole tiles and no split
+    "nn_precast_beta0": (2100, 2100, 512, 1, False, False, True, 0.0),
 }
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
 @pytest.mark.parametrize("layout", sorted(LAYOUTS))
 def test_gemm_128_tiles_low_precision_elementwise(lib, prec, layout):
-    M, N, K, nb, ta, tb, pre = LAYOUTS[layout]
-    assert -(-M // 128) * -(-N // 128) * nb >= 256  # the 128 x 128 tile path
+    """FP32 / BF16 products elementwise against float64 within the bound
+    derived from the unit roundoffs. With precast BF16 operands the products
+    run in the pipelined kernel (direct-to-LDS stages): ragged rows and
+    columns, batches, a contraction padded to whole 64-deep panels, split-K
+    partial sums, and the beta = 0 and beta != 0 epilogues."""
+    M, N, K, nb, ta, tb, pre, beta = LAYOUTS[layout]
+    if not layout.startswith("splitk"):
+        assert -(-M // 128) * -(-N // 128) * nb >= 256  # the 128 x 128 tile path
     g = torch.Generator(device="cpu").manual_seed(M + 7 * N + 13 * K + nb)
     A = torch.randn(nb, K, M, generator=g, dtype=torch.float64) if ta else \
         torch.randn(nb, M, K, generator=g, dtype=torch.float64)
@@ -99,13 +111,13 @@ def test_gemm_128_tiles_low_precision_elementwise(lib, prec, layout):
     Am = A.transpose(1, 2) if ta else A
     Bm = B.transpose(1, 2) if tb else B
     C0 = torch.randn(nb, M, N, generator=g, dtype=torch.float64)
-    ref = 0.5 * torch.bmm(Am.contiguous(), Bm.contiguous()) + 0.25 * C0
+    ref = 0.5 * torch.bmm(Am.contiguous(), Bm.contiguous()) + beta * C0
     absprod = torch.bmm(Am.abs().contiguous(), Bm.abs().contiguous())
     a_str = (1, M, M * K) if ta else (K, 1, M * K)
     b_str = (1, K, N * K) if tb else (N, 1, N * K)
     Cd = C0.cuda()
-    lib.diag_gemm_batched(A.cuda(), B.cuda(), Cd, a_str, b_str, (N, 1, M * N), M, N, K, nb, alpha=0.5, beta=0.25,
-                          prec=prec, precast=pre)
+    lib.diag_gemm_batched(A.cuda(), B.cuda(), Cd, a_str, b_str, (N, 1, M * N), M, N, K, nb, alpha=0.5, beta=beta,
+                          prec=prec, precast=pre, splitk=layout.startswith("splitk"))
     u = U_IN[prec]
     bound = 0.5 * (2 * u + u * u + K * 2.0 ** -24) * absprod + 1e-15 * ref.abs()
     err = (Cd.cpu() - ref).abs()
