@@ -231,15 +231,17 @@ def test_pnk_c4_fp64_root_is_an_oracle_root(c4_fp64_root):
     assert abs(e_or - info["e_corr"]) < 1e-9
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_pnk_c4_mixed_precision_root_and_energy(handle, lib, c4_fp64_root, prec):
+@pytest.mark.parametrize("prec,rtol_jv", [("fp32", 0.0), ("bf16", 0.0), ("bf16", 1e-4)])
+def test_pnk_c4_mixed_precision_root_and_energy(handle, lib, c4_fp64_root, prec, rtol_jv):
     """Mixed-precision PNK (J v in FP32 or BF16 with float accumulation;
     residual, energy and Arnoldi in FP64) on the same workload: an oracle
     root (max |R_oracle| < 1e-7) whose oracle energy equals the device's to
-    1e-9 Eh, and |E - E_FP64| <= 1e-6 Eh against the FP64 root above."""
+    1e-9 Eh, and |E - E_FP64| <= 1e-6 Eh against the FP64 root above. The
+    last case solves A_F^-1 J q inside the Krylov loop to 1e-4 only (the
+    bench line's setting: an order below the BF16 product's own error)."""
     p, f1, f2, ref = c4_fp64_root
     P = lib.DeviceProblem.from_problem(p)
-    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=200, jvp_prec=prec)
+    t1, t2, info = handle.solve_pnk(P, tol_inf=1e-8, max_newton=200, jvp_prec=prec, inner_rtol_jv=rtol_jv)
     assert info["status"] == "CC_OK", info
     res, e_or = _oracle_root_check(p, host(t1), host(t2), info)
     dE = abs(info["e_corr"] - ref["e_corr"])
