@@ -538,7 +538,7 @@ def bench_serving(args):
     sizes = [(r.nocc, r.nvir) for r in reqs]
     out = {"workload": f"serving stream, {len(reqs)} requests (C5 sample), PNK to ||r||_inf<1e-8, {args.slots} "
                        f"slots, stagnation stop after {args.stall_window} Newton steps without halving "
-                       f"||r||_inf; BF16 path with the Krylov-loop inner solves to 1e-6",
+                       f"||r||_inf; BF16 path with the Krylov-loop inner solves to {krylov_inner_rtol('bf16'):g}",
            "request_sizes": sizes, "closed_loop": closed, "poisson_rate_per_s": lam, "open_loop": opened,
            "max_abs_dE_bf16_vs_fp64_converged": de, "n_converged_in_both": len(both)}
     print(json.dumps(out), flush=True)
