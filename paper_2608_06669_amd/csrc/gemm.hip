@@ -480,6 +480,167 @@ __global__ __launch_bounds__(256) void gemm_bf16_pipe(KArgs p) {
   }
 }
 
+// FP64 product, A k-contiguous, B k-contiguous (B_KC) or n-contiguous, the
+// contraction a multiple of 16: 64 x 64 tiles, 16-deep panels loaded
+// straight into LDS (16 bytes = two doubles per lane) in a ring of three
+// stages, as in gemm_bf16_pipe. A k-contiguous operand is stored [row][16]
+// with the eight 16-byte chunks of a row at slot chunk ^ (row % 8); B
+// n-contiguous is stored [k][64] with its 32 chunks at slot chunk ^ (8 (k %
+// 4)): the 4 x 4 x 4 operand reads (4 rows x 4 k of A, 16 columns x 4 k of
+// B per instruction) then fall on distinct banks. A second product (A2,
+// B2) continues the same k loop into the same accumulators.
+template <bool B_KC>
+__global__ __launch_bounds__(256, 2) void gemm_f64_pipe(KArgs p) {
+  constexpr int BM = 64, BN = 64, BK = 16, STAGES = 3, AE = BM * BK, SE = AE + BN * BK;
+  __shared__ __attribute__((aligned(1024))) double st0[SE], st1[SE], st2[SE];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+
+  const int ntiles = p.tiles_m * p.tiles_n;
+  int bid = blockIdx.x;
+  {
+    const int q = ntiles >> 3, r = ntiles & 7, x = bid & 7;
+    bid = x * q + min(x, r) + (bid >> 3);
+  }
+  constexpr int kGroupM = 8;
+  const int gsize = kGroupM * p.tiles_n;
+  const int grp = bid / gsize;
+  const int first_m = grp * kGroupM;
+  const int gm = min(p.tiles_m - first_m, kGroupM);
+  const int rem = bid - grp * gsize;
+  const int m0 = (first_m + rem % gm) * BM;
+  const int n0 = (rem / gm) * BN;
+
+  const int split = blockIdx.z % p.splits;
+  const int zb = blockIdx.z / p.splits;
+  const int b0 = blockIdx.y % p.nb0;
+  const int b1 = blockIdx.y / p.nb0 + zb * (gridDim.y / p.nb0);
+  const int kbeg = split * p.kchunk;
+  const int nk1 = (min(p.K, kbeg + p.kchunk) - kbeg) / BK;  // >= 1
+  const bool dual = p.A2 != nullptr;
+  const int nk = dual ? 2 * nk1 : nk1;
+  const int64_t lda = p.a_m, ldb = B_KC ? p.b_n : p.b_k;
+  const int64_t aoff = b0 * p.a_b0 + b1 * p.a_b1 + kbeg;
+  const int64_t boff = b0 * p.b_b0 + b1 * p.b_b1 + (B_KC ? kbeg : (int64_t)kbeg * ldb);
+  double* __restrict__ Cg = (double*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
+
+  // this thread's chunks c = j 256 + tid, j = 0, 1, of A and of B (offsets
+  // within an operand; rows and columns past the matrix read its last ones,
+  // whose outputs are not written)
+  int64_t oa[2], ob[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const int c = j * 256 + tid;
+    {
+      const int r = c >> 3, g = (c & 7) ^ (r & 7);
+      oa[j] = (int64_t)min(m0 + r, p.M - 1) * lda + 2 * g;
+    }
+    if constexpr (B_KC) {
+      const int r = c >> 3, g = (c & 7) ^ (r & 7);
+      ob[j] = (int64_t)min(n0 + r, p.N - 1) * ldb + 2 * g;
+    } else {
+      const int k = c >> 5, g = (c & 31) ^ (8 * (k & 3));
+      ob[j] = (int64_t)k * ldb + min(n0 + 2 * g, p.N - 2);
+    }
+  }
+  const double* A1 = (const double*)p.A + aoff;
+  const double* B1 = (const double*)p.B + boff;
+  const double* A2 = dual ? (const double*)p.A2 + aoff : A1;
+  const double* B2 = dual ? (const double*)p.B2 + boff : B1;
+  // panel t into stage st (past the last panel: the last one again, never read)
+  auto issue = [&](double* st, int t) {
+    t = min(t, nk - 1);
+    const bool second = t >= nk1;
+    const int k0 = (second ? t - nk1 : t) * BK;
+    const double* Ab = (second ? A2 : A1) + k0;
+    const double* Bb = (second ? B2 : B1) + (B_KC ? (int64_t)k0 : (int64_t)k0 * ldb);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      __builtin_amdgcn_global_load_lds(Ab + oa[j], (__attribute__((address_space(3))) void*)(st + (j * 256 + wave * 64) * 2),
+                                       16, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      __builtin_amdgcn_global_load_lds(Bb + ob[j],
+                                       (__attribute__((address_space(3))) void*)(st + AE + (j * 256 + wave * 64) * 2),
+                                       16, 0, 0);
+  };
+  double acc[8][2];
+#pragma unroll
+  for (int a = 0; a < 8; ++a) acc[a][0] = acc[a][1] = 0.0;
+  auto compute = [&](const double* st) {
+#pragma unroll
+    for (int ks = 0; ks < BK; ks += 4) {
+      const int k = ks + (lane >> 4);
+      double af[8], bf[2];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) {
+        const int m = wm * 32 + a * 4 + (lane & 3);
+        af[a] = st[m * BK + 2 * ((k >> 1) ^ (m & 7)) + (k & 1)];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        const int n = wn * 32 + b * 16 + (lane & 15);
+        if constexpr (B_KC) bf[b] = st[AE + n * BK + 2 * ((k >> 1) ^ (n & 7)) + (k & 1)];
+        else bf[b] = st[AE + k * BN + 2 * ((n >> 1) ^ (8 * (k & 3))) + (n & 1)];
+      }
+#pragma unroll
+      for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_4x4x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+  };
+  issue(st0, 0);
+  issue(st1, 1);
+  // step t: panel t's 4 loads per thread landed (the next panel's 4 may be
+  // in flight) and this wave's earlier LDS reads done, then a plain barrier,
+  // the refill of the stage read at step t - 1, and panel t
+  auto step = [&](int t, const double* cur, double* nxt) {
+    wait_vm_lgkm0<4 * (STAGES - 2)>();
+    __builtin_amdgcn_s_barrier();
+    issue(nxt, t + STAGES - 1);
+    compute(cur);
+  };
+  int t = 0;
+  for (; t + 3 <= nk; t += 3) {
+    step(t, st0, st2);
+    step(t + 1, st1, st0);
+    step(t + 2, st2, st1);
+  }
+  if (t < nk) step(t, st0, st2);
+  if (t + 1 < nk) step(t + 1, st1, st0);
+  wait_vm_lgkm0<0>();
+
+  const double alpha = p.alpha, beta = p.beta;
+  auto row_of = [&](int a) { return m0 + wm * 32 + a * 4 + (lane >> 4); };
+  auto col_of = [&](int b) { return n0 + wn * 32 + b * 16 + (lane & 15); };
+  if (p.splits > 1) {
+    double* __restrict__ W = p.ws + ((int64_t)split * p.nbtot + (int64_t)b1 * p.nb0 + b0) * p.M * p.N;
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        if (row_of(a) < p.M && col_of(b) < p.N) W[(int64_t)row_of(a) * p.N + col_of(b)] = acc[a][b];
+  } else if (beta == 0.0) {
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        if (row_of(a) < p.M && col_of(b) < p.N) Cg[row_of(a) * p.c_m + col_of(b) * p.c_n] = alpha * acc[a][b];
+  } else {
+    double cv[8][2];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) cv[a][b] = Cg[min(row_of(a), p.M - 1) * p.c_m + min(col_of(b), p.N - 1) * p.c_n];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        if (row_of(a) < p.M && col_of(b) < p.N)
+          Cg[row_of(a) * p.c_m + col_of(b) * p.c_n] = alpha * acc[a][b] + beta * cv[a][b];
+  }
+}
+
 // Products with a short contraction (K <= kSmallK) and a short output side
 // (<= kSmallSide): a matrix-core tile would be mostly padding and the cost
 // is one pass over the long operand. Each lane owns one index of the long
@@ -656,8 +817,17 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   constexpr bool pipe_cfg = std::is_same<Mma, MmaBF16>::value && std::is_same<TA, uint16_t>::value &&
                             std::is_same<TB, uint16_t>::value && std::is_same<TC, double>::value && BM == 128 &&
                             BN == 128 && BK == 64;
+  // FP64, A k-contiguous, B k- or n-contiguous (an even number of columns),
+  // whole 16-deep panels, 16-byte rows: the pipelined FP64 kernel
+  constexpr bool f64_cfg = std::is_same<Mma, MmaF64>::value && std::is_same<TA, double>::value &&
+                           std::is_same<TB, double>::value && std::is_same<TC, double>::value && BM == 64 && BN == 64 &&
+                           BK == 16;
+  const bool bnc = d.b_n == 1 && d.b_k != 1;
   if (pipe_cfg && akc && bkc && !A2 && d.K % 64 == 0 && p.a_vec && p.b_vec) {
     gemm_bf16_pipe<<<grid, 256, 0, s>>>(p);
+  } else if (f64_cfg && akc && d.K % 16 == 0 && p.a_vec && p.b_vec && d.M >= 2 && (bkc || (bnc && d.N % 2 == 0))) {
+    if (bkc) gemm_f64_pipe<true><<<grid, 256, 0, s>>>(p);
+    else gemm_f64_pipe<false><<<grid, 256, 0, s>>>(p);
   } else if (akc && bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, true><<<grid, 256, 0, s>>>(p);
   else if (akc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, true, false><<<grid, 256, 0, s>>>(p);
   else if (bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, false, true><<<grid, 256, 0, s>>>(p);
