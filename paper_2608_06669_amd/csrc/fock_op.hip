@@ -741,22 +741,34 @@ struct OccSetArgs {
   const double* done;
 };
 
-// Position set u (0 <= u < nb^2) over the 8 x 8 blocks of the v x v grid
-// (nb = ceil(v / 8) per side): a diagonal block (T, T), or half h of an
-// off-diagonal block pair (Ta < Tb): rows 8 Ta + 4 h .. + 4 by columns 8
-// Tb .. + 8 together with its transpose. The blocks are taken in 2 x 2
-// groups (16 x 16 elements: two 128-byte lines of doubles per row), the
-// upper group triangle row by row, so that the sets of a group, which share
-// the lines they touch, run one after another on one XCD. A diagonal group
-// holds 4 sets: (2g, 2g), (2g, 2g + 1) halves 0 and 1, (2g + 1, 2g + 1);
-// an off-diagonal one 8: w = 4 dTa + 2 dTb + h; with nb odd the last
-// diagonal group holds 1 and the last column's groups 4 (dTb = 0).
-__device__ inline bool occ_set_decode(int u, int nb, bool* diag, int* a0, int* b0) {
+// With nb odd, the blocks of the last row and column are the second half
+// of a 2 x 2 group. When the v x v grid ends at most 4 elements into that
+// last block (edge), the set of an off-diagonal block pair (Ta, nb - 1) is
+// instead the 4 valid rows 8 (nb - 1) .. + 4 by the 8 columns of block Ta
+// together with its transpose (all 64 positions in range, one set in place
+// of two half-empty ones): at v = 180, 507 sets in place of 529, which two
+// rounds of one workgroup per compute unit cover.
+__host__ __device__ inline bool occ_set_edge(int v, int nb) { return (nb & 1) && v - 8 * (nb - 1) <= 4; }
+__host__ __device__ inline int occ_set_count(int v, int nb) { return nb * nb - (occ_set_edge(v, nb) ? nb - 1 : 0); }
+
+// Position set u (0 <= u < occ_set_count(v, nb)) over the 8 x 8 blocks of
+// the v x v grid (nb = ceil(v / 8) per side): a diagonal block (T, T), or
+// half h of an off-diagonal block pair (Ta < Tb): rows 8 Ta + 4 h .. + 4 by
+// columns 8 Tb .. + 8 together with its transpose (the edge sets above
+// aside). The blocks are taken in 2 x 2 groups (16 x 16 elements: two
+// 128-byte lines of doubles per row), the upper group triangle row by row,
+// so that the sets of a group, which share the lines they touch, run one
+// after another on one XCD. A diagonal group holds 4 sets: (2g, 2g), (2g,
+// 2g + 1) halves 0 and 1, (2g + 1, 2g + 1); an off-diagonal one 8: w = 4
+// dTa + 2 dTb + h; with nb odd the last diagonal group holds 1 and the last
+// column's groups 4 (dTb = 0; w = 2 dTa + h), or 2 edge sets (w = dTa).
+__device__ inline bool occ_set_decode(int u, int nb, bool edge, bool* diag, int* a0, int* b0) {
   const int ng = (nb + 1) / 2;
   const bool odd = nb & 1;
+  const int nhalf = edge ? 2 : 4;  // sets of a group in the last column (nb odd)
   for (int ga = 0; ga < ng; ++ga) {
     const int cd = odd && ga == ng - 1 ? 1 : 4, noff = ng - 1 - ga;
-    const int row = cd + 8 * noff - (odd && noff > 0 ? 4 : 0);
+    const int row = cd + 8 * noff - (odd && noff > 0 ? 8 - nhalf : 0);
     if (u >= row) {
       u -= row;
       continue;
@@ -771,8 +783,13 @@ __device__ inline bool occ_set_decode(int u, int nb, bool* diag, int* a0, int* b
     u -= cd;
     const int gb = ga + 1 + u / 8, w = u % 8;
     const bool half = odd && gb == ng - 1;
-    const int dTa = half ? w >> 1 : w >> 2, dTb = half ? 0 : (w >> 1) & 1, h = w & 1;
     *diag = false;
+    if (half && edge) {
+      *a0 = 8 * (nb - 1);
+      *b0 = 8 * (T + w);
+      return true;
+    }
+    const int dTa = half ? w >> 1 : w >> 2, dTb = half ? 0 : (w >> 1) & 1, h = w & 1;
     *a0 = 8 * (T + dTa) + 4 * h;
     *b0 = 8 * (2 * gb + dTb);
     return true;
@@ -893,7 +910,7 @@ __global__ __launch_bounds__(64 * NW) void fock_occ_set_kernel(OccSetArgs p) {
   bool diag = false;
   int a0 = 0, b0 = 0;
   if ((int)blockIdx.x < p.dwg && unit < p.units * p.bsplit &&
-      occ_set_decode(unit / p.bsplit, p.nb, &diag, &a0, &b0)) {
+      occ_set_decode(unit / p.bsplit, p.nb, occ_set_edge(v, p.nb), &diag, &a0, &b0)) {
     int a, b, lT;
     occ_set_lane(diag, l, a0, b0, &a, &b, &lT);
     const int part = unit % p.bsplit;
@@ -1185,7 +1202,7 @@ bool fock_op_plan(FockOp& op) {
       op.pnb = (int)ceil_div(op.v, 8);
       const int bg = (op.o + 3) / 4;
       op.pnblk = bg * (bg + 1) / 2;
-      const int64_t units = (int64_t)op.pnb * op.pnb;
+      const int64_t units = occ_set_count(op.v, op.pnb);
       // waves per workgroup: 16 where the staging fills a CU's LDS (taken
       // as the per-workgroup maximum), else 8 when there are more than 4
       // blocks (measured at o=10/v=90: 2.5 % faster than 4 waves with the
@@ -1334,7 +1351,7 @@ void fock_op_lanczos_occ_packed(const FockOp& op, const double* v, const double*
     c.v = op.v;
     c.npair = op.npair;
     c.nb = op.pnb;
-    c.units = op.pnb * op.pnb;
+    c.units = occ_set_count(op.v, op.pnb);
     c.bsplit = op.pbsplit;
     c.nblk = op.pnblk;
     c.dwg = op.pdwg;

@@ -201,7 +201,8 @@ def test_precond_solve_symmetric_fock_operator(handle, lib):
 
 
 @pytest.mark.parametrize("o,v,seed", [(5, 23, 47), (1, 9, 48), (10, 90, 49), (7, 40, 50), (12, 60, 51), (5, 64, 52),
-                                      (6, 96, 53), (4, 91, 54), (16, 40, 57), (24, 20, 58), (25, 30, 59)])
+                                      (6, 96, 53), (4, 91, 54), (16, 40, 57), (24, 20, 58), (25, 30, 59),
+                                      (6, 17, 60), (8, 36, 61), (10, 100, 62)])
 def test_precond_solve_pair_symmetric_packed_layout(handle, lib, o, v, seed):
     """cc_precond_solve_pairsym: the Lanczos vectors hold pairs i <= j only.
     The occupied part runs in the register-blocked form (64 positions per
@@ -209,7 +210,11 @@ def test_precond_solve_pair_symmetric_packed_layout(handle, lib, o, v, seed):
     blocks of the o x o output, ragged at o=5, 1, 10, 7 and 6) up to o=24,
     whose staging just fits a workgroup's LDS: 4 waves per workgroup at o <=
     8, 8 waves at o=10, 12 and 16, 16 at o=24, with a set's output blocks
-    split over two workgroups at o=16/v=40 and o=24/v=20. At o=25 it falls
+    split over two workgroups at o=16/v=40 and o=24/v=20. Where the grid
+    ends at most 4 elements into an odd-numbered last block (v=20, 17, 36
+    and 100), each set pairing a block with the last one holds that block's
+    columns by the 4 edge rows and the transpose (one set in place of two
+    half-empty ones; at v=17 the edge strip is ragged too). At o=25 it falls
     back to the tile form (tile edge 2).
     The virtual contraction of the fused step runs in panels of 32 at v=23,
     in one panel of 96 at v=90 and 91 and of 64 at v=60 (o=12: 32-wide
