@@ -311,23 +311,30 @@ __global__ __launch_bounds__(256) void splitk_reduce_wide(KArgs p) {
 }
 
 // BF16 product of two k-contiguous BF16 operands (rows 16-byte aligned, the
-// contraction a multiple of 64, zero-padded), 128 x 128 tiles, 64-deep
+// contraction a multiple of 64, zero-padded), BM x 128 tiles, 64-deep
 // panels in a ring of three LDS stages filled straight from global memory
 // (16 bytes per lane, no register staging), so two panels' loads are in
 // flight while the matrix cores work on the third. A stage holds A then B,
 // [row][64] each; the eight 16-byte chunks of a row are stored at slot
 // chunk ^ ((row / 2) % 8), which spreads the fragment reads of 16
 // consecutive rows over all 64 banks (each wave's load writes 1 KB
-// contiguously: its lanes fetch the chunks in slot order). Same tile order,
-// split-K and epilogue as gemm_kernel.
+// contiguously: its lanes fetch the chunks in slot order). Each wave forms
+// a 64 x 64 block of the tile: BM = 128 with 4 waves (96 KB of LDS), or BM
+// = 256 with 8 waves (144 KB: one workgroup per CU, two waves per SIMD; on
+// MI355X 1.1-1.4x faster than 128 x 128 on the 3600 x 3600 x 7232, 210 x
+// 16290 x 16290 and 400 x 3600 x 32400 products and 1.4x at 8192^3). Same
+// tile order, split-K and epilogue as gemm_kernel.
 template <int N>
 __device__ inline void wait_vm_lgkm0() {  // vmcnt(N), lgkmcnt(0)
   __builtin_amdgcn_s_waitcnt((N & 15) | (7 << 4) | ((N >> 4) << 14));
 }
 
-__global__ __launch_bounds__(256) void gemm_bf16_pipe(KArgs p) {
-  constexpr int BM = 128, BN = 128, BK = 64, STAGES = 3;
-  constexpr int SE = (BM + BN) * BK;  // elements per stage
+template <int BM, int NW>
+__global__ __launch_bounds__(64 * NW) void gemm_bf16_pipe(KArgs p) {
+  constexpr int BN = 128, BK = 64, STAGES = 3, NT = 64 * NW;
+  static_assert(BM == 64 * (NW / 2), "one 64 x 64 block per wave, two waves across the tile");
+  constexpr int SE = (BM + BN) * BK;                             // elements per stage
+  constexpr int CA = BM * BK / 8 / NT, CB = BN * BK / 8 / NT;  // 16-byte chunks per thread and stage
   __shared__ __attribute__((aligned(1024))) uint16_t st0[SE], st1[SE], st2[SE];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
@@ -357,28 +364,34 @@ __global__ __launch_bounds__(256) void gemm_bf16_pipe(KArgs p) {
   const uint16_t* __restrict__ Bg = (const uint16_t*)p.B + b0 * p.b_b0 + b1 * p.b_b1 + kbeg;
   double* __restrict__ Cg = (double*)p.C + b0 * p.c_b0 + b1 * p.c_b1;
 
-  // this thread's chunks c = j 256 + tid (row c / 8, slot c % 8), j = 0..3,
-  // of A and of B (rows past the matrix read its last row; those outputs are
-  // not written)
-  const uint16_t* ga[4];
-  const uint16_t* gb[4];
+  // this thread's chunks c = j NT + tid (row c / 8, slot c % 8) of A (j <
+  // CA) and of B (j < CB) (rows past the matrix read its last row; those
+  // outputs are not written)
+  const uint16_t* ga[CA];
+  const uint16_t* gb[CB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int c = j * 256 + tid, r = c >> 3, slot = c & 7, g = slot ^ ((r >> 1) & 7);
+  for (int j = 0; j < CA; ++j) {
+    const int c = j * NT + tid, r = c >> 3, slot = c & 7, g = slot ^ ((r >> 1) & 7);
     ga[j] = Ag + (int64_t)min(m0 + r, p.M - 1) * p.a_m + 8 * g;
+  }
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    const int c = j * NT + tid, r = c >> 3, slot = c & 7, g = slot ^ ((r >> 1) & 7);
     gb[j] = Bg + (int64_t)min(n0 + r, p.N - 1) * p.b_n + 8 * g;
   }
-  // panel t into stage st (past the last panel: the last one again, never read)
+  // panel t into stage st (past the last panel: the last one again, never
+  // read). (The global address goes in as void*: converted implicitly, the
+  // host pass drops the template's launch stub.)
   auto issue = [&](uint16_t* st, int t) {
     const int k0 = min(t, nk - 1) * BK;
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      __builtin_amdgcn_global_load_lds(ga[j] + k0, (__attribute__((address_space(3))) void*)(st + (j * 256 + wave * 64) * 8),
-                                       16, 0, 0);
+    for (int j = 0; j < CA; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(ga[j] + k0),
+                                       (__attribute__((address_space(3))) void*)(st + (j * NT + wave * 64) * 8), 16, 0, 0);
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      __builtin_amdgcn_global_load_lds(gb[j] + k0,
-                                       (__attribute__((address_space(3))) void*)(st + BM * BK + (j * 256 + wave * 64) * 8),
+    for (int j = 0; j < CB; ++j)
+      __builtin_amdgcn_global_load_lds((const void*)(gb[j] + k0),
+                                       (__attribute__((address_space(3))) void*)(st + BM * BK + (j * NT + wave * 64) * 8),
                                        16, 0, 0);
   };
   f4 acc[4][4];
@@ -410,14 +423,14 @@ __global__ __launch_bounds__(256) void gemm_bf16_pipe(KArgs p) {
   };
   issue(st0, 0);
   issue(st1, 1);
-  // step t: wait for panel t (8 loads per panel per thread; the next
-  // panel's 8 may still be in flight) and for this wave's earlier LDS
-  // reads, then a barrier (every wave's share of panel t has landed and
-  // every wave is done with the stage about to be refilled), refill that
-  // stage with panel t + 2, and compute panel t. (A plain barrier: the
-  // workgroup fence of __syncthreads would wait for all loads in flight.)
+  // step t: wait for panel t (CA + CB loads per panel per thread; the next
+  // panel's may still be in flight) and for this wave's earlier LDS reads,
+  // then a barrier (every wave's share of panel t has landed and every wave
+  // is done with the stage about to be refilled), refill that stage with
+  // panel t + 2, and compute panel t. (A plain barrier: the workgroup fence
+  // of __syncthreads would wait for all loads in flight.)
   auto step = [&](int t, const uint16_t* cur, uint16_t* nxt) {
-    wait_vm_lgkm0<8 * (STAGES - 2)>();
+    wait_vm_lgkm0<(CA + CB) * (STAGES - 2)>();
     __builtin_amdgcn_s_barrier();
     issue(nxt, t + STAGES - 1);
     compute(cur);
@@ -823,8 +836,48 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
                            std::is_same<TB, double>::value && std::is_same<TC, double>::value && BM == 64 && BN == 64 &&
                            BK == 16;
   const bool bnc = d.b_n == 1 && d.b_k != 1;
+  auto reduce = [&](const KArgs& q) {
+    if (q.splits <= 1) return;
+    const int64_t total = nb * d.M * d.N;
+    if (q.splits >= 32)
+      splitk_reduce_wide<TC><<<(unsigned)std::min<int64_t>(ceil_div(total, 16), 8192), 256, 0, s>>>(q);
+    else
+      splitk_reduce<TC><<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 4096), 256, 0, s>>>(q);
+    PNK_CHECK_LAUNCH();
+  };
+  if (pipe_cfg && akc && bkc && !A2 && d.K % 64 == 0 && p.a_vec && p.b_vec && d.M > 128) {
+    // more than 128 rows: 256 x 128 tiles with 8 waves, one workgroup per
+    // CU. Tiles that cannot fill the GPU take split-K in whole rounds of
+    // 256 workgroups where possible (at most 8 chunks of 8 or more panels):
+    // the ladder at o = 20, v = 180 (128 tiles) runs in 2 chunks, the T1
+    // part (58 tiles) in 4
+    KArgs q = p;
+    q.tiles_m = (int)ceil_div(d.M, 256);
+    const int64_t t2 = (int64_t)q.tiles_m * q.tiles_n * nb;
+    int sp = 1;
+    if (d.ws && t2 < 256) {
+      double best = (double)t2 / 256.0;
+      for (int64_t c = 2; c <= 8 && c <= d.K / (64 * 8) && c <= ws_fit; ++c) {
+        const int64_t items = t2 * c;
+        const double eff = (double)items / (double)(ceil_div(items, 256) * 256);
+        if (eff > best + 1e-9) {
+          best = eff;
+          sp = (int)c;
+        }
+      }
+    }
+    q.kchunk = sp > 1 ? (int)(ceil_div(ceil_div(d.K, sp), 64) * 64) : d.K;
+    if (sp > 1) sp = (int)ceil_div(d.K, q.kchunk);
+    q.splits = sp;
+    PNK_REQUIRE(gz * sp <= 65535, "gemm: batch too large");
+    dim3 g2((unsigned)(q.tiles_m * q.tiles_n), (unsigned)gy, (unsigned)(gz * sp));
+    gemm_bf16_pipe<256, 8><<<g2, 512, 0, s>>>(q);
+    PNK_CHECK_LAUNCH();
+    reduce(q);
+    return;
+  }
   if (pipe_cfg && akc && bkc && !A2 && d.K % 64 == 0 && p.a_vec && p.b_vec) {
-    gemm_bf16_pipe<<<grid, 256, 0, s>>>(p);
+    gemm_bf16_pipe<128, 4><<<grid, 256, 0, s>>>(p);
   } else if (f64_cfg && akc && d.K % 16 == 0 && p.a_vec && p.b_vec && d.M >= 2 && (bkc || (bnc && d.N % 2 == 0))) {
     if (bkc) gemm_f64_pipe<true><<<grid, 256, 0, s>>>(p);
     else gemm_f64_pipe<false><<<grid, 256, 0, s>>>(p);
@@ -833,14 +886,7 @@ void launch_cfg(const GemmDesc& d, const void* A, const void* B, const void* A2,
   else if (bkc) gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, false, true><<<grid, 256, 0, s>>>(p);
   else gemm_kernel<Mma, TA, TB, TC, BM, BN, BK, WGM, false, false><<<grid, 256, 0, s>>>(p);
   PNK_CHECK_LAUNCH();
-  if (splits > 1) {
-    const int64_t total = nb * d.M * d.N;
-    if (splits >= 32)
-      splitk_reduce_wide<TC><<<(unsigned)std::min<int64_t>(ceil_div(total, 16), 8192), 256, 0, s>>>(p);
-    else
-      splitk_reduce<TC><<<(unsigned)std::min<int64_t>(ceil_div(total, 256), 4096), 256, 0, s>>>(p);
-    PNK_CHECK_LAUNCH();
-  }
+  reduce(p);
 }
 
 
