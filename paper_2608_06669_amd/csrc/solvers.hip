@@ -1335,11 +1335,14 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
     double* es = he_ + (size_t)slot * n;
     copy(n, x, xs, s);
     jacobi_update(vo_, vv_, fo, fv, opt.level_shift, r_, xs, es, s);
-    // B row of the new error vector against every stored one (slot order)
+    // B row of the new error vector against every stored one (slot order).
+    // Slots are filled in order, so the m in use are 0 .. m - 1; the others
+    // hold uninitialised memory and are never read (a zero weight times a
+    // non-finite value there would still be NaN)
     const int m = (int)slots.size();
     const int mm = std::max(nd, 1);
-    multi_dot(n, nd, he_, n, es, dsc_, partials_, s);  // unused slots are ignored below
-    read_scalars(host_, dsc_, nd, s);
+    multi_dot(n, m, he_, n, es, dsc_, partials_, s);
+    read_scalars(host_, dsc_, m, s);
     for (int q : slots) {
       Bfull[(size_t)slot * mm + q] = host_[q];
       Bfull[(size_t)q * mm + slot] = host_[q];
@@ -1349,11 +1352,11 @@ void Solver::solve_fp_diis(double* x, const FpOptions& opt, SolveStats* st, hipS
       for (int a = 0; a < m; ++a)
         for (int b = 0; b < m; ++b) B[(size_t)a * m + b] = Bfull[(size_t)slots[a] * mm + slots[b]];
       if (pulay_solve(B, m, c)) {
-        std::vector<double> cs(nd, 0.0);
+        std::vector<double> cs(m, 0.0);
         for (int a = 0; a < m; ++a) cs[slots[a]] = c[a];
-        upload(dsc_ + 3 * kMaxBasis, cs.data(), nd, s);
+        upload(dsc_ + 3 * kMaxBasis, cs.data(), m, s);
         fill(n, 0.0, x, s);
-        combine(n, nd, hx_, n, dsc_ + 3 * kMaxBasis, 1.0, x, s);
+        combine(n, m, hx_, n, dsc_ + 3 * kMaxBasis, 1.0, x, s);
       } else {
         copy(n, xs, x, s);
       }
