@@ -953,41 +953,119 @@ struct PackArgs {
   int64_t s_r, s_k, s_b0, s_b1;
   int rows, K, kz, nb0, ld, koff;  // columns koff .. koff + kz - 1 written, zeros past K
   void* out;
+  int vst;  // rows of out 16-byte aligned at every multiple of 8 columns (16-byte stores)
 };
 
 template <typename T>
 __global__ __launch_bounds__(256) void pack_operand(PackArgs p) {
-  __shared__ double tile[32][33];
-  const int tiles_k = (p.kz + 31) / 32;
-  const int r0 = (blockIdx.x / tiles_k) * 32, k0 = (blockIdx.x % tiles_k) * 32;
+  // 32 rows x 64 k per workgroup: read coalesced along whichever index is
+  // contiguous in the input, then 8 lanes per row write 8 consecutive k
+  // each (one 16-byte store of BF16, two of FP32, where aligned)
+  __shared__ double tile[64][33];  // [k - k0][r - r0]
+  const int tiles_k = (p.kz + 63) / 64;
+  const int r0 = (blockIdx.x / tiles_k) * 32, k0 = (blockIdx.x % tiles_k) * 64;
   const int b = blockIdx.y;
   const int b0 = b % p.nb0, b1 = b / p.nb0;
   const double* in = p.in + b0 * p.s_b0 + b1 * p.s_b1;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
-  const bool along_r = p.s_r == 1 && p.s_k != 1;
-  for (int j = ty; j < 32; j += 8) {
-    // along_r: consecutive lanes walk r; otherwise they walk k
-    const int r = along_r ? r0 + tx : r0 + j;
-    const int k = along_r ? k0 + j : k0 + tx;
-    double x = 0.0;
-    if (r < p.rows && k < p.K) x = in[(int64_t)r * p.s_r + (int64_t)k * p.s_k];
-    if (along_r) tile[tx][j] = x;
-    else tile[j][tx] = x;
+  if (p.s_r == 1 && p.s_k != 1) {
+    // consecutive lanes walk r
+    for (int j = ty; j < 64; j += 8) {
+      const int r = r0 + tx, k = k0 + j;
+      tile[j][tx] = r < p.rows && k < p.K ? in[(int64_t)r + (int64_t)k * p.s_k] : 0.0;
+    }
+  } else {
+    // consecutive lanes walk k
+    for (int j = ty; j < 32; j += 8)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int r = r0 + j, k = k0 + 32 * h + tx;
+        tile[32 * h + tx][j] = r < p.rows && k < p.K ? in[(int64_t)r * p.s_r + (int64_t)k * p.s_k] : 0.0;
+      }
   }
   __syncthreads();
-  T* out = (T*)p.out + (int64_t)b * p.rows * p.ld;
-  for (int j = ty; j < 32; j += 8) {
-    const int r = r0 + j, k = k0 + tx;
-    if (r < p.rows && k < p.kz) out[(int64_t)r * p.ld + p.koff + k] = to_lds<double, T>(tile[j][tx]);
+  const int rr = threadIdx.x >> 3, kc = (threadIdx.x & 7) * 8;
+  const int r = r0 + rr;
+  if (r >= p.rows) return;
+  T y[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) y[e] = to_lds<double, T>(tile[kc + e][rr]);
+  T* dst = (T*)p.out + (int64_t)b * p.rows * p.ld + (int64_t)r * p.ld + p.koff + k0 + kc;
+  if (p.vst && k0 + kc + 8 <= p.kz) {
+    uint4* d4 = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+    for (int q = 0; q < (int)sizeof(y) / 16; ++q) {
+      uint4 w;
+      __builtin_memcpy(&w, reinterpret_cast<const char*>(y) + 16 * q, 16);
+      d4[q] = w;
+    }
+  } else {
+    for (int e = 0; e < 8 && k0 + kc + e < p.kz; ++e) dst[e] = y[e];
+  }
+}
+
+// The same rounding for an input already contiguous along k (s_k = 1),
+// with 16-byte aligned rows and segments: no transpose, so each lane reads
+// 16 / sizeof(T) consecutive doubles of a row and writes them as one
+// 16-byte store. Lanes walk the row's chunks, rows follow each other in the
+// grid-stride. (Measured on MI355X against a form with one 16-byte load and
+// one pair store per lane, fully coalesced: about 5 % faster on the 3600 x
+// 3600 operands of the ring products.)
+template <typename T>
+__global__ __launch_bounds__(256) void pack_operand_kc(PackArgs p) {
+  constexpr int VE = 16 / (int)sizeof(T);  // elements per 16-byte store
+  const int b = blockIdx.y;
+  const int b0 = b % p.nb0, b1 = b / p.nb0;
+  const double* __restrict__ in = p.in + b0 * p.s_b0 + b1 * p.s_b1;
+  T* __restrict__ out = (T*)p.out + (int64_t)b * p.rows * p.ld + p.koff;
+  const int cpr = (p.kz + VE - 1) / VE;  // chunks per row
+  const int64_t total = (int64_t)p.rows * cpr;
+  for (int64_t c = blockIdx.x * (int64_t)256 + threadIdx.x; c < total; c += (int64_t)gridDim.x * 256) {
+    const int r = (int)(c / cpr), k0 = (int)(c % cpr) * VE;
+    const double* src = in + (int64_t)r * p.s_r + k0;
+    double x[VE];
+    if (k0 + VE <= p.K) {
+#pragma unroll
+      for (int e = 0; e < VE; e += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(src + e);
+        x[e] = t.x;
+        x[e + 1] = t.y;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) x[e] = k0 + e < p.K ? src[e] : 0.0;
+    }
+    T y[VE];
+#pragma unroll
+    for (int e = 0; e < VE; ++e) y[e] = to_lds<double, T>(x[e]);
+    T* dst = out + (int64_t)r * p.ld + k0;
+    if (k0 + VE <= p.kz) {
+      uint4 w;
+      __builtin_memcpy(&w, y, 16);
+      *reinterpret_cast<uint4*>(dst) = w;
+    } else {
+      for (int e = 0; k0 + e < p.kz; ++e) dst[e] = y[e];
+    }
   }
 }
 
 template <typename T>
 void pack(const double* in, int64_t s_r, int64_t s_k, int64_t s_b0, int64_t s_b1, int rows, int K, int kz, int nb0,
           int nb1, int ld, int koff, void* out, hipStream_t s) {
-  PackArgs p{in, s_r, s_k, s_b0, s_b1, rows, K, kz, nb0, ld, koff, out};
-  dim3 grid((unsigned)(ceil_div(rows, 32) * ceil_div(kz, 32)), (unsigned)(nb0 * nb1));
-  pack_operand<T><<<grid, 256, 0, s>>>(p);
+  const int vst = ((uintptr_t)out & 15u) == 0 && ld % 8 == 0 && koff % 8 == 0;
+  PackArgs p{in, s_r, s_k, s_b0, s_b1, rows, K, kz, nb0, ld, koff, out, vst};
+  // k-contiguous input with 16-byte aligned chunks in and out
+  constexpr int VE = 16 / (int)sizeof(T);
+  const bool kc = s_k == 1 && rows > 0 && ((uintptr_t)in & 15u) == 0 && s_r % 2 == 0 && s_b0 % 2 == 0 &&
+                  s_b1 % 2 == 0 && ((uintptr_t)out & 15u) == 0 && ld % VE == 0 && koff % VE == 0;
+  if (kc) {
+    const int64_t total = (int64_t)rows * ceil_div(kz, VE);
+    dim3 grid((unsigned)std::min<int64_t>(ceil_div(total, 256), 4096), (unsigned)(nb0 * nb1));
+    pack_operand_kc<T><<<grid, 256, 0, s>>>(p);
+  } else {
+    dim3 grid((unsigned)(ceil_div(rows, 32) * ceil_div(kz, 64)), (unsigned)(nb0 * nb1));
+    pack_operand<T><<<grid, 256, 0, s>>>(p);
+  }
   PNK_CHECK_LAUNCH();
 }
 
