@@ -52,7 +52,7 @@ VIR_LZ_TRAFFIC_BYTES = 33288550
 # profiles/fock_occ_set_kernel_c2_c4_counters.md; None when a kernel has
 # changed since the counters were taken.
 RESIDUAL_TRAFFIC_BYTES = 37799035918
-OCC_PACKED_TRAFFIC_BYTES = 289373094
+OCC_PACKED_TRAFFIC_BYTES = 276513390
 
 
 def nominal_residual_flops(o, v, naux):
