@@ -89,7 +89,30 @@ LAYOUTS = {
     "splitk_precast_beta0": (768, 1030, 4100, 1, True, False, True, 0.0),
     # beta = 0 with whole tiles and no split
     "nn_precast_beta0": (2100, 2100, 512, 1, False, False, True, 0.0),
+    # 20 rows with a long contraction, split over many chunks (B along n,
+    # and B along k)
+    "splitk_thin_nn": (20, 180, 20000, 1, False, False, False, 0.25),
+    "splitk_thin_nt": (20, 20, 40000, 1, False, True, False, 0.0),
 }
+
+
+@pytest.mark.parametrize("M,N,K,tb", [(20, 180, 20000, False), (20, 20, 40000, True), (32, 256, 5000, False),
+                                      (1, 7, 4096, True)])
+def test_gemm_thin_long_contraction_fp64(lib, M, N, K, tb):
+    """FP64 products with at most 32 rows and 256 columns and a long
+    contraction (64 x 64 tiles with 32-deep panels, many contraction chunks
+    summed through the split-K scratch) against float64."""
+    g = torch.Generator(device="cpu").manual_seed(M + 3 * N + K)
+    A = torch.randn(M, K, generator=g, dtype=torch.float64)
+    B = torch.randn(N, K, generator=g, dtype=torch.float64) if tb else torch.randn(K, N, generator=g, dtype=torch.float64)
+    C0 = torch.randn(M, N, generator=g, dtype=torch.float64)
+    ref = 0.7 * (A @ (B.T if tb else B)) - 0.3 * C0
+    Cd = C0.cuda()
+    b_str = (1, K, N * K) if tb else (N, 1, N * K)
+    lib.diag_gemm_batched(A.cuda(), B.cuda(), Cd, (K, 1, M * K), b_str, (N, 1, M * N), M, N, K, 1, alpha=0.7,
+                          beta=-0.3, prec="fp64", splitk=True)
+    err = (Cd.cpu() - ref).abs().max().item()
+    assert err <= 1e-12 * max(1.0, K ** 0.5) * ref.abs().max().item()
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
@@ -99,7 +122,8 @@ def test_gemm_128_tiles_low_precision_elementwise(lib, prec, layout):
     derived from the unit roundoffs. With precast BF16 operands the products
     run in the pipelined kernel (direct-to-LDS stages): ragged rows and
     columns, batches, a contraction padded to whole 64-deep panels, split-K
-    partial sums, and the beta = 0 and beta != 0 epilogues."""
+    partial sums, and the beta = 0 and beta != 0 epilogues; the thin layouts
+    (20 rows, a long contraction) round the FP64 operands while staging."""
     M, N, K, nb, ta, tb, pre, beta = LAYOUTS[layout]
     if not layout.startswith("splitk"):
         assert -(-M // 128) * -(-N // 128) * nb >= 256  # the 128 x 128 tile path
