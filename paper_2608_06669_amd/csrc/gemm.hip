@@ -902,6 +902,35 @@ void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A
                   hipStream_t s) {
   const int64_t nb = (int64_t)d.nb0 * d.nb1;
   if constexpr (sizeof(typename Mma::L) == 8) {
+    // long contractions of more than 64 rows that the pipelined FP64 kernel
+    // takes (A k-contiguous with 16-byte rows, B k-contiguous or
+    // n-contiguous with an even column count): its 64 x 64 tiles before the
+    // 72/80-row rules below (thin products keep their 32-deep tiles); a
+    // contraction that is not a whole number of 16-deep panels runs its
+    // last K % 16 columns as a second product added into C (the ladders at
+    // o = 20, v = 180: K = 16290 and 16110)
+    const bool akc = d.a_k == 1 && d.a_m != 1, bkc = d.b_k == 1 && d.b_n != 1, bnc = d.b_n == 1 && d.b_k != 1;
+    const bool pipe_ok =
+        akc && d.M > 64 && d.K >= 1024 && (bkc || (bnc && d.N % 2 == 0)) &&
+        vec_ok<double>(A, d.a_m, d.a_k, d.a_b0, d.a_b1, true) &&
+        (!A2 || vec_ok<double>(A2, d.a_m, d.a_k, d.a_b0, d.a_b1, true)) &&
+        vec_ok<double>(B, d.b_n, d.b_k, d.b_b0, d.b_b1, bkc) && (!A2 || vec_ok<double>(B2, d.b_n, d.b_k, d.b_b0, d.b_b1, bkc));
+    if (pipe_ok) {
+      const int r = d.K % 16;
+      GemmDesc dm = d;
+      dm.K = d.K - r;
+      launch_cfg<Mma, TA, TB, TC, 64, 64, 16, 2>(dm, A, B, A2, B2, C, s);
+      if (r) {
+        GemmDesc dt = d;
+        dt.K = r;
+        dt.beta = 1.0;
+        const int64_t ka = (int64_t)(d.K - r) * d.a_k, kb = (int64_t)(d.K - r) * d.b_k;
+        launch_cfg<Mma, TA, TB, TC, 64, 64, 16, 2>(dt, (const double*)A + ka, (const double*)B + kb,
+                                                   A2 ? (const double*)A2 + ka : nullptr,
+                                                   A2 ? (const double*)B2 + kb : nullptr, C, s);
+      }
+      return;
+    }
     // row counts that 72- or 80-row tiles cover with at least 10 % less
     // padding than 64-row ones (at o = 20: the ladder's 210 pair rows, 216
     // against 256; the 400 pair rows of the T1 part of the ladder, 400
