@@ -36,7 +36,8 @@ BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "c2_haar"      # the FP64 solve line (--workload c2_haar)
 HEADLINE = "c4_mixed"     # the default line
-# The driver's window for the whole default run; the untimed FP64 reference
+# Time allowed for the whole default run (20 timed solves, 5 warm-up and the
+# host baseline); the untimed FP64 reference
 # solve is skipped when it would not fit.
 RUN_BUDGET_S = 540.0
 # HBM bytes per launch of the fused first kernel of the inner Lanczos step
