@@ -931,11 +931,12 @@ void launch_sized(const GemmDesc& d, const void* A, const void* B, const void* A
       }
       return;
     }
-    // row counts that 72- or 80-row tiles cover with at least 10 % less
-    // padding than 64-row ones (at o = 20: the ladder's 210 pair rows, 216
-    // against 256; the 400 pair rows of the T1 part of the ladder, 400
-    // against 448), with a long contraction: 72 x 128 or 80 x 128 with
-    // 8-deep panels (9 % and 16 % faster than 64 x 64 there)
+    // otherwise, row counts that 72- or 80-row tiles cover with at least 10 %
+    // less padding than 64-row ones (such as the ladder's 210 pair rows, 216
+    // against 256, and the 400 rows of its T1 part, 400 against 448, when
+    // their operands do not suit the pipelined kernel), with a long
+    // contraction: 72 x 128 or 80 x 128 with 8-deep panels (9 % and 16 %
+    // faster than the register-staged 64 x 64 tiles there)
     const int64_t r64 = ceil_div(d.M, 64) * 64, r72 = ceil_div(d.M, 72) * 72, r80 = ceil_div(d.M, 80) * 80;
     // (at least 128 such tiles: fewer go to 64 x 64 tiles and many chunks)
     const int64_t n128 = ceil_div(d.N, 128) * nb;
