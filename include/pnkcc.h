@@ -412,6 +412,16 @@ cc_status cc_diag_contraction_flops(cc_handle* h, const cc_problem* p, cc_precis
  * CC_NOT_CONVERGED if the iteration stalls. */
 cc_status cc_diag_hessenberg_eigenvalues(int m, const double* H, double* re, double* im);
 
+/* The position sets of the occupied A_F kernel on the packed pair layout
+ * (the o x o contractions of the A_F product, Appendix A.7, for each
+ * virtual pair (a, b)): every workgroup takes 64 positions closed under
+ * (a, b) -> (b, a). For nvir virtuals, writes for set u and lane l the
+ * position a[64 u + l], b[64 u + l] (entries >= nvir mark padding lanes)
+ * and lane_t[64 u + l], the lane of the same set holding (b, a); *nsets
+ * receives the set count. Host arrays of cap elements each; host code, no
+ * GPU. CC_ERR_ARG for null pointers, nvir < 1 or cap < 64 * nsets. */
+cc_status cc_diag_occ_sets(int nvir, int* a, int* b, int* lane_t, int64_t cap, int* nsets);
+
 /* C = alpha * A * B + beta * C with element strides (A[m*a_m + k*a_k],
  * B[k*b_k + n*b_n], C[m*c_m + n*c_n]), all float64 device arrays, computed
  * on the matrix cores in precision `prec` (FP32/BF16: float accumulation).

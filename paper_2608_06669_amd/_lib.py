@@ -99,6 +99,7 @@ SIGNATURES = {
     "cc_fp_spectral_radius": (I, [P, ctypes.POINTER(cc_problem), P, P, P, P, D, I, ctypes.POINTER(D), P, P,
                                   ctypes.POINTER(I), P]),
     "cc_diag_hessenberg_eigenvalues": (I, [I, P, P, P]),
+    "cc_diag_occ_sets": (I, [I, P, P, P, ctypes.c_int64, ctypes.POINTER(I)]),
     "cc_pnk_opts_default": (None, [ctypes.POINTER(cc_pnk_opts)]),
     "cc_fp_opts_default": (None, [ctypes.POINTER(cc_fp_opts)]),
     "cc_solve_pnk": (I, [P, ctypes.POINTER(cc_problem), ctypes.POINTER(cc_pnk_opts), P, P,

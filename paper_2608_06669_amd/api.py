@@ -318,6 +318,23 @@ def gemm_noalloc(A, B, C, a_strides, b_strides, c_strides, M, N, K, nbatch, alph
     return C
 
 
+def occ_sets(nvir):
+    """The occupied A_F kernel's position sets for nvir virtuals
+    (cc_diag_occ_sets; host code, no GPU): arrays a, b, lane_t of shape
+    (sets, 64)."""
+    nb = (nvir + 7) // 8
+    cap = 64 * nb * nb
+    a = np.zeros(cap, dtype=np.int32)
+    b = np.zeros(cap, dtype=np.int32)
+    lt = np.zeros(cap, dtype=np.int32)
+    n = ctypes.c_int(0)
+    st = _lib().cc_diag_occ_sets(nvir, a.ctypes.data, b.ctypes.data, lt.ctypes.data, cap, ctypes.byref(n))
+    if st != L.CC_OK:
+        raise CCError(st, "cc_diag_occ_sets failed")
+    k = 64 * n.value
+    return a[:k].reshape(-1, 64), b[:k].reshape(-1, 64), lt[:k].reshape(-1, 64)
+
+
 def hessenberg_eigenvalues(H) -> np.ndarray:
     """Eigenvalues of a real upper Hessenberg matrix by the library's host
     QR iteration (cc_diag_hessenberg_eigenvalues; no GPU needed)."""

@@ -11,6 +11,7 @@
 #include "../../include/pnkcc.h"
 #include "api_internal.hpp"
 #include "eig.hpp"
+#include "fock_op.hpp"
 #include "gauge.hpp"
 #include "gemm.hpp"
 #include "tensor_ops.hpp"
@@ -687,6 +688,14 @@ cc_status cc_diag_contraction_flops(cc_handle* h, const cc_problem* p, cc_precis
 cc_status cc_diag_hessenberg_eigenvalues(int m, const double* H, double* re, double* im) {
   if (m < 1 || !H || !re || !im) return CC_ERR_ARG;
   return hessenberg_eigenvalues(H, m, re, im) ? CC_OK : CC_NOT_CONVERGED;
+}
+
+cc_status cc_diag_occ_sets(int nvir, int* a, int* b, int* lane_t, int64_t cap, int* nsets) {
+  if (nvir < 1 || !a || !b || !lane_t || !nsets || cap < 0) return CC_ERR_ARG;
+  const int n = fock_op_set_positions(nvir, a, b, lane_t, cap);
+  if (n < 0) return CC_ERR_ARG;
+  *nsets = n;
+  return CC_OK;
 }
 
 cc_status cc_diag_gemm(int M, int N, int K, const double* A, int64_t a_m, int64_t a_k, const double* B,

@@ -762,7 +762,7 @@ __host__ __device__ inline int occ_set_count(int v, int nb) { return nb * nb - (
 // 2g + 1) halves 0 and 1, (2g + 1, 2g + 1); an off-diagonal one 8: w = 4
 // dTa + 2 dTb + h; with nb odd the last diagonal group holds 1 and the last
 // column's groups 4 (dTb = 0; w = 2 dTa + h), or 2 edge sets (w = dTa).
-__device__ inline bool occ_set_decode(int u, int nb, bool edge, bool* diag, int* a0, int* b0) {
+__host__ __device__ inline bool occ_set_decode(int u, int nb, bool edge, bool* diag, int* a0, int* b0) {
   const int ng = (nb + 1) / 2;
   const bool odd = nb & 1;
   const int nhalf = edge ? 2 : 4;  // sets of a group in the last column (nb odd)
@@ -798,7 +798,7 @@ __device__ inline bool occ_set_decode(int u, int nb, bool edge, bool* diag, int*
 }
 
 // Lane l's position (a, b) in the set, and the lane lT holding (b, a).
-__device__ inline void occ_set_lane(bool diag, int l, int a0, int b0, int* a, int* b, int* lT) {
+__host__ __device__ inline void occ_set_lane(bool diag, int l, int a0, int b0, int* a, int* b, int* lT) {
   if (diag) {
     const int r = l >> 3, c = l & 7;
     *a = a0 + r;
@@ -1127,6 +1127,20 @@ size_t occ_set_lds_limit() {
 // Occupied kernel: the widest chunk (64 .. 16 elements, 8 only when 16 does
 // not fit) whose LDS stays within 64 KB (two workgroups per CU) and that
 // still gives 512 workgroups.
+int fock_op_set_positions(int v, int* a, int* b, int* lt, int64_t cap) {
+  if (v < 1 || !a || !b || !lt) return -1;
+  const int nb = (v + 7) / 8, n = occ_set_count(v, nb);
+  if ((int64_t)n * 64 > cap) return -1;
+  const bool edge = occ_set_edge(v, nb);
+  for (int u = 0; u < n; ++u) {
+    bool diag = false;
+    int a0 = 0, b0 = 0;
+    if (!occ_set_decode(u, nb, edge, &diag, &a0, &b0)) return -1;
+    for (int l = 0; l < 64; ++l) occ_set_lane(diag, l, a0, b0, &a[u * 64 + l], &b[u * 64 + l], &lt[u * 64 + l]);
+  }
+  return n;
+}
+
 bool fock_op_plan(FockOp& op) {
   if (op.o < 1 || op.v < 1 || op.o > kFockOpMaxOcc) return false;
   const int cand[3] = {32, 48, 64};

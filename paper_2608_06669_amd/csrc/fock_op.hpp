@@ -47,6 +47,12 @@ struct FockOp {
 // large) and the caller must use the general path.
 bool fock_op_plan(FockOp& op);
 
+// Host copy of the occupied kernel's position sets for v virtuals: for set
+// u and lane l, a[64 u + l], b[64 u + l] is the lane's (a, b) (past v: a
+// padding lane) and lt[64 u + l] the lane holding (b, a). Returns the set
+// count, or -1 when v < 1 or cap (elements per array) is too small.
+int fock_op_set_positions(int v, int* a, int* b, int* lt, int64_t cap);
+
 // y = A_F x (y must not alias x)
 void fock_op_apply(const FockOp& op, const double* x1, const double* x2, double* y1, double* y2, hipStream_t s);
 

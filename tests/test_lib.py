@@ -90,3 +90,28 @@ def test_host_hessenberg_eigenvalues_match_numpy():
         for lam in ref:
             assert np.min(np.abs(got - lam)) < 1e-9 * scale * H.shape[0], (H.shape, lam)
         assert abs(np.max(np.abs(got)) - np.max(np.abs(ref))) < 1e-9 * scale * H.shape[0]
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_occupied_kernel_position_sets_cover_every_pair_once():
+    """The occupied A_F kernel's position sets (cc_diag_occ_sets, host
+    code): every (a, b) with a, b < v lies in exactly one lane of one set,
+    each lane's partner lane holds (b, a), and the set count is nb^2 (nb =
+    ceil(v / 8) blocks per side) less one per block paired with a last
+    block that the grid leaves at most 4 elements into (nb odd): 507 sets
+    at v = 180, 144 at v = 90."""
+    import numpy as np
+
+    import paper_2608_06669_amd as pk
+    for v in list(range(1, 41)) + [57, 90, 91, 96, 100, 144, 172, 180, 181, 185]:
+        a, b, lt = pk.occ_sets(v)
+        nb = -(-v // 8)
+        edge = nb % 2 == 1 and v - 8 * (nb - 1) <= 4
+        assert a.shape[0] == nb * nb - (nb - 1 if edge else 0), v
+        rows = np.arange(a.shape[0])[:, None]
+        assert np.array_equal(a[rows, lt], b) and np.array_equal(b[rows, lt], a), v
+        valid = (a < v) & (b < v)
+        cover = np.zeros((v, v), dtype=np.int64)
+        np.add.at(cover, (a[valid], b[valid]), 1)
+        assert (cover == 1).all(), v
+    assert pk.occ_sets(180)[0].shape[0] == 507 and pk.occ_sets(90)[0].shape[0] == 144
